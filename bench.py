@@ -1,0 +1,248 @@
+"""Benchmark of the vectorized Sparrow step on one MI355X.
+
+Workload (default): 4096 envs, each with its own 366 x 366 synthetic map,
+32 LiDAR rays over 270 degrees with range 100, full per-env randomisation,
+auto-reset; actions from the BF16 Q-network 36-256-256-7 with per-env
+epsilon linearly spaced in [0.01, 0.3] (VEM).
+
+A "step" is one vectorized step of all N envs: actor + simulator step.
+  fused : K-step rollouts of the persistent kernel (actor fused, maps in LDS),
+          replayed from a cached HIP graph; the headline value
+  plain : per step, uniform random actions + the plain step kernel
+  plain+actor : per step, the separate actor kernel + the plain step kernel
+Prints one JSON line (rank 0, N=1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_HBM_GBS = 8000.0
+MI355X_CUS, MI355X_CLOCK_GHZ = 256, 2.4
+MI355X_LDS_GBS = MI355X_CUS * 128 * MI355X_CLOCK_GHZ  # 128 B/clk/CU
+MI355X_VALU_GOPS = MI355X_CUS * 64 * MI355X_CLOCK_GHZ  # wave64 lane-ops per second (non-packed)
+MI355X_BF16_TFLOPS = 2500.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2048)
+    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--workload", default="m")
+    ap.add_argument("--rollout", type=int, default=64, help="steps per fused rollout launch")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=512)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, maps, w, b, eps, seconds):
+    """The oracle (FP32 step + FP64 Q-network + VEM) on the host cores, on a
+    bounded sample of envs, one Python thread per core over env shards (the
+    C calls release the GIL)."""
+    import oracle
+    n_sample = 256
+    cores = min(os.cpu_count() or 1, 16)
+    sub = dict(cfg, n_envs=n_sample)
+    from paper_2305_04180_amd import inputs
+    smaps = inputs.Maps(grids=maps.grids[:n_sample], env_to_map=np.arange(n_sample, dtype=np.int32))
+    o = oracle.Oracle(sub, smaps)
+    obs, _ = o.reset()
+    dims = cfg["qnet"]
+    D = o.obs_dim
+    eps_s = np.ascontiguousarray(eps[:n_sample])
+    shards = np.array_split(np.arange(n_sample), cores)
+    acts = np.zeros(n_sample, np.int32)
+    rew = np.zeros(n_sample, np.float32)
+    done = np.zeros(n_sample, np.uint8)
+    nobs = np.zeros_like(obs)
+
+    def actor_and_step(sh):
+        e0, e1 = int(sh[0]), int(sh[-1]) + 1
+        q = oracle.qnet_f64(dims, w, b, obs[e0:e1])
+        # VEM for the shard's envs (same counters as the full batch)
+        full_q = np.zeros((n_sample, 7))
+        full_q[e0:e1] = q
+        a, _ = o.vem(full_q, eps_s)
+        acts[e0:e1] = a[e0:e1]
+        o.step_range(e0, e1, acts, nobs, rew, done)
+
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        th = [threading.Thread(target=actor_and_step, args=(sh,)) for sh in shards if len(sh)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        o.advance()
+        obs[:] = nobs
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * steps / dt, "unit": "env-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n_sample} of the {cfg['n_envs']} envs (same maps/physics), {steps} steps, "
+                      f"FP64 Q-network + VEM + FP32 step, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU; envs are independent, so N GPUs would "
+              "each run their own shard with no per-step exchange (see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2305_04180_amd import inputs, sparrow
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    cfg = inputs.workload(args.workload)
+    N = cfg["n_envs"]
+    log(f"[bench] generating {N} maps ({cfg['sides']})")
+    t0 = time.time()
+    maps = inputs.make_maps(cfg)
+    log(f"[bench] maps ready in {time.time() - t0:.1f}s")
+    dims = cfg["qnet"]
+    w, b, _ = inputs.qnet_weights(dims)
+    eps = sparrow.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
+
+    env = sparrow.Env(cfg, maps)
+    env.set_qnet(dims, w, b, eps)
+    env.reset()
+    tune = {}
+    if not args.no_tune:
+        tune = env.autotune(steps=8)
+        log(f"[bench] autotune: {json.dumps(tune)[:400]}")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    # ---------------- fused rollout ----------------
+    K = args.rollout
+    n_roll = max(1, math.ceil(args.steps / K))
+    n_warm = max(1, math.ceil(args.warmup / K))
+    acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
+    rew = torch.zeros(K, N, dtype=torch.float32, device="cuda")
+    done = torch.zeros(K, N, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(N, env.obs_dim, dtype=torch.float32, device="cuda")
+    log(f"[bench] fused warmup {n_warm} x {K} steps")
+    for _ in range(n_warm):
+        env.rollout(K, True, acts, rew, done, obs)
+    torch.cuda.synchronize()
+    log("[bench] fused timed")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n_roll)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(n_roll):
+        ev[i][0].record(stream)
+        env.rollout(K, True, acts, rew, done, obs)
+        ev[i][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    fused_ms = t_start.elapsed_time(t_end)
+    launch_ms = np.array([a.elapsed_time(b2) for a, b2 in ev])
+    steps_fused = n_roll * K
+    fused_rate = N * steps_fused / (fused_ms / 1e3)
+    assert env.status() == 0
+    hits = env.debug_hits().to(torch.int32)
+    M = int(cfg["range"] / cfg["ds"])
+    samples_last = float(torch.where(hits < 0, torch.full_like(hits, M), hits).add(1).sum().item())
+    log(f"[bench] fused: {fused_rate / 1e6:.1f} M env-steps/s ({fused_ms / steps_fused * 1e3:.2f} us/step)")
+
+    # ---------------- plain step ----------------
+    P = args.plain_steps
+    a_buf = torch.zeros(N, dtype=torch.int32, device="cuda")
+    for _ in range(32):
+        env.random_actions(a_buf)
+        env.step(a_buf)
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(P):
+        env.random_actions(a_buf)
+        env.step(a_buf)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = s0.elapsed_time(s1)
+    plain_rate = N * P / (plain_ms / 1e3)
+    log(f"[bench] plain: {plain_rate / 1e6:.1f} M env-steps/s")
+    # plain step with the separate actor kernel
+    q0 = torch.cuda.Event(enable_timing=True)
+    q1 = torch.cuda.Event(enable_timing=True)
+    q0.record(stream)
+    for _ in range(P):
+        env.act(env.obs, a_buf)
+        env.step(a_buf)
+    q1.record(stream)
+    torch.cuda.synchronize()
+    pa_rate = N * P / (q0.elapsed_time(q1) / 1e3)
+    log(f"[bench] plain+actor: {pa_rate / 1e6:.1f} M env-steps/s")
+
+    # ---------------- roofline of the fused kernel ----------------
+    # Algorithmic LDS traffic: one 4-byte word per marched ray sample; the
+    # sample count per env-step is taken from the last step's hit indices.
+    samples_per_env_step = samples_last / N
+    lds_bytes_per_launch = samples_per_env_step * 4.0 * N * K
+    avg_launch_s = float(launch_ms.mean()) / 1e3
+    lds_gbs = lds_bytes_per_launch / avg_launch_s / 1e9
+    roofline = {"bound": "lds", "achieved": round(lds_gbs, 1), "peak": MI355X_LDS_GBS,
+                "unit": "GB/s", "frac": round(lds_gbs / MI355X_LDS_GBS, 4), "traffic": None,
+                "kernel": "k_rollout (fused actor)", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                "samples_per_env_step": round(samples_per_env_step, 2)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(cfg, maps, w, b, eps, args.cpu_seconds)
+
+    out = {
+        "metric": "env-steps/s at N=4096, 366^2 maps, 32 rays; fused BF16 vs plain; % HBM/LDS peak",
+        "value": round(fused_rate, 1),
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": steps_fused,
+        "warmup": n_warm * K,
+        "ms_per_step": round(fused_ms / steps_fused, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 sim + bf16 mfma actor",
+        "data": "synthetic",
+        "config": {"workload": "4096 envs, own 366x366 map each, 32 rays/270 deg/range 100, "
+                               "full DR, Q-MLP 36-256-256-7 bf16, eps linspace(0.01,0.3)",
+                   "n_envs": N, "rollout_k": K, "parallelism": "single GPU"},
+        "plain_env_steps_per_s": round(plain_rate, 1),
+        "plain_actor_env_steps_per_s": round(pa_rate, 1),
+        "fused_over_plain": round(fused_rate / plain_rate, 3),
+        "wall_s_timed": round(wall, 4),
+        "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

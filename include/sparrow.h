@@ -1,0 +1,198 @@
+/*
+ * sparrow.h -- C-ABI of the MI355X (gfx950) vectorized Sparrow step library.
+ *
+ * The library advances N independent copies of a 2D mobile-robot simulator
+ * at once, as the Sparrow simulator of arXiv 2305.04180 does (Sec. 3.2):
+ *   - per-env control delay and domain-randomised physics (Sec. 3.2.4),
+ *   - simplified differential-drive kinematics, Eq. (5) and Eq. (6), applied
+ *     row-wise over the batch as in Eq. (7) and Eq. (8),
+ *   - LiDAR ray casting against each env's own occupancy grid, sensor noise,
+ *     collision detection (Sec. 3.2 functionalities),
+ *   - terminal rewards and done flags (Sec. 4.3.1), AutoReset (Sec. 3.2.5),
+ *   - a gymnasium-style reset()/step() on device buffers with built-in
+ *     normalisation and no host round trip (Sec. 3.2.1, Alg. 1 step 4),
+ *   - an optional fused actor: a Q-network (Sec. 4.3.2) in BF16 on MFMA with
+ *     FP32 accumulation, followed by vectorized epsilon-greedy exploration
+ *     (VEM, Sec. 3.1.1), feeding K-step rollouts (Alg. 1 steps 2-4).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: SPARROW_OK (0) or a negative SPARROW_E* code; the message
+ *     of the last failure on the calling thread is in sparrow_last_error().
+ *   - "dev" pointers are HIP device pointers; "host" pointers are host memory.
+ *     The caller owns every buffer it passes; the library never frees them
+ *     and keeps no reference after the call returns (except sparrow_set_qnet,
+ *     which copies).
+ *   - Every GPU entry point is asynchronous on the stream given at create;
+ *     results are valid after that stream is synchronised. No entry point
+ *     synchronises except sparrow_status, sparrow_get_state, sparrow_set_state
+ *     and sparrow_autotune.
+ *   - A handle belongs to one stream and is not thread-safe; distinct handles
+ *     are independent. Calls on one handle must not overlap.
+ *   - Layouts: obs is FP32 row-major [N][n_rays + 4]; reward FP32 [N];
+ *     done uint8 0/1 [N]; flags uint8 [N]; actions int32 [N] in [0, 7).
+ *     Rollout outputs are step-major [K][N].
+ *
+ * Observation row (Sec. 4.3.1 state, normalised, relative to the robot):
+ *   [0, n_rays)   range_j / range (after noise, clipped to [0, range])
+ *   n_rays        linear velocity / v_max of the env
+ *   n_rays + 1    angular velocity / omega_max
+ *   n_rays + 2    distance to target / (sqrt(2) * max(W, H))
+ *   n_rays + 3    bearing of the target in the robot frame / pi, in (-1, 1]
+ */
+#ifndef SPARROW_H
+#define SPARROW_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPARROW_OK 0
+#define SPARROW_EINVAL (-1)       /* bad argument, shape or configuration          */
+#define SPARROW_ENOMEM (-2)       /* device or host allocation failed              */
+#define SPARROW_EHIP (-3)         /* HIP runtime failure (message has the detail)  */
+#define SPARROW_ERESET (-4)       /* AutoReset found no free start/target cell     */
+#define SPARROW_EUNSUPPORTED (-5) /* not gfx950, or LDS/variant capacity exceeded  */
+
+#define SPARROW_N_ACTIONS 7
+#define SPARROW_MAX_SIDE 512
+#define SPARROW_MAX_RAYS 128
+
+/* flags bits (sparrow_step / sparrow_rollout) */
+#define SPARROW_FLAG_TERMINATED 1u /* collision or arrival                        */
+#define SPARROW_FLAG_TRUNCATED 2u  /* episode reached timeout_steps               */
+#define SPARROW_FLAG_COLLISION 4u
+#define SPARROW_FLAG_ARRIVAL 8u
+
+typedef struct sparrow_env sparrow_env; /* opaque; library-owned */
+
+/* Configuration, copied at create. Units: cells, seconds, radians.
+ * Domain randomisation (Sec. 3.2.4): at every episode start each env draws
+ * dt ~ U[dt_lo, dt_hi] (control interval), K ~ U[K_lo, K_hi] (inertia blend of
+ * Eq. (5)), mu ~ U[mu_lo, mu_hi] (friction gain on the target velocity),
+ * v_max ~ U[vmax_lo, vmax_hi] (cells/s), sigma ~ U[sigma_lo, sigma_hi] (LiDAR
+ * noise, cells), delay ~ U{delay_lo..delay_hi} (steps, <= 2), and its start
+ * pose. omega_max is fixed. Every random draw is Philox4x32-10 keyed by seed
+ * and counted by (env, global step, purpose, index). */
+typedef struct {
+  int32_t n_envs;        /* N >= 1                                        */
+  int32_t n_rays;        /* 1..128, spread over fov_rad, endpoints included */
+  int32_t n_actions;     /* must be 7                                     */
+  float fov_rad;         /* field of view, centred on the heading         */
+  float range_cells;     /* LiDAR range R > 0                             */
+  float march_step;      /* sample spacing along a ray, > 0               */
+  float robot_radius;    /* collision disk radius, (0, 8]                 */
+  float arrive_radius;   /* arrival when the distance to target <= this   */
+  int32_t timeout_steps; /* truncation after this many steps, >= 1        */
+  float dt_lo, dt_hi, K_lo, K_hi, mu_lo, mu_hi, vmax_lo, vmax_hi, omega_max,
+      sigma_lo, sigma_hi;
+  int32_t delay_lo, delay_hi;
+  uint64_t seed;
+} sparrow_config;
+
+/* Maps (host pointers, copied and bit-packed at create). cells holds n_maps
+ * uint8 grids [height][width] row-major (0 = free, else occupied) at byte
+ * offsets[m]; x indexes columns, y rows. env_to_map[n_envs] lets envs share a
+ * map. 1 <= width, height <= 512. */
+typedef struct {
+  int32_t n_maps;
+  const uint8_t *cells;
+  const int64_t *offsets;
+  const int32_t *width;
+  const int32_t *height;
+  const int32_t *env_to_map;
+} sparrow_maps;
+
+/* Create a handle on the current HIP device; all work goes to hip_stream
+ * (a hipStream_t; NULL = the null stream). Packs the maps into LDS-ready
+ * words on the device. No env is initialised until sparrow_reset.
+ * Errors: EINVAL, ENOMEM, EHIP, EUNSUPPORTED (device is not gfx950). */
+int sparrow_create(const sparrow_config *cfg, const sparrow_maps *maps, void *hip_stream,
+                   sparrow_env **out);
+
+/* Reset every env (Alg. 1 initial s = envs.reset()): draws physics, start and
+ * target, writes obs (dev [N][n_rays+4]). Advances the global step by one.
+ * A map with no free start/target makes the error sticky (see status). */
+int sparrow_reset(sparrow_env *env, float *obs);
+
+/* One vectorized step (Alg. 1 step 4: s', r, done = envs.step(a_hat)).
+ * actions: dev [N] (values outside [0, 7) act as "stop"). Writes obs, reward,
+ * done, and optionally flags (dev [N]) and final_obs (dev [N][n_rays+4], the
+ * observation at the terminal pose of envs that are done; rows of other envs
+ * are left untouched). Envs that are done are reset inside the step and obs
+ * holds their first observation of the next episode (AutoReset, Sec. 3.2.5).
+ * Advances the global step by one. */
+int sparrow_step(sparrow_env *env, const int32_t *actions, float *obs, float *reward,
+                 uint8_t *done, uint8_t *flags, float *final_obs);
+
+/* Uniform random actions for the current global step (dev [N]); the same
+ * draws a rollout with use_qnet = 0 makes. Does not advance the step. */
+int sparrow_random_actions(sparrow_env *env, int32_t *actions);
+
+/* Install the actor: Q-network dims[4] = {obs_dim, h1, h2, 7} (host), with
+ * obs_dim = n_rays + 4, h1 and h2 multiples of 32 up to 512, h1*h2 <= 65536.
+ * w_bf16: dev, bf16 bit patterns, [W1 (h1 x obs_dim) | W2 (h2 x h1) |
+ * W3 (7 x h2)], each row-major [out][in] (Sec. 4.3.2 fully connected layers
+ * with ReLU). b_f32: dev [h1 + h2 + 7]. eps: dev [N] per-env exploration
+ * probability of VEM (Sec. 3.1.1). All three are copied. */
+int sparrow_set_qnet(sparrow_env *env, const int32_t *dims, const uint16_t *w_bf16,
+                     const float *b_f32, const float *eps);
+
+/* Q-network forward on given observations (dev obs [n][obs_dim] -> dev q
+ * [n][7] FP32, dev greedy [n] int32 = lowest argmax). Same MFMA code as the
+ * fused actor: the observation is rounded to bf16 (RNE), layers accumulate in
+ * FP32, hidden activations are stored as bf16. Either output may be NULL. */
+int sparrow_qnet_forward(sparrow_env *env, const float *obs, int32_t n, float *q,
+                         int32_t *greedy);
+
+/* The actor as a separate kernel: Q-network on obs (dev [N][obs_dim]), then
+ * VEM with the current global step. Writes actions (dev [N]). Does not
+ * advance the step. */
+int sparrow_act(sparrow_env *env, const float *obs, int32_t *actions);
+
+/* K-step rollout in one persistent kernel (maps stay in LDS for all K steps),
+ * launched through a cached HIP graph. Per step: actor (use_qnet = 1: the
+ * installed Q-network + VEM on the current observation; 0: uniform random
+ * actions), then the step with AutoReset. Outputs, step-major: actions
+ * (dev [K][N], nullable), reward (dev [K][N]), done (dev [K][N]), and obs
+ * (dev [N][n_rays+4]) after the last step. Needs a prior reset (the current
+ * observation is kept on the device). Advances the global step by K. */
+int sparrow_rollout(sparrow_env *env, int32_t K, int32_t use_qnet, int32_t *actions,
+                    float *reward, uint8_t *done, float *obs);
+
+/* Per-ray sample index of the first hit (-1: none) of the most recent
+ * observation of each env (dev [N][n_rays] int16). For parity checks. */
+int sparrow_debug_hits(sparrow_env *env, int16_t *hit_k);
+
+/* Synchronising state access (host buffers). Float fields [N][13]:
+ * x y phi vl va tx ty dprev dt K mu vmax sigma; int fields [N][4]:
+ * t delay q0 q1. set_state also invalidates the cached observation. */
+int sparrow_get_state(sparrow_env *env, float *f_host, int32_t *i_host);
+int sparrow_set_state(sparrow_env *env, const float *f_host, const int32_t *i_host);
+
+uint32_t sparrow_global_step(const sparrow_env *env);
+void sparrow_set_global_step(sparrow_env *env, uint32_t g);
+
+/* Kernel variants. kernel: 0 = step/reset, 1 = rollout. envs_per_group in
+ * {1, 2, 4, 8}; lanes_per_env in {16, 32, 64} (fewer lanes than rays: each
+ * lane marches several rays; more lanes than rays: lanes of one ray split its
+ * samples). Every variant computes identical results. */
+int sparrow_set_variant(sparrow_env *env, int32_t kernel, int32_t envs_per_group,
+                        int32_t lanes_per_env);
+int sparrow_get_variant(const sparrow_env *env, int32_t kernel, int32_t *envs_per_group,
+                        int32_t *lanes_per_env);
+/* Time every admissible variant of both kernels on a scratch copy of the
+ * state (the env itself is not advanced), keep the fastest. Synchronises.
+ * report (host, nullable) receives a JSON summary of the timings. */
+int sparrow_autotune(sparrow_env *env, int32_t steps, char *report, int32_t report_len);
+
+/* Synchronise the stream and return the sticky asynchronous error (ERESET)
+ * or a HIP error, else SPARROW_OK. */
+int sparrow_status(sparrow_env *env);
+void sparrow_destroy(sparrow_env *env);
+const char *sparrow_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

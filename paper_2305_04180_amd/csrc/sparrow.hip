@@ -1,0 +1,1028 @@
+// sparrow.hip -- kernels and C-ABI host side of the gfx950 Sparrow step library.
+//
+// Kernels:
+//   k_pack      uint8 grids -> bit-packed rows with an occupied ring (LDS-ready)
+//   k_step<L>   one vectorized step (or reset) per launch; each workgroup
+//               stages its group's maps into LDS, then every env runs on L lanes
+//   k_rollout<L, QNET>
+//               persistent K-step rollout: maps staged once per group and kept
+//               in LDS for all K steps; actor = uniform draws or the BF16 MFMA
+//               Q-network + VEM (Alg. 1 steps 2-4 fused)
+//   k_actions   uniform random actions (one thread per env)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sparrow.h"
+#include "sparrow_device.h"
+#include "sparrow_qnet.h"
+
+using namespace sp;
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+
+// One 32-bit word per thread: map m's packed row r (= y + 1), word c covers
+// x + 1 in [32c, 32c + 32). Bits outside [0, W) x [0, H) are set.
+__global__ void k_pack(const uint8_t* __restrict__ cells, const int64_t* __restrict__ offs,
+                       const MapMeta* __restrict__ meta, uint32_t* __restrict__ words,
+                       int32_t n_maps) {
+  const int m = blockIdx.y + blockIdx.z * 65535;
+  if (m >= n_maps) return;
+  const MapMeta mm = meta[m];
+  const int total = mm.wpr * (mm.H + 2);
+  const int padded = (total + 3) & ~3;
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < padded; w += gridDim.x * blockDim.x) {
+    uint32_t v = 0xFFFFFFFFu;
+    if (w < total) {
+      const int row = w / mm.wpr, cw = w % mm.wpr;
+      const int y = row - 1;
+      v = 0u;
+      for (int b = 0; b < 32; ++b) {
+        const int x = cw * 32 + b - 1;
+        const bool occ = x < 0 || x >= mm.W || y < 0 || y >= mm.H ||
+                         cells[offs[m] + (int64_t)y * mm.W + x] != 0;
+        v |= (occ ? 1u : 0u) << b;
+      }
+    }
+    words[mm.off + w] = v;
+  }
+}
+
+__global__ void k_actions(int32_t n, uint32_t g, uint32_t key0, uint32_t key1,
+                          int32_t* __restrict__ actions) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const U4 w = philox((uint32_t)i, g, kActionUniform, 0u, key0, key1);
+  actions[i] = scale_u32(w.x, kNumActions);
+}
+
+// Copy the group's maps into LDS (16-byte words; offsets are multiples of 4).
+__device__ __forceinline__ void stage_maps(const Params& p, int grp, uint32_t* lds) {
+  for (int s = 0; s < p.epw; ++s) {
+    const int4 sl = p.slots[grp * p.epw + s];
+    if (sl.x < 0) break;
+    const uint4* src = reinterpret_cast<const uint4*>(p.words + p.meta[sl.y].off);
+    uint4* dst = reinterpret_cast<uint4*>(lds + sl.z);
+    const int n4 = sl.w >> 2;
+    for (int w = threadIdx.x; w < n4; w += blockDim.x) dst[w] = src[w];
+  }
+}
+
+__device__ __forceinline__ Slot make_slot(const Params& p, const int4& sl, const uint32_t* lds) {
+  const MapMeta mm = p.meta[sl.y];
+  Slot m;
+  m.w1 = lds + sl.z + mm.wpr;
+  m.W = mm.W;
+  m.H = mm.H;
+  m.wpr = mm.wpr;
+  return m;
+}
+
+// mode 0: step, mode 1: reset
+template <int L>
+__global__ void __launch_bounds__(512) k_step(Params p, int mode) {
+  extern __shared__ uint32_t lds[];
+  const int grp = blockIdx.x;
+  stage_maps(p, grp, lds);
+  __syncthreads();
+  const int slot = threadIdx.x / L;
+  if (slot >= p.epw) return;
+  const int4 sl = p.slots[grp * p.epw + slot];
+  if (sl.x < 0) return;
+  const int i = sl.x;
+  const Lanes<L> ln(threadIdx.x);
+  const Slot m = make_slot(p, sl, lds);
+  const float inv_dn = p.inv_dn[sl.y];
+  const int D = p.obs_dim;
+  Env e = load_env(p.s, i);
+  float* orow = p.obs + (size_t)i * D;
+  float* crow = p.cur_obs + (size_t)i * D;
+  int16_t* hk = p.hit_k + (size_t)i * p.n_rays;
+  if (mode == 1) {
+    const bool ok = reset_env<L>(p, ln, m, e, i, p.g);
+    if (!ok && ln.q == 0) p.err[0] = SPARROW_ERESET;
+    observe<L>(p, ln, m, e, i, p.g, kNoiseReset, inv_dn, orow, crow, hk, nullptr);
+    if (ln.q == 0) store_env(p.s, i, e);
+    return;
+  }
+  const StepOut o = step_env<L>(p, ln, m, e, p.actions[i]);
+  if (o.done) {
+    if (p.final_obs)
+      observe<L>(p, ln, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D, nullptr,
+                 nullptr, nullptr);
+    const bool ok = reset_env<L>(p, ln, m, e, i, p.g);
+    if (!ok && ln.q == 0) p.err[0] = SPARROW_ERESET;
+    observe<L>(p, ln, m, e, i, p.g, kNoiseReset, inv_dn, orow, crow, hk, nullptr);
+  } else {
+    observe<L>(p, ln, m, e, i, p.g, kNoise, inv_dn, orow, crow, hk, nullptr);
+  }
+  if (ln.q == 0) {
+    store_env(p.s, i, e);
+    p.reward[i] = o.reward;
+    p.done[i] = o.done;
+    if (p.flags) p.flags[i] = o.flags;
+  }
+}
+
+// Persistent rollout: workgroup b serves groups b, b + gridDim.x, ...
+// QC = NoQ: uniform random actions; QC = QNetCfg<...>: fused BF16 actor.
+template <int L, class QC>
+__global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
+  extern __shared__ uint32_t lds[];
+  constexpr bool kQ = QC::kOn;
+  const int slot = threadIdx.x / L;
+  const Lanes<L> ln(threadIdx.x);
+  const int N = p.n_envs, D = p.obs_dim;
+  typename QC::Weights qw;
+  qw.load(qp, threadIdx.x);
+  if constexpr (kQ) {
+    // clear the actor's LDS so padded rows and columns hold finite values
+    uint32_t* a = lds + qp.lds_base_words;
+    const int nw = (int)(qnet_region_a_bytes(qp) + qnet_region_b_bytes(qp)) / 4;
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) a[k] = 0u;
+  }
+  for (int grp = blockIdx.x; grp < p.n_groups; grp += gridDim.x) {
+    __syncthreads();
+    stage_maps(p, grp, lds);
+    int4 sl = make_int4(-1, 0, 0, 0);
+    if (slot < p.epw) sl = p.slots[grp * p.epw + slot];
+    const bool live = sl.x >= 0;
+    const int i = live ? sl.x : 0;
+    Env e{};
+    Slot m{};
+    float inv_dn = 0.0f, eps = 0.0f;
+    if (live) {
+      e = load_env(p.s, i);
+      m = make_slot(p, sl, lds);
+      inv_dn = p.inv_dn[sl.y];
+      if constexpr (kQ) eps = p.eps[i];
+    }
+    uint16_t* act_in = nullptr;
+    if constexpr (kQ) {
+      if (slot < kQRows) act_in = qnet_input_row(qp, lds, slot);
+      // the current observation feeds the first actor step
+      if (live)
+        for (int k = ln.q; k < D; k += L) act_in[k] = bf16_rne(p.cur_obs[(size_t)i * D + k]);
+    }
+    __syncthreads();
+    for (int t = 0; t < p.K_steps; ++t) {
+      const uint32_t g = p.g + (uint32_t)t;
+      int a_hat = 0;
+      if constexpr (kQ) {
+        qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);  // barriers inside
+        if (live) a_hat = qnet_vem_action(qp, lds, slot, i, g, eps, p.key0, p.key1);
+      } else {
+        const U4 w = philox((uint32_t)i, g, kActionUniform, 0u, p.key0, p.key1);
+        a_hat = scale_u32(w.x, kNumActions);
+      }
+      if (live) {
+        const StepOut o = step_env<L>(p, ln, m, e, a_hat);
+        const bool last = t == p.K_steps - 1;
+        float* orow = last ? p.obs + (size_t)i * D : nullptr;
+        float* crow = (last || !kQ) ? p.cur_obs + (size_t)i * D : nullptr;
+        int16_t* hk = last ? p.hit_k + (size_t)i * p.n_rays : nullptr;
+        if (o.done) {
+          const bool ok = reset_env<L>(p, ln, m, e, i, g);
+          if (!ok && ln.q == 0) p.err[0] = SPARROW_ERESET;
+          observe<L>(p, ln, m, e, i, g, kNoiseReset, inv_dn, orow, crow, hk, act_in);
+        } else {
+          observe<L>(p, ln, m, e, i, g, kNoise, inv_dn, orow, crow, hk, act_in);
+        }
+        if (ln.q == 0) {
+          const size_t o_idx = (size_t)t * N + i;
+          p.r_reward[o_idx] = o.reward;
+          p.r_done[o_idx] = o.done;
+          if (p.r_actions) p.r_actions[o_idx] = a_hat;
+        }
+      }
+      if constexpr (kQ) __syncthreads();
+    }
+    if (live && ln.q == 0) store_env(p.s, i, e);
+  }
+}
+
+// Q-network forward for the parity entry point and the separate actor kernel:
+// each workgroup takes 16 rows of obs at a time.
+template <class QC>
+__global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restrict__ obs,
+                                              int32_t n, float* __restrict__ q,
+                                              int32_t* __restrict__ greedy,
+                                              const float* __restrict__ eps, uint32_t g,
+                                              uint32_t key0, uint32_t key1,
+                                              int32_t* __restrict__ actions) {
+  extern __shared__ uint32_t lds[];
+  typename QC::Weights qw;
+  qw.load(qp, threadIdx.x);
+  {
+    const int nw = (int)(qnet_region_a_bytes(qp) + qnet_region_b_bytes(qp)) / 4;
+    for (int k = threadIdx.x; k < nw; k += blockDim.x) lds[k] = 0u;
+  }
+  for (int r0 = blockIdx.x * kQRows; r0 < n; r0 += gridDim.x * kQRows) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kQRows * qp.d0p; idx += blockDim.x) {
+      const int r = idx / qp.d0p, k = idx % qp.d0p;
+      uint16_t* row = qnet_input_row(qp, lds, r);
+      row[k] = (r0 + r < n && k < qp.d0) ? bf16_rne(obs[(size_t)(r0 + r) * qp.d0 + k]) : 0;
+    }
+    qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);
+    if (threadIdx.x < kQRows && r0 + (int)threadIdx.x < n) {
+      const int r = threadIdx.x, row = r0 + r;
+      float qa[kNumActions];
+      const int gi = qnet_q_values(qp, lds, r, qa);
+      if (q)
+        for (int a = 0; a < kNumActions; ++a) q[(size_t)row * kNumActions + a] = qa[a];
+      if (greedy) greedy[row] = gi;
+      if (actions) actions[row] = vem_select(gi, row, g, eps[row], key0, key1);
+    }
+  }
+}
+
+using Q64 = QNetCfg<64, 256, 256>;
+using Q96 = QNetCfg<96, 256, 256>;
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail(SPARROW_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+struct Groups {
+  int epw = 0, G = 0, max_words = 0;
+  int4* d_slots = nullptr;
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
+  hipKernelNodeParams kp{};
+};
+
+}  // namespace
+
+struct sparrow_env {
+  sparrow_config cfg{};
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;
+  int device = 0;
+  int lds_max = 65536;
+  int n_cu = 256;
+  int n_maps = 0;
+  uint32_t g = 0;
+  bool was_reset = false;
+  // device buffers
+  State s{};
+  void* state_block = nullptr;
+  uint32_t* words = nullptr;
+  MapMeta* meta = nullptr;
+  float* inv_dn = nullptr;
+  int32_t* env_map = nullptr;
+  float2* rays = nullptr;
+  float* cur_obs = nullptr;
+  int16_t* hit_k = nullptr;
+  int32_t* err = nullptr;
+  // host copies
+  std::vector<MapMeta> h_meta;
+  std::vector<int32_t> h_env_map;
+  // variants: 0 = step/reset, 1 = rollout
+  int var_epw[2] = {4, 8};
+  int var_L[2] = {32, 64};
+  std::map<std::pair<int, int>, Groups> groups;  // (epw, budget words)
+  std::map<std::tuple<int, int, int, int, void*, void*, void*, void*>, GraphEntry> graphs;
+  // actor
+  bool has_qnet = false;
+  QParams qp{};
+  void* q_block = nullptr;
+  float* eps = nullptr;
+};
+
+namespace {
+
+int obs_dim(const sparrow_env* e) { return e->cfg.n_rays + 4; }
+
+int words_of(const MapMeta& m) { return ((m.wpr * (m.H + 2)) + 3) & ~3; }
+
+// Envs sorted by packed size (largest first), packed greedily into groups of at
+// most epw envs whose maps fit the LDS budget together.
+int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out) {
+  auto key = std::make_pair(epw, budget_words);
+  auto it = e->groups.find(key);
+  if (it != e->groups.end()) {
+    *out = &it->second;
+    return SPARROW_OK;
+  }
+  const int N = e->cfg.n_envs;
+  std::vector<int> order(N);
+  for (int i = 0; i < N; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return words_of(e->h_meta[e->h_env_map[a]]) > words_of(e->h_meta[e->h_env_map[b]]);
+  });
+  std::vector<int4> slots;
+  Groups gr;
+  gr.epw = epw;
+  int cur = 0, used = 0;
+  std::vector<int4> cur_slots;
+  auto flush = [&]() {
+    if (cur == 0) return;
+    for (int s = cur; s < epw; ++s) cur_slots.push_back(make_int4(-1, 0, 0, 0));
+    slots.insert(slots.end(), cur_slots.begin(), cur_slots.end());
+    gr.max_words = std::max(gr.max_words, used);
+    gr.G += 1;
+    cur_slots.clear();
+    cur = 0;
+    used = 0;
+  };
+  for (int i : order) {
+    const int m = e->h_env_map[i];
+    const int w = words_of(e->h_meta[m]);
+    if (w > budget_words)
+      return fail(SPARROW_EUNSUPPORTED, "a map does not fit the LDS budget of a workgroup");
+    if (cur == epw || used + w > budget_words) flush();
+    cur_slots.push_back(make_int4(i, m, used, w));
+    used += w;
+    cur += 1;
+  }
+  flush();
+  if (hipMalloc(&gr.d_slots, sizeof(int4) * slots.size()) != hipSuccess)
+    return fail(SPARROW_ENOMEM, "slot table allocation failed");
+  HIP_TRY(hipMemcpy(gr.d_slots, slots.data(), sizeof(int4) * slots.size(),
+                    hipMemcpyHostToDevice));
+  auto res = e->groups.emplace(key, gr);
+  *out = &res.first->second;
+  return SPARROW_OK;
+}
+
+Params base_params(sparrow_env* e) {
+  Params p{};
+  const sparrow_config& c = e->cfg;
+  p.s = e->s;
+  p.words = e->words;
+  p.meta = e->meta;
+  p.inv_dn = e->inv_dn;
+  p.env_map = e->env_map;
+  p.rays = e->rays;
+  p.n_envs = c.n_envs;
+  p.n_rays = c.n_rays;
+  p.obs_dim = obs_dim(e);
+  p.M = (int32_t)std::floor((double)c.range_cells / (double)c.march_step);
+  p.t_max = c.timeout_steps;
+  p.delay_lo = c.delay_lo;
+  p.delay_hi = c.delay_hi;
+  p.ds = c.march_step;
+  p.range = c.range_cells;
+  p.inv_R = (float)(1.0 / (double)c.range_cells);
+  p.robot_r = c.robot_radius;
+  p.arrive_r = c.arrive_radius;
+  p.omega_max = c.omega_max;
+  // spans in binary32, as the draws use them
+  p.dt_lo = c.dt_lo;
+  p.dt_span = c.dt_hi - c.dt_lo;
+  p.K_lo = c.K_lo;
+  p.K_span = c.K_hi - c.K_lo;
+  p.mu_lo = c.mu_lo;
+  p.mu_span = c.mu_hi - c.mu_lo;
+  p.vmax_lo = c.vmax_lo;
+  p.vmax_span = c.vmax_hi - c.vmax_lo;
+  p.sigma_lo = c.sigma_lo;
+  p.sigma_span = c.sigma_hi - c.sigma_lo;
+  p.key0 = (uint32_t)c.seed;
+  p.key1 = (uint32_t)(c.seed >> 32);
+  p.g = e->g;
+  p.cur_obs = e->cur_obs;
+  p.hit_k = e->hit_k;
+  p.err = e->err;
+  p.eps = e->eps;
+  return p;
+}
+
+int check_L(int L) { return L == 16 || L == 32 || L == 64; }
+
+template <int L>
+int launch_step_L(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
+  const int threads = std::max(64, gr.epw * L);
+  const size_t shmem = (size_t)gr.max_words * 4;
+  HIP_TRY(hipFuncSetAttribute((const void*)k_step<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shmem));
+  hipLaunchKernelGGL(k_step<L>, dim3(gr.G), dim3(threads), shmem, e->stream, p, mode);
+  HIP_TRY(hipGetLastError());
+  return SPARROW_OK;
+}
+
+int launch_step(sparrow_env* e, Params p, int mode, int epw, int L) {
+  Groups* gr = nullptr;
+  int rc = get_groups(e, epw, e->lds_max / 4, &gr);
+  if (rc) return rc;
+  p.slots = gr->d_slots;
+  p.n_groups = gr->G;
+  p.epw = gr->epw;
+  switch (L) {
+    case 16: return launch_step_L<16>(e, p, *gr, mode);
+    case 32: return launch_step_L<32>(e, p, *gr, mode);
+    case 64: return launch_step_L<64>(e, p, *gr, mode);
+  }
+  return fail(SPARROW_EINVAL, "lanes_per_env must be 16, 32 or 64");
+}
+
+// 0: no actor network; 1: obs padded to 64; 2: obs padded to 96
+int qnet_kind(const QParams& q) {
+  if (q.h1 != 256 || q.h2 != 256) return -1;
+  return q.d0p == 64 ? 1 : q.d0p == 96 ? 2 : -1;
+}
+
+template <int L>
+const void* rollout_fn_L(int kind) {
+  if (kind == 1) return (const void*)k_rollout<L, Q64>;
+  if (kind == 2) return (const void*)k_rollout<L, Q96>;
+  return (const void*)k_rollout<L, NoQ>;
+}
+
+const void* rollout_kernel(int L, int kind) {
+  switch (L) {
+    case 16: return rollout_fn_L<16>(kind);
+    case 32: return rollout_fn_L<32>(kind);
+    default: return rollout_fn_L<64>(kind);
+  }
+}
+
+const void* qnet_kernel(int kind) {
+  return kind == 2 ? (const void*)k_qnet<Q96> : (const void*)k_qnet<Q64>;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+const char* sparrow_last_error(void) { return g_last_error.c_str(); }
+
+int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hip_stream,
+                   sparrow_env** out) {
+  if (!cfg || !maps || !out) return fail(SPARROW_EINVAL, "NULL argument");
+  *out = nullptr;
+  const sparrow_config& c = *cfg;
+  if (c.n_envs < 1) return fail(SPARROW_EINVAL, "n_envs must be >= 1");
+  if (c.n_rays < 1 || c.n_rays > SPARROW_MAX_RAYS) return fail(SPARROW_EINVAL, "n_rays must be in [1, 128]");
+  if (c.n_actions != SPARROW_N_ACTIONS) return fail(SPARROW_EINVAL, "n_actions must be 7");
+  if (!(c.range_cells > 0.0f) || !(c.march_step > 0.0f) ||
+      c.range_cells / c.march_step > 4096.0f)
+    return fail(SPARROW_EINVAL, "range/march_step out of bounds");
+  if (!(c.robot_radius > 0.0f && c.robot_radius <= 8.0f)) return fail(SPARROW_EINVAL, "robot_radius must be in (0, 8]");
+  if (!(c.arrive_radius >= 0.0f)) return fail(SPARROW_EINVAL, "arrive_radius must be >= 0");
+  if (c.timeout_steps < 1) return fail(SPARROW_EINVAL, "timeout_steps must be >= 1");
+  if (c.delay_lo < 0 || c.delay_hi > 2 || c.delay_lo > c.delay_hi) return fail(SPARROW_EINVAL, "delay range must lie in [0, 2]");
+  if (!(c.omega_max > 0.0f) || !(c.vmax_lo > 0.0f) || c.vmax_hi < c.vmax_lo || c.dt_hi < c.dt_lo ||
+      c.K_hi < c.K_lo || c.mu_hi < c.mu_lo || c.sigma_hi < c.sigma_lo || c.sigma_lo < 0.0f)
+    return fail(SPARROW_EINVAL, "bad randomisation range");
+  if (maps->n_maps < 1 || !maps->cells || !maps->offsets || !maps->width || !maps->height ||
+      !maps->env_to_map)
+    return fail(SPARROW_EINVAL, "bad maps");
+  for (int m = 0; m < maps->n_maps; ++m)
+    if (maps->width[m] < 1 || maps->height[m] < 1 || maps->width[m] > SPARROW_MAX_SIDE ||
+        maps->height[m] > SPARROW_MAX_SIDE || maps->offsets[m] < 0)
+      return fail(SPARROW_EINVAL, "map side must be in [1, 512]");
+  for (int i = 0; i < c.n_envs; ++i)
+    if (maps->env_to_map[i] < 0 || maps->env_to_map[i] >= maps->n_maps)
+      return fail(SPARROW_EINVAL, "env_to_map entry out of range");
+
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SPARROW_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+
+  auto* e = new sparrow_env();
+  e->cfg = c;
+  e->stream = (hipStream_t)hip_stream;
+  e->device = dev;
+  e->n_cu = prop.multiProcessorCount;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+    e->lds_max = lds;
+  e->n_maps = maps->n_maps;
+  const int N = c.n_envs;
+
+  // maps: meta, pack on the device
+  e->h_meta.resize(maps->n_maps);
+  uint64_t total_words = 0;
+  int64_t cell_bytes = 0;
+  for (int m = 0; m < maps->n_maps; ++m) {
+    MapMeta mm;
+    mm.W = maps->width[m];
+    mm.H = maps->height[m];
+    mm.wpr = (mm.W + 2 + 31) / 32;
+    mm.off = (uint32_t)total_words;
+    total_words += (uint64_t)words_of(mm);
+    e->h_meta[m] = mm;
+    cell_bytes = std::max<int64_t>(cell_bytes, maps->offsets[m] + (int64_t)mm.W * mm.H);
+  }
+  if (total_words >= (1ull << 32)) {
+    delete e;
+    return fail(SPARROW_EINVAL, "maps too large");
+  }
+  e->h_env_map.assign(maps->env_to_map, maps->env_to_map + N);
+  std::vector<float> inv_dn(maps->n_maps);
+  for (int m = 0; m < maps->n_maps; ++m)
+    inv_dn[m] = (float)(1.0 / (std::sqrt(2.0) * (double)std::max(e->h_meta[m].W, e->h_meta[m].H)));
+  std::vector<float2> rays(c.n_rays);
+  for (int j = 0; j < c.n_rays; ++j) {
+    const double fov = (double)c.fov_rad;
+    const double th = c.n_rays > 1 ? -fov / 2.0 + (double)j * fov / (double)(c.n_rays - 1) : 0.0;
+    rays[j] = make_float2((float)std::cos(th), (float)std::sin(th));
+  }
+
+  int rc = SPARROW_OK;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (rc) return;
+    if (hipMalloc(p, bytes ? bytes : 4) != hipSuccess) rc = fail(SPARROW_ENOMEM, "hipMalloc failed");
+  };
+  alloc((void**)&e->words, total_words * 4);
+  alloc((void**)&e->meta, sizeof(MapMeta) * maps->n_maps);
+  alloc((void**)&e->inv_dn, sizeof(float) * maps->n_maps);
+  alloc((void**)&e->env_map, sizeof(int32_t) * N);
+  alloc((void**)&e->rays, sizeof(float2) * c.n_rays);
+  alloc((void**)&e->cur_obs, sizeof(float) * (size_t)N * obs_dim(e));
+  alloc((void**)&e->hit_k, sizeof(int16_t) * (size_t)N * c.n_rays);
+  alloc((void**)&e->err, sizeof(int32_t));
+  const size_t fbytes = sizeof(float) * (size_t)N;
+  alloc(&e->state_block, fbytes * 15);
+  if (rc) {
+    sparrow_destroy(e);
+    return rc;
+  }
+  float* fb = (float*)e->state_block;
+  float** fields[] = {&e->s.x, &e->s.y, &e->s.phi, &e->s.vl, &e->s.va, &e->s.tx, &e->s.ty,
+                      &e->s.dprev, &e->s.dt, &e->s.K, &e->s.mu, &e->s.vmax, &e->s.sigma};
+  for (int f = 0; f < 13; ++f) *fields[f] = fb + (size_t)f * N;
+  e->s.t = (int32_t*)(fb + (size_t)13 * N);
+  e->s.ctl = (uint32_t*)(fb + (size_t)14 * N);
+
+  uint8_t* d_cells = nullptr;
+  int64_t* d_offs = nullptr;
+  auto cleanup = [&](int code) {
+    if (d_cells) (void)hipFree(d_cells);
+    if (d_offs) (void)hipFree(d_offs);
+    if (code) sparrow_destroy(e);
+    return code;
+  };
+  if (hipMalloc((void**)&d_cells, (size_t)std::max<int64_t>(cell_bytes, 1)) != hipSuccess ||
+      hipMalloc((void**)&d_offs, sizeof(int64_t) * maps->n_maps) != hipSuccess)
+    return cleanup(fail(SPARROW_ENOMEM, "hipMalloc failed"));
+#define CREATE_TRY(expr)                                                                    \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return cleanup(fail(SPARROW_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e))); \
+  } while (0)
+  CREATE_TRY(hipMemcpy(d_cells, maps->cells, (size_t)cell_bytes, hipMemcpyHostToDevice));
+  CREATE_TRY(hipMemcpy(d_offs, maps->offsets, sizeof(int64_t) * maps->n_maps, hipMemcpyHostToDevice));
+  CREATE_TRY(hipMemcpy(e->meta, e->h_meta.data(), sizeof(MapMeta) * maps->n_maps, hipMemcpyHostToDevice));
+  CREATE_TRY(hipMemcpy(e->inv_dn, inv_dn.data(), sizeof(float) * maps->n_maps, hipMemcpyHostToDevice));
+  CREATE_TRY(hipMemcpy(e->env_map, maps->env_to_map, sizeof(int32_t) * N, hipMemcpyHostToDevice));
+  CREATE_TRY(hipMemcpy(e->rays, rays.data(), sizeof(float2) * c.n_rays, hipMemcpyHostToDevice));
+  CREATE_TRY(hipMemset(e->err, 0, sizeof(int32_t)));
+  CREATE_TRY(hipMemset(e->state_block, 0, fbytes * 15));
+  CREATE_TRY(hipMemset(e->cur_obs, 0, sizeof(float) * (size_t)N * obs_dim(e)));
+  CREATE_TRY(hipMemset(e->hit_k, 0, sizeof(int16_t) * (size_t)N * c.n_rays));
+  {
+    int max_words = 0;
+    for (auto& mm : e->h_meta) max_words = std::max(max_words, words_of(mm));
+    const int gy = std::min(maps->n_maps, 65535), gz = (maps->n_maps + 65534) / 65535;
+    dim3 grid((max_words + 255) / 256, gy, gz);
+    hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, nullptr, d_cells, d_offs, e->meta, e->words,
+                       maps->n_maps);
+    CREATE_TRY(hipGetLastError());
+    CREATE_TRY(hipDeviceSynchronize());
+  }
+  CREATE_TRY(hipStreamCreateWithFlags(&e->capture, hipStreamNonBlocking));
+#undef CREATE_TRY
+  cleanup(SPARROW_OK);
+  *out = e;
+  return SPARROW_OK;
+}
+
+void sparrow_destroy(sparrow_env* e) {
+  if (!e) return;
+  for (auto& kv : e->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
+  for (auto& kv : e->groups)
+    if (kv.second.d_slots) (void)hipFree(kv.second.d_slots);
+  void* bufs[] = {e->words, e->meta, e->inv_dn, e->env_map, e->rays, e->cur_obs, e->hit_k,
+                  e->err, e->state_block, e->q_block, e->eps};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (e->capture) (void)hipStreamDestroy(e->capture);
+  delete e;
+}
+
+int sparrow_reset(sparrow_env* e, float* obs) {
+  if (!e || !obs) return fail(SPARROW_EINVAL, "NULL argument");
+  Params p = base_params(e);
+  p.obs = obs;
+  const int rc = launch_step(e, p, 1, e->var_epw[0], e->var_L[0]);
+  if (rc) return rc;
+  e->g += 1;
+  e->was_reset = true;
+  return SPARROW_OK;
+}
+
+int sparrow_step(sparrow_env* e, const int32_t* actions, float* obs, float* reward, uint8_t* done,
+                 uint8_t* flags, float* final_obs) {
+  if (!e || !actions || !obs || !reward || !done) return fail(SPARROW_EINVAL, "NULL argument");
+  Params p = base_params(e);
+  p.actions = actions;
+  p.obs = obs;
+  p.reward = reward;
+  p.done = done;
+  p.flags = flags;
+  p.final_obs = final_obs;
+  const int rc = launch_step(e, p, 0, e->var_epw[0], e->var_L[0]);
+  if (rc) return rc;
+  e->g += 1;
+  return SPARROW_OK;
+}
+
+int sparrow_random_actions(sparrow_env* e, int32_t* actions) {
+  if (!e || !actions) return fail(SPARROW_EINVAL, "NULL argument");
+  const int N = e->cfg.n_envs;
+  hipLaunchKernelGGL(k_actions, dim3((N + 255) / 256), dim3(256), 0, e->stream, N, e->g,
+                     (uint32_t)e->cfg.seed, (uint32_t)(e->cfg.seed >> 32), actions);
+  HIP_TRY(hipGetLastError());
+  return SPARROW_OK;
+}
+
+int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16, const float* b_f32,
+                     const float* eps) {
+  if (!e || !dims || !w_bf16 || !b_f32 || !eps) return fail(SPARROW_EINVAL, "NULL argument");
+  const int d0 = dims[0], h1 = dims[1], h2 = dims[2], A = dims[3];
+  if (d0 != obs_dim(e) || A != SPARROW_N_ACTIONS) return fail(SPARROW_EINVAL, "qnet dims must be {n_rays + 4, h1, h2, 7}");
+  if (h1 != 256 || h2 != 256 || d0 > 96)
+    return fail(SPARROW_EUNSUPPORTED, "the register-resident actor supports h1 = h2 = 256, obs_dim <= 96");
+  if (e->q_block) {
+    (void)hipFree(e->q_block);
+    e->q_block = nullptr;
+  }
+  if (e->eps) {
+    (void)hipFree(e->eps);
+    e->eps = nullptr;
+  }
+  QParams qp{};
+  qp.d0 = d0;
+  qp.h1 = h1;
+  qp.h2 = h2;
+  qp.d0p = d0 <= 64 ? 64 : 96;
+  const size_t w_elems = (size_t)h1 * d0 + (size_t)h2 * h1 + (size_t)A * h2;
+  const size_t b_elems = (size_t)h1 + h2 + A;
+  const size_t w1p = (size_t)h1 * qp.d0p, w2p = (size_t)h2 * h1, w3p = (size_t)16 * h2;
+  const size_t bytes = (w1p + w2p + w3p) * 2 + (size_t)(h1 + h2 + 16) * 4 + 256;
+  if (hipMalloc(&e->q_block, bytes) != hipSuccess) return fail(SPARROW_ENOMEM, "hipMalloc failed");
+  if (hipMalloc((void**)&e->eps, sizeof(float) * e->cfg.n_envs) != hipSuccess)
+    return fail(SPARROW_ENOMEM, "hipMalloc failed");
+  char* base = (char*)e->q_block;
+  qp.w1 = (uint16_t*)base;
+  qp.w2 = qp.w1 + w1p;
+  qp.w3 = qp.w2 + w2p;
+  qp.b1 = (float*)(qp.w3 + w3p);
+  qp.b2 = qp.b1 + h1;
+  qp.b3 = qp.b2 + h2;
+  // repack on the device: W1 rows padded to d0p, W3 padded to 16 rows, b3 to 16
+  HIP_TRY(hipMemsetAsync(e->q_block, 0, bytes, e->stream));
+  HIP_TRY(hipMemcpy2DAsync((void*)qp.w1, qp.d0p * 2, w_bf16, (size_t)d0 * 2, (size_t)d0 * 2, h1,
+                           hipMemcpyDeviceToDevice, e->stream));
+  HIP_TRY(hipMemcpyAsync((void*)qp.w2, w_bf16 + (size_t)h1 * d0, w2p * 2, hipMemcpyDeviceToDevice, e->stream));
+  HIP_TRY(hipMemcpyAsync((void*)qp.w3, w_bf16 + (size_t)h1 * d0 + w2p, (size_t)A * h2 * 2,
+                         hipMemcpyDeviceToDevice, e->stream));
+  HIP_TRY(hipMemcpyAsync((void*)qp.b1, b_f32, (size_t)b_elems * 4, hipMemcpyDeviceToDevice, e->stream));
+  HIP_TRY(hipMemcpyAsync(e->eps, eps, sizeof(float) * e->cfg.n_envs, hipMemcpyDeviceToDevice,
+                         e->stream));
+  (void)w_elems;
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  e->qp = qp;
+  e->has_qnet = true;
+  return SPARROW_OK;
+}
+
+static int launch_qnet(sparrow_env* e, const float* obs, int32_t n, float* q, int32_t* greedy,
+                       int32_t* actions) {
+  const void* fn = qnet_kernel(qnet_kind(e->qp));
+  QParams qp = e->qp;
+  qp.lds_base_words = 0;
+  const size_t shmem = qnet_lds_bytes(qp);
+  HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const int blocks = std::max(1, std::min((n + kQRows - 1) / kQRows, e->n_cu));
+  const float* eps = e->eps;
+  uint32_t g = e->g, k0 = (uint32_t)e->cfg.seed, k1 = (uint32_t)(e->cfg.seed >> 32);
+  void* args[] = {&qp, &obs, &n, &q, &greedy, &eps, &g, &k0, &k1, &actions};
+  HIP_TRY(hipLaunchKernel(fn, dim3(blocks), dim3(kQThreads), args, shmem, e->stream));
+  return SPARROW_OK;
+}
+
+int sparrow_qnet_forward(sparrow_env* e, const float* obs, int32_t n, float* q, int32_t* greedy) {
+  if (!e || !obs || n < 0) return fail(SPARROW_EINVAL, "bad argument");
+  if (!e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
+  if (n == 0) return SPARROW_OK;
+  return launch_qnet(e, obs, n, q, greedy, nullptr);
+  return SPARROW_OK;
+}
+
+int sparrow_act(sparrow_env* e, const float* obs, int32_t* actions) {
+  if (!e || !obs || !actions) return fail(SPARROW_EINVAL, "NULL argument");
+  if (!e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
+  return launch_qnet(e, obs, e->cfg.n_envs, nullptr, nullptr, actions);
+}
+
+static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int32_t* actions,
+                          float* reward, uint8_t* done, float* obs, bool use_graph) {
+  const int reserve = q ? (int)qnet_lds_bytes(e->qp) : 0;
+  const int budget_words = (e->lds_max - reserve) / 4;
+  Groups* gr = nullptr;
+  int rc = get_groups(e, epw, budget_words, &gr);
+  if (rc) return rc;
+  const int threads = q ? kQThreads : std::max(64, epw * L);
+  const size_t shmem = (size_t)reserve + (size_t)gr->max_words * 4;
+  const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0);
+  HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  int per_cu = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem));
+  if (per_cu < 1) return fail(SPARROW_EUNSUPPORTED, "rollout variant does not fit a CU");
+  const int grid = std::min(gr->G, per_cu * e->n_cu);
+
+  Params p = base_params(e);
+  p.slots = gr->d_slots;
+  p.n_groups = gr->G;
+  p.epw = gr->epw;
+  p.K_steps = K;
+  p.obs = obs;
+  p.r_actions = actions;
+  p.r_reward = reward;
+  p.r_done = done;
+  QParams qp = e->qp;
+  qp.lds_base_words = gr->max_words;
+  void* args[] = {&p, &qp};
+  if (!use_graph) {
+    HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(threads), args, shmem, e->stream));
+    e->g += (uint32_t)K;
+    return SPARROW_OK;
+  }
+  auto key = std::make_tuple((int)K, (int)q, L, epw, (void*)actions, (void*)reward, (void*)done,
+                             (void*)obs);
+  auto it = e->graphs.find(key);
+  if (it == e->graphs.end()) {
+    GraphEntry ge;
+    HIP_TRY(hipStreamBeginCapture(e->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipLaunchKernel(fn, dim3(grid), dim3(threads), args, shmem, e->capture);
+    hipError_t ce = hipStreamEndCapture(e->capture, &ge.graph);
+    if (le != hipSuccess) return fail(SPARROW_EHIP, std::string("rollout launch: ") + hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(SPARROW_EHIP, std::string("capture: ") + hipGetErrorString(ce));
+    size_t n_nodes = 0;
+    HIP_TRY(hipGraphGetNodes(ge.graph, nullptr, &n_nodes));
+    if (n_nodes != 1) return fail(SPARROW_EHIP, "unexpected graph shape");
+    HIP_TRY(hipGraphGetNodes(ge.graph, &ge.node, &n_nodes));
+    HIP_TRY(hipGraphKernelNodeGetParams(ge.node, &ge.kp));
+    HIP_TRY(hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+    it = e->graphs.emplace(key, ge).first;
+  }
+  GraphEntry& ge = it->second;
+  hipKernelNodeParams kp = ge.kp;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.node, &kp));
+  HIP_TRY(hipGraphLaunch(ge.exec, e->stream));
+  e->g += (uint32_t)K;
+  return SPARROW_OK;
+}
+
+int sparrow_rollout(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* actions, float* reward,
+                    uint8_t* done, float* obs) {
+  if (!e || !reward || !done || !obs || K < 1) return fail(SPARROW_EINVAL, "bad argument");
+  if (use_qnet && !e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
+  if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
+  return launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done,
+                        obs, true);
+}
+
+int sparrow_debug_hits(sparrow_env* e, int16_t* hit_k) {
+  if (!e || !hit_k) return fail(SPARROW_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(hit_k, e->hit_k, sizeof(int16_t) * (size_t)e->cfg.n_envs * e->cfg.n_rays,
+                         hipMemcpyDeviceToDevice, e->stream));
+  return SPARROW_OK;
+}
+
+int sparrow_get_state(sparrow_env* e, float* f, int32_t* iv) {
+  if (!e || !f || !iv) return fail(SPARROW_EINVAL, "NULL argument");
+  const int N = e->cfg.n_envs;
+  std::vector<float> blk((size_t)N * 15);
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  HIP_TRY(hipMemcpy(blk.data(), e->state_block, blk.size() * 4, hipMemcpyDeviceToHost));
+  for (int i = 0; i < N; ++i) {
+    for (int k = 0; k < 13; ++k) f[(size_t)i * 13 + k] = blk[(size_t)k * N + i];
+    int32_t t;
+    uint32_t ctl;
+    std::memcpy(&t, &blk[(size_t)13 * N + i], 4);
+    std::memcpy(&ctl, &blk[(size_t)14 * N + i], 4);
+    iv[(size_t)i * 4 + 0] = t;
+    iv[(size_t)i * 4 + 1] = (int32_t)(ctl & 0xFF);
+    iv[(size_t)i * 4 + 2] = (int32_t)((ctl >> 8) & 0xFF);
+    iv[(size_t)i * 4 + 3] = (int32_t)((ctl >> 16) & 0xFF);
+  }
+  return SPARROW_OK;
+}
+
+int sparrow_set_state(sparrow_env* e, const float* f, const int32_t* iv) {
+  if (!e || !f || !iv) return fail(SPARROW_EINVAL, "NULL argument");
+  const int N = e->cfg.n_envs;
+  std::vector<float> blk((size_t)N * 15);
+  for (int i = 0; i < N; ++i) {
+    for (int k = 0; k < 13; ++k) blk[(size_t)k * N + i] = f[(size_t)i * 13 + k];
+    const int32_t d = iv[(size_t)i * 4 + 1], q0 = iv[(size_t)i * 4 + 2], q1 = iv[(size_t)i * 4 + 3];
+    if (d < 0 || d > 2 || q0 < 0 || q0 > kStop || q1 < 0 || q1 > kStop)
+      return fail(SPARROW_EINVAL, "delay must be 0..2 and queued actions 0..7");
+    const uint32_t ctl = (uint32_t)d | ((uint32_t)q0 << 8) | ((uint32_t)q1 << 16);
+    std::memcpy(&blk[(size_t)13 * N + i], &iv[(size_t)i * 4 + 0], 4);
+    std::memcpy(&blk[(size_t)14 * N + i], &ctl, 4);
+  }
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  HIP_TRY(hipMemcpy(e->state_block, blk.data(), blk.size() * 4, hipMemcpyHostToDevice));
+  e->was_reset = true;
+  return SPARROW_OK;
+}
+
+uint32_t sparrow_global_step(const sparrow_env* e) { return e ? e->g : 0u; }
+void sparrow_set_global_step(sparrow_env* e, uint32_t g) {
+  if (e) e->g = g;
+}
+
+int sparrow_set_variant(sparrow_env* e, int32_t kernel, int32_t epw, int32_t L) {
+  if (!e || (kernel != 0 && kernel != 1)) return fail(SPARROW_EINVAL, "kernel must be 0 or 1");
+  if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8)) return fail(SPARROW_EINVAL, "envs_per_group must be 1, 2, 4 or 8");
+  if (!check_L(L)) return fail(SPARROW_EINVAL, "lanes_per_env must be 16, 32 or 64");
+  e->var_epw[kernel] = epw;
+  e->var_L[kernel] = L;
+  return SPARROW_OK;
+}
+
+int sparrow_get_variant(const sparrow_env* e, int32_t kernel, int32_t* epw, int32_t* L) {
+  if (!e || !epw || !L || (kernel != 0 && kernel != 1)) return fail(SPARROW_EINVAL, "bad argument");
+  *epw = e->var_epw[kernel];
+  *L = e->var_L[kernel];
+  return SPARROW_OK;
+}
+
+int sparrow_autotune(sparrow_env* e, int32_t steps, char* report, int32_t report_len) {
+  if (!e || steps < 1) return fail(SPARROW_EINVAL, "bad argument");
+  if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before autotune");
+  const int N = e->cfg.n_envs, D = obs_dim(e);
+  const size_t sbytes = sizeof(float) * (size_t)N * 15, obytes = sizeof(float) * (size_t)N * D;
+  const size_t hbytes = sizeof(int16_t) * (size_t)N * e->cfg.n_rays;
+  const int K = steps;
+  // scratch: saved state, observation, hits; step and rollout outputs
+  void *s_state = nullptr, *s_obs = nullptr, *s_hit = nullptr, *o_buf = nullptr;
+  const size_t obuf = (size_t)K * N * (4 + 4 + 1) + obytes + (size_t)N * (4 + 4 + 1) + 256;
+  auto release = [&]() {
+    for (void* b : {s_state, s_obs, s_hit, o_buf})
+      if (b) (void)hipFree(b);
+  };
+  if (hipMalloc(&s_state, sbytes) != hipSuccess || hipMalloc(&s_obs, obytes) != hipSuccess ||
+      hipMalloc(&s_hit, hbytes) != hipSuccess || hipMalloc(&o_buf, obuf) != hipSuccess) {
+    release();
+    return fail(SPARROW_ENOMEM, "autotune scratch allocation failed");
+  }
+  char* ob = (char*)o_buf;
+  int32_t* r_act = (int32_t*)ob;
+  float* r_rew = (float*)(ob + (size_t)K * N * 4);
+  uint8_t* r_done = (uint8_t*)(ob + (size_t)K * N * 8);
+  float* obs = (float*)(ob + (((size_t)K * N * 9 + 255) & ~(size_t)255));
+  int32_t* acts = (int32_t*)((char*)obs + obytes);
+  float* rew = (float*)(acts + N);
+  uint8_t* dn = (uint8_t*)(rew + N);
+  const uint32_t g0 = e->g;
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  int rc = SPARROW_OK;
+  auto save = [&]() {
+    (void)hipMemcpyAsync(s_state, e->state_block, sbytes, hipMemcpyDeviceToDevice, e->stream);
+    (void)hipMemcpyAsync(s_obs, e->cur_obs, obytes, hipMemcpyDeviceToDevice, e->stream);
+    (void)hipMemcpyAsync(s_hit, e->hit_k, hbytes, hipMemcpyDeviceToDevice, e->stream);
+  };
+  auto restore = [&]() {
+    (void)hipMemcpyAsync(e->state_block, s_state, sbytes, hipMemcpyDeviceToDevice, e->stream);
+    (void)hipMemcpyAsync(e->cur_obs, s_obs, obytes, hipMemcpyDeviceToDevice, e->stream);
+    (void)hipMemcpyAsync(e->hit_k, s_hit, hbytes, hipMemcpyDeviceToDevice, e->stream);
+    e->g = g0;
+  };
+  save();
+  std::string js = "{\"step\": [";
+  const int epws[4] = {1, 2, 4, 8}, Ls[3] = {16, 32, 64};
+  float best[2] = {1e30f, 1e30f};
+  int best_epw[2] = {e->var_epw[0], e->var_epw[1]}, best_L[2] = {e->var_L[0], e->var_L[1]};
+  bool first = true;
+  for (int kernel = 0; kernel < 2 && rc == SPARROW_OK; ++kernel) {
+    if (kernel == 1) js += "], \"rollout\": [";
+    first = true;
+    for (int ei = 0; ei < 4 && rc == SPARROW_OK; ++ei)
+      for (int li = 0; li < 3 && rc == SPARROW_OK; ++li) {
+        const int epw = epws[ei], L = Ls[li];
+        auto run = [&]() -> int {
+          if (kernel == 0) {
+            for (int s = 0; s < K; ++s) {
+              int r = sparrow_random_actions(e, acts);
+              if (!r) {
+                Params p = base_params(e);
+                p.actions = acts;
+                p.obs = obs;
+                p.reward = rew;
+                p.done = dn;
+                r = launch_step(e, p, 0, epw, L);
+              }
+              if (r) return r;
+              e->g += 1;
+            }
+            return SPARROW_OK;
+          }
+          return launch_rollout(e, K, e->has_qnet, epw, L, r_act, r_rew, r_done, obs, false);
+        };
+        int r = run();  // warm-up (also builds the slot table)
+        restore();
+        if (r == SPARROW_OK) {
+          (void)hipEventRecord(t0, e->stream);
+          r = run();
+          (void)hipEventRecord(t1, e->stream);
+          restore();
+        }
+        float ms = -1.0f;
+        if (r == SPARROW_OK) {
+          if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+            rc = fail(SPARROW_EHIP, "autotune timing failed");
+            break;
+          }
+          if (ms < best[kernel]) {
+            best[kernel] = ms;
+            best_epw[kernel] = epw;
+            best_L[kernel] = L;
+          }
+        } else if (r != SPARROW_EUNSUPPORTED) {
+          rc = r;
+          break;
+        }
+        char buf[128];
+        std::snprintf(buf, sizeof(buf), "%s{\"epw\": %d, \"L\": %d, \"ms\": %.4f}", first ? "" : ", ",
+                      epw, L, ms);
+        js += buf;
+        first = false;
+      }
+  }
+  js += "]";
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  (void)hipStreamSynchronize(e->stream);
+  release();
+  if (rc) return rc;
+  for (int k = 0; k < 2; ++k) {
+    e->var_epw[k] = best_epw[k];
+    e->var_L[k] = best_L[k];
+  }
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), ", \"chosen\": {\"step\": [%d, %d], \"rollout\": [%d, %d]}, \"steps\": %d}",
+                best_epw[0], best_L[0], best_epw[1], best_L[1], K);
+  js += buf;
+  if (report && report_len > 0) std::snprintf(report, report_len, "%s", js.c_str());
+  return SPARROW_OK;
+}
+
+int sparrow_status(sparrow_env* e) {
+  if (!e) return fail(SPARROW_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  int32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, e->err, 4, hipMemcpyDeviceToHost));
+  if (err) return fail(err, "AutoReset found no free start or target cell");
+  return SPARROW_OK;
+}
+
+}  // extern "C"

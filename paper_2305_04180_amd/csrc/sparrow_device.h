@@ -1,0 +1,567 @@
+// sparrow_device.h -- gfx950 device code of the vectorized Sparrow step.
+//
+// Method (arXiv 2305.04180): Sec. 3.2.2 Eq. (5)/(6) kinematics applied per
+// env as in Eq. (7)/(8); Sec. 3.2 LiDAR ray casting, noise and collision on
+// the occupancy grid; Sec. 3.2.4 per-episode domain randomisation; Sec. 3.2.5
+// AutoReset; Sec. 4.3.1 state, actions and terminal rewards; Sec. 3.1.1 VEM.
+//
+// Execution model. A workgroup owns a group of envs whose bit-packed maps it
+// stages into LDS. Each env is served by L consecutive lanes of one wave
+// (L = 16, 32 or 64); those lanes hold the env's scalar state redundantly, so
+// kinematics need no broadcast, and split the per-ray and per-cell work:
+// a lane marches one ray (or several, or half the samples of one ray when
+// L exceeds the ray count) and wave ballots give first hits, collision and
+// the lowest accepted reset candidate.
+//
+// Floating point: everything that can move a grid index or a done flag is
+// evaluated as separately rounded binary32 operations in a fixed order
+// (built with -ffp-contract=off), so hit cells and done flags are exact.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sp {
+
+constexpr int kStop = 7;
+constexpr int kNumActions = 7;
+
+// Philox counter word 2 ("purpose") of each random draw.
+enum : uint32_t {
+  kResetDR = 1, kResetStart = 2, kResetTarget = 3, kNoise = 4,
+  kNoiseReset = 5, kActionUniform = 6, kExplore = 7
+};
+
+constexpr double kPiD = 3.14159265358979323846;
+constexpr float kPiF = (float)kPiD;
+constexpr float kTwoPiF = (float)(2.0 * kPiD);
+constexpr float kTwoOverPiF = (float)(2.0 / kPiD);
+constexpr float kInvPiF = (float)(1.0 / kPiD);
+constexpr float kTwoM24 = 5.9604644775390625e-08f;
+
+// Target velocity table: (fraction of v_max, fraction of omega_max).
+__constant__ const float kActV[7] = {0.02f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 0.02f};
+__constant__ const float kActW[7] = {1.0f, 1.0f, 0.5f, 0.0f, -0.5f, -1.0f, -1.0f};
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11), counter (env, step, purpose, sub).
+// ------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// float -> bf16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * kTwoM24; }
+__device__ __forceinline__ int scale_u32(uint32_t w, uint32_t n) {
+  return (int)__umulhi(w, n);  // floor(w * n / 2^32)
+}
+
+// ------------------------------------------------------------------------
+// sincos: Cody-Waite three-part reduction by pi/2, Taylor polynomials of
+// sin (to r^11) and cos (to r^10) with coefficients +-1/n!.
+// ------------------------------------------------------------------------
+constexpr float clear12(float f) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, f) & ~0xFFFu);
+}
+constexpr float kRedA = clear12((float)(kPiD / 2.0));
+constexpr float kRedB = clear12((float)(kPiD / 2.0 - (double)kRedA));
+constexpr float kRedC = (float)(kPiD / 2.0 - (double)kRedA - (double)kRedB);
+
+__device__ __forceinline__ void sincos_f32(float phi, float& s_out, float& c_out) {
+  const float s1 = (float)(-1.0 / 6.0), s2 = (float)(1.0 / 120.0),
+              s3 = (float)(-1.0 / 5040.0), s4 = (float)(1.0 / 362880.0),
+              s5 = (float)(-1.0 / 39916800.0);
+  const float c1 = (float)(-1.0 / 2.0), c2 = (float)(1.0 / 24.0), c3 = (float)(-1.0 / 720.0),
+              c4 = (float)(1.0 / 40320.0), c5 = (float)(-1.0 / 3628800.0);
+  const float kq = __builtin_rintf(phi * kTwoOverPiF);
+  const int k = (int)kq;
+  float r = phi - kq * kRedA;
+  r = r - kq * kRedB;
+  r = r - kq * kRedC;
+  const float r2 = r * r;
+  float ps = s5;
+  ps = ps * r2 + s4;
+  ps = ps * r2 + s3;
+  ps = ps * r2 + s2;
+  ps = ps * r2 + s1;
+  const float s = r + (r * r2) * ps;
+  float pc = c5;
+  pc = pc * r2 + c4;
+  pc = pc * r2 + c3;
+  pc = pc * r2 + c2;
+  pc = pc * r2 + c1;
+  const float c = 1.0f + r2 * pc;
+  const int quad = k & 3;
+  s_out = quad == 0 ? s : quad == 1 ? c : quad == 2 ? -s : -c;
+  c_out = quad == 0 ? c : quad == 1 ? -s : quad == 2 ? -c : s;
+}
+
+// ------------------------------------------------------------------------
+// Kernel parameters (passed by value).
+// ------------------------------------------------------------------------
+struct State {  // structure of arrays, [N] each
+  float *x, *y, *phi, *vl, *va, *tx, *ty, *dprev, *dt, *K, *mu, *vmax, *sigma;
+  int32_t* t;
+  uint32_t* ctl;  // delay | q0 << 8 | q1 << 16
+};
+
+struct MapMeta {  // packed map m: words [off, off + (H + 2) * wpr)
+  uint32_t off;
+  int32_t W, H, wpr;
+};
+
+struct Params {
+  State s;
+  const uint32_t* words;    // all packed maps
+  const MapMeta* meta;      // [n_maps]
+  const float* inv_dn;      // [n_maps]
+  const int32_t* env_map;   // [N]
+  const float2* rays;       // [n_rays] (cos, sin) of each ray's offset angle
+  const int4* slots;        // [n_groups][epw]: {env (-1: empty), map, LDS word offset, words}
+  int32_t n_groups, epw;
+  int32_t n_envs, n_rays, obs_dim, M, t_max, delay_lo, delay_hi;
+  float ds, range, inv_R, robot_r, arrive_r, omega_max;
+  float dt_lo, dt_span, K_lo, K_span, mu_lo, mu_span, vmax_lo, vmax_span, sigma_lo,
+      sigma_span;
+  uint32_t key0, key1;
+  uint32_t g;               // global step of this launch (rollout: of its first step)
+  int32_t K_steps;          // rollout length
+  // step / reset I/O
+  const int32_t* actions;   // [N]
+  float* obs;               // [N][obs_dim]
+  float* cur_obs;           // library copy of the latest observation
+  float* reward;
+  uint8_t* done;
+  uint8_t* flags;
+  float* final_obs;
+  int16_t* hit_k;           // [N][n_rays]
+  int32_t* err;             // sticky error word
+  // rollout I/O ([K][N])
+  int32_t* r_actions;
+  float* r_reward;
+  uint8_t* r_done;
+  // actor
+  const float* eps;         // [N]
+};
+
+// ------------------------------------------------------------------------
+// Per-env register state (every lane of the env holds a copy).
+// ------------------------------------------------------------------------
+struct Env {
+  float x, y, phi, vl, va, tx, ty, dprev, dt, K, mu, vmax, sigma;
+  int32_t t, delay, q0, q1;
+};
+
+__device__ __forceinline__ Env load_env(const State& s, int i) {
+  Env e;
+  e.x = s.x[i]; e.y = s.y[i]; e.phi = s.phi[i]; e.vl = s.vl[i]; e.va = s.va[i];
+  e.tx = s.tx[i]; e.ty = s.ty[i]; e.dprev = s.dprev[i]; e.dt = s.dt[i]; e.K = s.K[i];
+  e.mu = s.mu[i]; e.vmax = s.vmax[i]; e.sigma = s.sigma[i]; e.t = s.t[i];
+  const uint32_t c = s.ctl[i];
+  e.delay = (int)(c & 0xFFu); e.q0 = (int)((c >> 8) & 0xFFu); e.q1 = (int)((c >> 16) & 0xFFu);
+  return e;
+}
+
+__device__ __forceinline__ void store_env(const State& s, int i, const Env& e) {
+  s.x[i] = e.x; s.y[i] = e.y; s.phi[i] = e.phi; s.vl[i] = e.vl; s.va[i] = e.va;
+  s.tx[i] = e.tx; s.ty[i] = e.ty; s.dprev[i] = e.dprev; s.dt[i] = e.dt; s.K[i] = e.K;
+  s.mu[i] = e.mu; s.vmax[i] = e.vmax; s.sigma[i] = e.sigma; s.t[i] = e.t;
+  s.ctl[i] = (uint32_t)e.delay | ((uint32_t)e.q0 << 8) | ((uint32_t)e.q1 << 16);
+}
+
+// ------------------------------------------------------------------------
+// Lane geometry of one env inside a wave.
+// ------------------------------------------------------------------------
+template <int L>
+struct Lanes {
+  int q;          // lane index within the env, [0, L)
+  int seg;        // first wave lane of the env
+  uint64_t mask;  // the env's lanes in a wave ballot
+  __device__ __forceinline__ explicit Lanes(int tid) {
+    q = tid & (L - 1);
+    seg = (tid & 63) & ~(L - 1);
+    if constexpr (L == 64) mask = ~0ull;
+    else mask = ((1ull << L) - 1ull) << seg;
+  }
+  __device__ __forceinline__ uint64_t ballot(bool p) const {
+    return (uint64_t)__ballot(p) & mask;
+  }
+};
+
+// v_cvt_flr_i32_f32: floor and convert in one instruction (equal to
+// (int)floorf(x) for |x| < 2^31; saturates beyond, and NaN gives 0).
+__device__ __forceinline__ int cvt_flr(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ __forceinline__ int med3i(int x, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
+
+// A map slot in LDS: bit (ix + 1) of row (iy + 1), ix in [-1, W], iy in [-1, H];
+// the ring around the map is set, so a coordinate clamped to the ring reads as
+// occupied: outside the map counts as an obstacle. w1 points at row 0 (y = 0),
+// so a clamped row index of -1 addresses the ring row in front of it.
+struct Slot {
+  const uint32_t* w1;
+  int32_t W, H, wpr;
+  // word index (relative to w1) and bit of cell (ix, iy), clamped to the ring
+  __device__ __forceinline__ int word_of(int ix, int iy, int& bit) const {
+    ix = med3i(ix, -1, W);
+    iy = med3i(iy, -1, H);
+    bit = ix + 1;
+    return __mul24(iy, wpr) + (bit >> 5);
+  }
+  __device__ __forceinline__ bool occ(int ix, int iy) const {
+    int bit;
+    const uint32_t word = w1[word_of(ix, iy, bit)];
+    return __builtin_amdgcn_ubfe(word, (uint32_t)bit, 1u) != 0u;
+  }
+};
+
+// Exact disk test over the cell squares meeting [px - r, px + r] x [py - r, py + r].
+__device__ __forceinline__ bool collides_cells(const Slot& m, float px, float py, float r,
+                                               int i0, int i1, int j0, int j1) {
+  const float r2 = r * r;
+  bool hit = false;
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      if (!m.occ(i, j)) continue;
+      const float fi = (float)i, fj = (float)j;
+      const float dx = fmaxf(fmaxf(fi - px, 0.0f), px - (fi + 1.0f));
+      const float dy = fmaxf(fmaxf(fj - py, 0.0f), py - (fj + 1.0f));
+      const float d2 = dx * dx + dy * dy;
+      hit |= d2 <= r2;
+    }
+  return hit;
+}
+
+// Disk of radius r at (px, py) against every occupied cell square that meets
+// the closed box [px - r, px + r] x [py - r, py + r] (distance <= r collides).
+// One lane. When the box lies inside the map, its bits are first read a row
+// at a time (at most two words per row): an empty box cannot collide.
+__device__ __forceinline__ bool collides_seq(const Slot& m, float px, float py, float r) {
+  const int i0 = (int)ceilf(px - r) - 1, i1 = (int)floorf(px + r);
+  const int j0 = (int)ceilf(py - r) - 1, j1 = (int)floorf(py + r);
+  if (i0 >= 0 && j0 >= 0 && i1 < m.W && j1 < m.H) {
+    const int b0 = i0 + 1, nb = i1 - i0 + 1;  // padded bit columns [b0, b0 + nb)
+    const int wlo = b0 >> 5, sh = b0 & 31;
+    const uint64_t mask = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+    uint64_t acc = 0;
+    for (int j = j0; j <= j1; ++j) {
+      // the second word may be the next row's first one: in range, masked off
+      const uint32_t* row = m.w1 + j * m.wpr + wlo;
+      const uint64_t v = (uint64_t)row[0] | ((uint64_t)row[1] << 32);
+      acc |= (v >> sh) & mask;
+    }
+    if (acc == 0) return false;
+  }
+  return collides_cells(m, px, py, r, i0, i1, j0, j1);
+}
+
+// Same test with the cells spread over the env's L lanes.
+template <int L>
+__device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, float px,
+                                             float py, float r) {
+  const float r2 = r * r;
+  const int i0 = (int)ceilf(px - r) - 1, i1 = (int)floorf(px + r);
+  const int j0 = (int)ceilf(py - r) - 1, j1 = (int)floorf(py + r);
+  const int nx = i1 - i0 + 1, nc = nx * (j1 - j0 + 1);
+  bool hit = false;
+  for (int c = ln.q; c < nc; c += L) {
+    const int i = i0 + c % nx, j = j0 + c / nx;
+    if (!m.occ(i, j)) continue;
+    const float fi = (float)i, fj = (float)j;
+    const float dx = fmaxf(fmaxf(fi - px, 0.0f), px - (fi + 1.0f));
+    const float dy = fmaxf(fmaxf(fj - py, 0.0f), py - (fj + 1.0f));
+    const float d2 = dx * dx + dy * dy;
+    hit |= d2 <= r2;
+  }
+  return ln.ballot(hit) != 0ull;
+}
+
+constexpr int kUnroll = 4;  // samples per lane per iteration (independent LDS reads)
+constexpr int kNoHit = 1 << 30;
+
+// Distance of sample k. With ds == 1 it is (float)k; otherwise (float)k * ds.
+template <bool UNIT>
+__device__ __forceinline__ float sample_t(int k, float ds) {
+  return UNIT ? (float)k : (float)k * ds;
+}
+
+// kUnroll samples k0 + u * stride of one ray: all addresses first, then all
+// LDS reads, then the tests, so the reads are in flight together. Returns the
+// smallest hitting k <= M, or kNoHit. Samples past M stay inside the slot
+// (clamped to the ring) and are never reported.
+template <bool UNIT>
+__device__ __forceinline__ int sample_block(const Slot& m, float x, float y, float ux, float uy,
+                                            float ds, int M, int k0, int stride) {
+  int idx[kUnroll], bit[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const float tk = sample_t<UNIT>(k0 + u * stride, ds);
+    const float px = x + tk * ux;
+    const float py = y + tk * uy;
+    idx[u] = m.word_of(cvt_flr(px), cvt_flr(py), bit[u]);
+  }
+  uint32_t wv[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) wv[u] = m.w1[idx[u]];
+  int kh = kNoHit;
+#pragma unroll
+  for (int u = kUnroll - 1; u >= 0; --u) {
+    const int k = k0 + u * stride;
+    if (__builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) != 0u && k <= M) kh = k;
+  }
+  return kh;
+}
+
+// First hit of one ray marched by one lane. Returns -1 when no sample up to M hits.
+template <bool UNIT>
+__device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float ux, float uy,
+                                          float ds, int M) {
+  for (int k0 = 0; k0 <= M; k0 += kUnroll) {
+    const int kh = sample_block<UNIT>(m, x, y, ux, uy, ds, M, k0, 1);
+    if (kh != kNoHit) return kh;
+  }
+  return -1;
+}
+
+// P lanes per ray (P = L / Lr, a power of two): in iteration `it` lane
+// `phase` tests samples it*P*U + u*P + phase; the lanes of the ray then take
+// the minimum hit, so the ray stops at the first iteration with any hit.
+template <bool UNIT>
+__device__ __forceinline__ int march_split(const Slot& m, float x, float y, float ux, float uy,
+                                           float ds, int M, int P, int phase, int Lr, int L) {
+  const int span = P * kUnroll;
+  for (int it = 0;; ++it) {
+    int kl = sample_block<UNIT>(m, x, y, ux, uy, ds, M, it * span + phase, P);
+    for (int s = Lr; s < L; s <<= 1) kl = min(kl, __shfl_xor(kl, s));
+    if (kl != kNoHit) return kl;
+    if (it * span + span - 1 >= M) return -1;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Observation of one env: rays (march + noise), velocities, target.
+// ------------------------------------------------------------------------
+template <int L>
+__device__ void observe(const Params& p, const Lanes<L>& ln, const Slot& m, const Env& e,
+                        int i, uint32_t g, uint32_t purpose, float inv_dn, float* dst, float* dst2,
+                        int16_t* hk, uint16_t* dst_bf16) {
+  float s, c;
+  sincos_f32(e.phi, s, c);
+  const float fx = -c, fy = -s;  // heading: direction of motion in Eq. (6)
+  const int nr = p.n_rays;
+  int R2 = 1;
+  while (R2 < nr) R2 <<= 1;
+  const int P = L >= R2 ? L / R2 : 1;   // lanes per ray
+  const int Lr = L >= R2 ? R2 : L;      // rays handled side by side
+  const int RPL = L >= R2 ? 1 : R2 / L; // rays per lane
+  const int j0 = ln.q % Lr, phase = ln.q / Lr;
+  for (int rr = 0; rr < RPL; ++rr) {
+    const int j = j0 + rr * Lr;
+    const bool valid = j < nr;
+    float ux = 0.0f, uy = 0.0f;
+    if (valid) {
+      const float2 cs = p.rays[j];
+      ux = fx * cs.x - fy * cs.y;
+      uy = fy * cs.x + fx * cs.y;
+    }
+    int kh = -1;
+    if (valid) {
+      const bool unit = p.ds == 1.0f;
+      if (P == 1)
+        kh = unit ? march_lane<true>(m, e.x, e.y, ux, uy, p.ds, p.M)
+                  : march_lane<false>(m, e.x, e.y, ux, uy, p.ds, p.M);
+      else
+        kh = unit ? march_split<true>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L)
+                  : march_split<false>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L);
+    }
+    if (valid && phase == 0) {
+      const float d = kh < 0 ? p.range : (float)kh * p.ds;
+      const U4 w = philox((uint32_t)i, g, purpose, (uint32_t)j, p.key0, p.key1);
+      const float u1 = (float)((w.x >> 8) + 1u) * kTwoM24;
+      const float u2 = (float)(w.y >> 8) * kTwoM24;
+      const float z = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+      float dn = d + e.sigma * z;
+      dn = fminf(fmaxf(dn, 0.0f), p.range);
+      const float o = dn * p.inv_R;
+      if (dst) dst[j] = o;
+      if (dst2) dst2[j] = o;
+      if (dst_bf16) dst_bf16[j] = bf16_rne(o);
+      if (hk) hk[j] = (int16_t)kh;
+    }
+  }
+  if (ln.q == 0) {
+    const float dx = e.tx - e.x, dy = e.ty - e.y;
+    const float d2 = dx * dx + dy * dy;
+    const float bx = dx * fx + dy * fy;
+    const float by = dy * fx - dx * fy;
+    float o[4];
+    o[0] = e.vl / e.vmax;
+    o[1] = e.va / p.omega_max;
+    o[2] = sqrtf(d2) * inv_dn;
+    o[3] = atan2f(by, bx) * kInvPiF;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (dst) dst[nr + a] = o[a];
+      if (dst2) dst2[nr + a] = o[a];
+      if (dst_bf16) dst_bf16[nr + a] = bf16_rne(o[a]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// AutoReset of one env (Sec. 3.2.5) with per-episode randomisation (Sec.
+// 3.2.4): physics draws, then start and target as the first collision-free
+// candidate cell centre in counter order; the env's lanes test candidates
+// side by side and a ballot takes the lowest accepted one.
+// Returns false when no candidate was accepted.
+// ------------------------------------------------------------------------
+template <int L>
+__device__ bool reset_env(const Params& p, const Lanes<L>& ln, const Slot& m, Env& e, int i,
+                          uint32_t g) {
+  const U4 a = philox((uint32_t)i, g, kResetDR, 0u, p.key0, p.key1);
+  const U4 b = philox((uint32_t)i, g, kResetDR, 1u, p.key0, p.key1);
+  e.dt = p.dt_lo + p.dt_span * unit24(a.x);
+  e.K = p.K_lo + p.K_span * unit24(a.y);
+  e.mu = p.mu_lo + p.mu_span * unit24(a.z);
+  e.vmax = p.vmax_lo + p.vmax_span * unit24(a.w);
+  e.sigma = p.sigma_lo + p.sigma_span * unit24(b.x);
+  e.delay = p.delay_lo + scale_u32(b.y, (uint32_t)(p.delay_hi - p.delay_lo + 1));
+  e.phi = unit24(b.z) * kTwoPiF - kPiF;
+  const uint32_t W = (uint32_t)m.W, H = (uint32_t)m.H;
+  const float ra2 = p.arrive_r * p.arrive_r;
+  bool ok = true;
+  float pos[2][2];
+#pragma unroll
+  for (int which = 0; which < 2; ++which) {
+    const uint32_t purpose = which == 0 ? kResetStart : kResetTarget;
+    const U4 w0 = philox((uint32_t)i, g, purpose, 0u, p.key0, p.key1);
+    float bx = (float)scale_u32(w0.x, W) + 0.5f, by = (float)scale_u32(w0.y, H) + 0.5f;
+    bool found = false;
+    for (int n0 = 0; n0 < 16 * 64 && !found; n0 += L) {
+      const uint32_t n = (uint32_t)(n0 + ln.q);
+      const U4 w = philox((uint32_t)i, g, purpose, n, p.key0, p.key1);
+      const float px = (float)scale_u32(w.x, W) + 0.5f;
+      const float py = (float)scale_u32(w.y, H) + 0.5f;
+      bool acc = !collides_seq(m, px, py, p.robot_r);
+      if (which == 1) {
+        const float dx = px - pos[0][0], dy = py - pos[0][1];
+        const float d2 = dx * dx + dy * dy;
+        acc = acc && d2 > ra2;
+      }
+      const uint64_t bal = ln.ballot(acc);
+      if (bal) {
+        const int src = __builtin_ctzll(bal);
+        bx = __shfl(px, src);
+        by = __shfl(py, src);
+        found = true;
+      }
+    }
+    ok = ok && found;
+    pos[which][0] = bx;
+    pos[which][1] = by;
+  }
+  e.x = pos[0][0]; e.y = pos[0][1]; e.tx = pos[1][0]; e.ty = pos[1][1];
+  e.vl = 0.0f; e.va = 0.0f; e.t = 0; e.q0 = kStop; e.q1 = kStop;
+  const float dx = e.tx - e.x, dy = e.ty - e.y;
+  e.dprev = sqrtf(dx * dx + dy * dy);
+  return ok;
+}
+
+// ------------------------------------------------------------------------
+// One step of one env (Alg. 1 step 4). Writes reward/done/flags through the
+// lane with q == 0. Returns the done flag.
+// ------------------------------------------------------------------------
+struct StepOut {
+  float reward;
+  uint8_t done, flags;
+};
+
+template <int L>
+__device__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m, Env& e,
+                            int a_hat) {
+  if (a_hat < 0 || a_hat >= kNumActions) a_hat = kStop;
+  int a;
+  if (e.delay == 0) {
+    a = a_hat;
+  } else if (e.delay == 1) {
+    a = e.q0;
+    e.q0 = a_hat;
+  } else {
+    a = e.q0;
+    e.q0 = e.q1;
+    e.q1 = a_hat;
+  }
+  float cl = 0.0f, ca = 0.0f;
+  if (a != kStop) {
+    cl = e.mu * (kActV[a] * e.vmax);
+    ca = e.mu * (kActW[a] * p.omega_max);
+  }
+  // Eq. (5)
+  const float omk = 1.0f - e.K;
+  float vl = e.K * e.vl + omk * cl;
+  float va = e.K * e.va + omk * ca;
+  vl = fminf(fmaxf(vl, -e.vmax), e.vmax);
+  va = fminf(fmaxf(va, -p.omega_max), p.omega_max);
+  // Eq. (6): new velocity, old heading
+  float s, c;
+  sincos_f32(e.phi, s, c);
+  e.x = e.x - e.dt * (vl * c);
+  e.y = e.y - e.dt * (vl * s);
+  float phi = e.phi + e.dt * va;
+  if (phi > kPiF) phi -= kTwoPiF;
+  else if (phi <= -kPiF) phi += kTwoPiF;
+  e.phi = phi;
+  e.vl = vl;
+  e.va = va;
+  e.t += 1;
+  // collision, arrival, reward (Sec. 4.3.1)
+  const bool coll = collides_env<L>(ln, m, e.x, e.y, p.robot_r);
+  const float dx = e.tx - e.x, dy = e.ty - e.y;
+  const float d2 = dx * dx + dy * dy;
+  const bool arrived = d2 <= p.arrive_r * p.arrive_r;
+  bool term = false;
+  float r;
+  if (coll) {
+    r = -10.0f;
+    term = true;
+  } else if (arrived) {
+    r = 10.0f;
+    term = true;
+  } else {
+    const float dist = sqrtf(d2);
+    r = (e.dprev - dist) - 0.01f;
+    e.dprev = dist;
+  }
+  const bool trunc = !term && e.t >= p.t_max;
+  StepOut o;
+  o.reward = r;
+  o.done = (uint8_t)(term || trunc);
+  o.flags = (uint8_t)((term ? 1 : 0) | (trunc ? 2 : 0) | (coll ? 4 : 0) |
+                      (arrived && !coll ? 8 : 0));
+  return o;
+}
+
+}  // namespace sp

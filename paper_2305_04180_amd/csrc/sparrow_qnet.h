@@ -1,0 +1,226 @@
+// sparrow_qnet.h -- the actor: Q-network forward in BF16 on MFMA (FP32
+// accumulation) and vectorized epsilon-greedy exploration (VEM).
+//
+// The Q-network is the fully connected ReLU stack of Sec. 4.3.2 mapping the
+// state to one value per discrete action; the actor takes its greedy action
+// and VEM (Sec. 3.1.1) replaces it by a uniform random action with the env's
+// own probability eps_i (Alg. 1 steps 2-3).
+//
+// Layout. Eight waves serve 16 rows (envs) at a time. Each wave keeps its
+// slice of the weights resident in VGPRs for the whole kernel (weight-
+// stationary): layer 1 and layer 2 are split by output tiles of 16 hidden
+// units, layer 3 by 32-wide K steps whose partial sums meet in LDS. One MFMA
+// v_mfma_f32_16x16x32_bf16 computes D[h][env] += W[h][k] * X[env][k] over a
+// 16 x 16 x 32 block: A = weight rows, B = activation rows from LDS, D rows =
+// hidden units, D columns = envs. Activations live in LDS as bf16 rows [env][k]
+// padded by 16 bytes against bank conflicts; between layers they are rounded
+// to bf16 (RNE) after bias and ReLU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sparrow_device.h"
+
+namespace sp {
+
+constexpr int kQThreads = 512;  // eight waves
+constexpr int kQWaves = 8;
+constexpr int kQRows = 16;      // envs per MLP pass (MFMA N)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct QParams {
+  const uint16_t* w1;  // [h1][d0p] bf16, zero-padded columns
+  const uint16_t* w2;  // [h2][h1]
+  const uint16_t* w3;  // [16][h2], rows >= 7 zero
+  const float* b1;     // [h1]
+  const float* b2;     // [h2]
+  const float* b3;     // [16], entries >= 7 zero
+  int32_t d0, d0p, h1, h2;
+  int32_t lds_base_words;  // first LDS word of the actor's buffers
+};
+
+// LDS: region A holds the bf16 input rows and, later in the same pass, the
+// second hidden layer; region B holds the first hidden layer and then the
+// layer-3 partial sums.
+__host__ __device__ inline int qnet_stride0(const QParams& q) { return q.d0p + 8; }
+__host__ __device__ inline int qnet_stride1(const QParams& q) { return q.h1 + 8; }
+__host__ __device__ inline int qnet_stride2(const QParams& q) { return q.h2 + 8; }
+__host__ __device__ inline int qnet_region_a_bytes(const QParams& q) {
+  const int a0 = kQRows * qnet_stride0(q) * 2, a2 = kQRows * qnet_stride2(q) * 2;
+  return ((a0 > a2 ? a0 : a2) + 15) & ~15;
+}
+__host__ __device__ inline int qnet_region_b_bytes(const QParams& q) {
+  const int b1 = kQRows * qnet_stride1(q) * 2, bp = kQWaves * kQRows * 16 * 4;
+  return ((b1 > bp ? b1 : bp) + 15) & ~15;
+}
+inline size_t qnet_lds_bytes(const QParams& q) {
+  return (size_t)qnet_region_a_bytes(q) + (size_t)qnet_region_b_bytes(q);
+}
+
+__device__ __forceinline__ uint16_t* qnet_region_a(const QParams& q, uint32_t* lds) {
+  return reinterpret_cast<uint16_t*>(lds + q.lds_base_words);
+}
+__device__ __forceinline__ uint16_t* qnet_region_b(const QParams& q, uint32_t* lds) {
+  return reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds + q.lds_base_words) +
+                                     qnet_region_a_bytes(q));
+}
+__device__ __forceinline__ uint16_t* qnet_input_row(const QParams& q, uint32_t* lds, int row) {
+  return qnet_region_a(q, lds) + row * qnet_stride0(q);
+}
+
+// Weights resident in the VGPRs of one wave. D0P, H1, H2 fixed at compile time.
+template <int D0P, int H1, int H2>
+struct QNetCfg {
+  static constexpr bool kOn = true;
+  static constexpr int T1 = H1 / 16 / kQWaves;  // output tiles of layer 1 per wave
+  static constexpr int K1 = D0P / 32;
+  static constexpr int T2 = H2 / 16 / kQWaves;
+  static constexpr int K2 = H1 / 32;
+  static constexpr int K3 = H2 / 32 / kQWaves;  // layer-3 K steps per wave
+  static_assert(T1 >= 1 && T2 >= 1 && K3 >= 1, "hidden sizes must be multiples of 256");
+  static_assert(H1 % (16 * kQWaves) == 0 && H2 % (32 * kQWaves) == 0, "unsupported sizes");
+
+  struct Weights {
+    bf16x8 a1[T1][K1];
+    bf16x8 a2[T2][K2];
+    bf16x8 a3[K3];
+    f32x4 bias1[T1];
+    f32x4 bias2[T2];
+
+    __device__ __forceinline__ void load(const QParams& q, int tid) {
+      const int w = tid >> 6, l = tid & 63;
+      const int r = l & 15, kq = (l >> 4) * 8;
+#pragma unroll
+      for (int t = 0; t < T1; ++t) {
+        const int h = (w * T1 + t) * 16 + r;
+#pragma unroll
+        for (int ks = 0; ks < K1; ++ks)
+          a1[t][ks] = *reinterpret_cast<const bf16x8*>(q.w1 + (size_t)h * D0P + ks * 32 + kq);
+        const int hb = (w * T1 + t) * 16 + (l >> 4) * 4;
+        bias1[t] = f32x4{q.b1[hb], q.b1[hb + 1], q.b1[hb + 2], q.b1[hb + 3]};
+      }
+#pragma unroll
+      for (int t = 0; t < T2; ++t) {
+        const int h = (w * T2 + t) * 16 + r;
+#pragma unroll
+        for (int ks = 0; ks < K2; ++ks)
+          a2[t][ks] = *reinterpret_cast<const bf16x8*>(q.w2 + (size_t)h * H1 + ks * 32 + kq);
+        const int hb = (w * T2 + t) * 16 + (l >> 4) * 4;
+        bias2[t] = f32x4{q.b2[hb], q.b2[hb + 1], q.b2[hb + 2], q.b2[hb + 3]};
+      }
+#pragma unroll
+      for (int ks = 0; ks < K3; ++ks)
+        a3[ks] = *reinterpret_cast<const bf16x8*>(q.w3 + (size_t)r * H2 + (w * K3 + ks) * 32 + kq);
+    }
+  };
+};
+
+struct NoQ {
+  static constexpr bool kOn = false;
+  struct Weights {
+    __device__ __forceinline__ void load(const QParams&, int) {}
+  };
+};
+
+__device__ __forceinline__ f32x4 mfma16x16x32(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t pack_relu_bf16x2(float lo, float hi) {
+  lo = fmaxf(lo, 0.0f);
+  hi = fmaxf(hi, 0.0f);
+  return (uint32_t)bf16_rne(lo) | ((uint32_t)bf16_rne(hi) << 16);
+}
+
+// One dense layer for this wave's output tiles: out[env][h] = relu(W x + b).
+template <int T, int KS>
+__device__ __forceinline__ void qnet_layer(const bf16x8 (&a)[T][KS], const f32x4 (&bias)[T],
+                                           const uint16_t* in, int in_stride, uint16_t* out,
+                                           int out_stride, int tile0, int l) {
+  const int env = l & 15, kq = (l >> 4) * 8, hq = (l >> 4) * 4;
+  bf16x8 b[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+    b[ks] = *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq);
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acc = mfma16x16x32(a[t][ks], b[ks], acc);
+    acc += bias[t];
+    uint2 v;
+    v.x = pack_relu_bf16x2(acc[0], acc[1]);
+    v.y = pack_relu_bf16x2(acc[2], acc[3]);
+    *reinterpret_cast<uint2*>(out + env * out_stride + (tile0 + t) * 16 + hq) = v;
+  }
+}
+
+// Forward pass over the 16 input rows in LDS region A. Ends with a barrier
+// after which the layer-3 partial sums are in region B.
+template <class QC>
+__device__ __forceinline__ void qnet_forward_group(const QParams& q,
+                                                   const typename QC::Weights& W,
+                                                   uint32_t* lds, int tid) {
+  if constexpr (QC::kOn) {
+    const int w = tid >> 6, l = tid & 63;
+    uint16_t* ra = qnet_region_a(q, lds);
+    uint16_t* rb = qnet_region_b(q, lds);
+    __syncthreads();  // input rows complete
+    qnet_layer<QC::T1, QC::K1>(W.a1, W.bias1, ra, qnet_stride0(q), rb, qnet_stride1(q),
+                               w * QC::T1, l);
+    __syncthreads();
+    qnet_layer<QC::T2, QC::K2>(W.a2, W.bias2, rb, qnet_stride1(q), ra, qnet_stride2(q),
+                               w * QC::T2, l);
+    __syncthreads();
+    {
+      const int env = l & 15, kq = (l >> 4) * 8;
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < QC::K3; ++ks) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(ra + env * qnet_stride2(q) +
+                                                          (w * QC::K3 + ks) * 32 + kq);
+        acc = mfma16x16x32(W.a3[ks], b, acc);
+      }
+      // partial[w][env][action], actions 4*(l/16) .. +3
+      float* part = reinterpret_cast<float*>(rb);
+      *reinterpret_cast<f32x4*>(part + (w * kQRows + env) * 16 + (l >> 4) * 4) = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Q values of row `row` (bias + partial sums in a fixed order); returns the
+// lowest index of the maximum.
+__device__ __forceinline__ int qnet_q_values(const QParams& q, uint32_t* lds, int row,
+                                             float (&qa)[kNumActions]) {
+  const float* part = reinterpret_cast<const float*>(qnet_region_b(q, lds));
+  int best = 0;
+#pragma unroll
+  for (int a = 0; a < kNumActions; ++a) {
+    float v = q.b3[a];
+#pragma unroll
+    for (int w = 0; w < kQWaves; ++w) v += part[(w * kQRows + row) * 16 + a];
+    qa[a] = v;
+    if (v > qa[best]) best = a;
+  }
+  return best;
+}
+
+// VEM (Sec. 3.1.1): with probability eps the greedy action is replaced by a
+// uniform random one; the draw is Philox (env, step, EXPLORE, 0).
+__device__ __forceinline__ int vem_select(int greedy, int env, uint32_t g, float eps,
+                                          uint32_t key0, uint32_t key1) {
+  const U4 w = philox((uint32_t)env, g, kExplore, 0u, key0, key1);
+  return unit24(w.x) < eps ? scale_u32(w.y, kNumActions) : greedy;
+}
+
+__device__ __forceinline__ int qnet_vem_action(const QParams& q, uint32_t* lds, int row, int env,
+                                               uint32_t g, float eps, uint32_t key0,
+                                               uint32_t key1) {
+  float qa[kNumActions];
+  return vem_select(qnet_q_values(q, lds, row, qa), env, g, eps, key0, key1);
+}
+
+}  // namespace sp

@@ -1,0 +1,264 @@
+"""ctypes binding of libsparrow.so (the C-ABI in include/sparrow.h).
+
+Argument marshalling only: every step of the simulation runs in the library's
+HIP kernels. torch provides device memory and the stream; buffers are passed
+as raw device pointers. There is no CPU fallback: without the built library
+on a gfx950 device the constructor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsparrow.so")
+
+OK, EINVAL, ENOMEM, EHIP, ERESET, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+FLAG_TERMINATED, FLAG_TRUNCATED, FLAG_COLLISION, FLAG_ARRIVAL = 1, 2, 4, 8
+N_ACTIONS = 7
+STATE_F = ("x", "y", "phi", "vl", "va", "tx", "ty", "dprev", "dt", "K", "mu", "vmax", "sigma")
+STATE_I = ("t", "delay", "q0", "q1")
+
+EXPORTS = (
+    "sparrow_create", "sparrow_reset", "sparrow_step", "sparrow_random_actions",
+    "sparrow_set_qnet", "sparrow_qnet_forward", "sparrow_act", "sparrow_rollout",
+    "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
+    "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
+    "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
+)
+
+
+class SparrowError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sparrow error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n_envs", C.c_int32), ("n_rays", C.c_int32), ("n_actions", C.c_int32),
+        ("fov_rad", C.c_float), ("range_cells", C.c_float), ("march_step", C.c_float),
+        ("robot_radius", C.c_float), ("arrive_radius", C.c_float), ("timeout_steps", C.c_int32),
+        ("dt_lo", C.c_float), ("dt_hi", C.c_float), ("K_lo", C.c_float), ("K_hi", C.c_float),
+        ("mu_lo", C.c_float), ("mu_hi", C.c_float), ("vmax_lo", C.c_float),
+        ("vmax_hi", C.c_float), ("omega_max", C.c_float), ("sigma_lo", C.c_float),
+        ("sigma_hi", C.c_float), ("delay_lo", C.c_int32), ("delay_hi", C.c_int32),
+        ("seed", C.c_uint64),
+    ]
+
+
+class MapsStruct(C.Structure):
+    _fields_ = [("n_maps", C.c_int32), ("cells", C.c_void_p), ("offsets", C.c_void_p),
+                ("width", C.c_void_p), ("height", C.c_void_p), ("env_to_map", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+        L = C.CDLL(path)
+        P, I32, U32 = C.c_void_p, C.c_int32, C.c_uint32
+        sig = {
+            "sparrow_create": (I32, [C.POINTER(Config), C.POINTER(MapsStruct), P, C.POINTER(P)]),
+            "sparrow_reset": (I32, [P, P]),
+            "sparrow_step": (I32, [P, P, P, P, P, P, P]),
+            "sparrow_random_actions": (I32, [P, P]),
+            "sparrow_set_qnet": (I32, [P, P, P, P, P]),
+            "sparrow_qnet_forward": (I32, [P, P, I32, P, P]),
+            "sparrow_act": (I32, [P, P, P]),
+            "sparrow_rollout": (I32, [P, I32, I32, P, P, P, P]),
+            "sparrow_debug_hits": (I32, [P, P]),
+            "sparrow_get_state": (I32, [P, P, P]),
+            "sparrow_set_state": (I32, [P, P, P]),
+            "sparrow_global_step": (U32, [P]),
+            "sparrow_set_global_step": (None, [P, U32]),
+            "sparrow_set_variant": (I32, [P, I32, I32, I32]),
+            "sparrow_get_variant": (I32, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
+            "sparrow_autotune": (I32, [P, I32, C.c_char_p, I32]),
+            "sparrow_status": (I32, [P]),
+            "sparrow_destroy": (None, [P]),
+            "sparrow_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise SparrowError(rc, lib().sparrow_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_config(cfg: dict) -> Config:
+    c = Config()
+    c.n_envs, c.n_rays, c.n_actions = cfg["n_envs"], cfg["n_rays"], N_ACTIONS
+    c.fov_rad, c.range_cells, c.march_step = cfg["fov"], cfg["range"], cfg["ds"]
+    c.robot_radius, c.arrive_radius, c.timeout_steps = cfg["robot_r"], cfg["arrive_r"], cfg["t_max"]
+    for f in ("dt_lo", "dt_hi", "K_lo", "K_hi", "mu_lo", "mu_hi", "vmax_lo", "vmax_hi",
+              "omega_max", "sigma_lo", "sigma_hi"):
+        setattr(c, f, float(cfg[f]))
+    c.delay_lo, c.delay_hi, c.seed = cfg["delay_lo"], cfg["delay_hi"], cfg["seed"]
+    return c
+
+
+class Env:
+    """N Sparrow environments on the current HIP device and torch stream."""
+
+    def __init__(self, cfg: dict, maps, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = dict(cfg)
+        self.n = cfg["n_envs"]
+        self.n_rays = cfg["n_rays"]
+        self.obs_dim = self.n_rays + 4
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cells, offsets, width, height, env_to_map = maps.flat()
+        self._keep = (cells, offsets, width, height, env_to_map)
+        ms = MapsStruct(len(width), cells.ctypes.data, offsets.ctypes.data, width.ctypes.data,
+                        height.ctypes.data, env_to_map.ctypes.data)
+        self._c = make_config(cfg)
+        h = C.c_void_p()
+        _check(lib().sparrow_create(C.byref(self._c), C.byref(ms),
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        f32, u8, i32 = torch.float32, torch.uint8, torch.int32
+        dev = self.device
+        self.obs = torch.zeros(self.n, self.obs_dim, dtype=f32, device=dev)
+        self.reward = torch.zeros(self.n, dtype=f32, device=dev)
+        self.done = torch.zeros(self.n, dtype=u8, device=dev)
+        self.flags = torch.zeros(self.n, dtype=u8, device=dev)
+        self.actions = torch.zeros(self.n, dtype=i32, device=dev)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sparrow_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- RL-API ---------------------------------------------------------------
+    def reset(self, obs=None):
+        obs = self.obs if obs is None else obs
+        _check(lib().sparrow_reset(self._h, _ptr(obs)))
+        return obs
+
+    def step(self, actions, obs=None, reward=None, done=None, flags=None, final_obs=None):
+        obs = self.obs if obs is None else obs
+        reward = self.reward if reward is None else reward
+        done = self.done if done is None else done
+        _check(lib().sparrow_step(self._h, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done),
+                                  _ptr(flags), _ptr(final_obs)))
+        return obs, reward, done
+
+    def random_actions(self, out=None):
+        out = self.actions if out is None else out
+        _check(lib().sparrow_random_actions(self._h, _ptr(out)))
+        return out
+
+    # -- actor ----------------------------------------------------------------
+    def set_qnet(self, dims, w_bf16, b_f32, eps):
+        torch = self.torch
+        d = (C.c_int32 * 4)(*[int(x) for x in dims])
+        w = torch.as_tensor(np.asarray(w_bf16).view(np.int16)).to(self.device)
+        b = torch.as_tensor(np.asarray(b_f32, np.float32)).to(self.device)
+        e = torch.as_tensor(np.asarray(eps, np.float32)).to(self.device)
+        _check(lib().sparrow_set_qnet(self._h, d, _ptr(w), _ptr(b), _ptr(e)))
+        self._qkeep = (w, b, e)
+
+    def qnet_forward(self, obs, q=None, greedy=None):
+        torch = self.torch
+        n = obs.shape[0]
+        q = torch.zeros(n, N_ACTIONS, dtype=torch.float32, device=self.device) if q is None else q
+        greedy = torch.zeros(n, dtype=torch.int32, device=self.device) if greedy is None else greedy
+        _check(lib().sparrow_qnet_forward(self._h, _ptr(obs), n, _ptr(q), _ptr(greedy)))
+        return q, greedy
+
+    def act(self, obs, actions=None):
+        actions = self.actions if actions is None else actions
+        _check(lib().sparrow_act(self._h, _ptr(obs), _ptr(actions)))
+        return actions
+
+    def rollout(self, K, use_qnet, actions=None, reward=None, done=None, obs=None):
+        torch = self.torch
+        dev = self.device
+        actions = torch.zeros(K, self.n, dtype=torch.int32, device=dev) if actions is None else actions
+        reward = torch.zeros(K, self.n, dtype=torch.float32, device=dev) if reward is None else reward
+        done = torch.zeros(K, self.n, dtype=torch.uint8, device=dev) if done is None else done
+        obs = self.obs if obs is None else obs
+        _check(lib().sparrow_rollout(self._h, K, int(bool(use_qnet)), _ptr(actions),
+                                     _ptr(reward), _ptr(done), _ptr(obs)))
+        return actions, reward, done, obs
+
+    # -- inspection -----------------------------------------------------------
+    def debug_hits(self):
+        t = self.torch.zeros(self.n, self.n_rays, dtype=self.torch.int16, device=self.device)
+        _check(lib().sparrow_debug_hits(self._h, _ptr(t)))
+        return t
+
+    def get_state(self):
+        f = np.zeros((self.n, len(STATE_F)), np.float32)
+        i = np.zeros((self.n, len(STATE_I)), np.int32)
+        _check(lib().sparrow_get_state(self._h, f.ctypes.data, i.ctypes.data))
+        return f, i
+
+    def set_state(self, f, i):
+        f = np.ascontiguousarray(f, np.float32)
+        i = np.ascontiguousarray(i, np.int32)
+        _check(lib().sparrow_set_state(self._h, f.ctypes.data, i.ctypes.data))
+
+    @property
+    def global_step(self):
+        return int(lib().sparrow_global_step(self._h))
+
+    @global_step.setter
+    def global_step(self, g):
+        lib().sparrow_set_global_step(self._h, int(g))
+
+    def set_variant(self, kernel, envs_per_group, lanes_per_env):
+        _check(lib().sparrow_set_variant(self._h, kernel, envs_per_group, lanes_per_env))
+
+    def get_variant(self, kernel):
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().sparrow_get_variant(self._h, kernel, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, steps=8):
+        buf = C.create_string_buffer(1 << 16)
+        _check(lib().sparrow_autotune(self._h, steps, buf, len(buf)))
+        return json.loads(buf.value.decode() or "{}")
+
+    def status(self):
+        return lib().sparrow_status(self._h)
+
+
+def vem_epsilon(n: int, m: int, e_min: float, e_max: float) -> np.ndarray:
+    """Per-env exploration probabilities of VEM (Sec. 3.1.1): the exploiting
+    interval holds e_min; the last m envs (the exploring interval) rise
+    linearly from e_min to e_min + e_max."""
+    eps = np.full(n, e_min, np.float64)
+    if m > 0:
+        j = np.arange(m, dtype=np.float64)
+        frac = j / (m - 1) if m > 1 else np.ones(1)
+        eps[n - m:] = e_min + e_max * frac
+    return eps.astype(np.float32)

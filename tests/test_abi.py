@@ -1,0 +1,115 @@
+"""The C-ABI library loads and exports every symbol its header declares, and
+rejects invalid arguments before touching a device (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_04180_amd import inputs, sparrow
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sparrow.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sparrow_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sparrow.LIB_PATH):
+        pytest.skip("libsparrow.so not built")
+    return sparrow.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 18
+    raw = C.CDLL(sparrow.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(sparrow.EXPORTS)
+
+
+def _create(cfg, maps):
+    c = sparrow.make_config(cfg)
+    cells, offsets, width, height, env_to_map = maps.flat()
+    ms = sparrow.MapsStruct(len(width), cells.ctypes.data, offsets.ctypes.data,
+                            width.ctypes.data, height.ctypes.data, env_to_map.ctypes.data)
+    h = C.c_void_p()
+    rc = sparrow.lib().sparrow_create(C.byref(c), C.byref(ms), None, C.byref(h))
+    keep = (cells, offsets, width, height, env_to_map)
+    return rc, h, keep
+
+
+@pytest.mark.parametrize("change", [
+    dict(n_envs=0), dict(n_rays=0), dict(n_rays=129), dict(range=0.0), dict(ds=0.0),
+    dict(robot_r=0.0), dict(robot_r=9.0), dict(t_max=0), dict(delay_hi=3),
+    dict(delay_lo=2, delay_hi=1), dict(vmax_lo=0.0), dict(sigma_lo=-1.0),
+    dict(dt_lo=0.3, dt_hi=0.2),
+])
+def test_invalid_config_is_einval(lib, change):
+    cfg = inputs.workload("c1", n_envs=2)
+    cfg.update(change)
+    maps = inputs.single_maps([np.zeros((16, 16), np.uint8)], n_envs=max(cfg["n_envs"], 1))
+    rc, h, _ = _create(cfg, maps)
+    assert rc == sparrow.EINVAL, (change, rc)
+    assert not h.value
+    assert lib.sparrow_last_error()
+
+
+def test_bad_maps_are_einval(lib):
+    cfg = inputs.workload("c1", n_envs=2)
+    big = inputs.single_maps([np.zeros((513, 16), np.uint8)], n_envs=2)
+    assert _create(cfg, big)[0] == sparrow.EINVAL
+    badmap = inputs.single_maps([np.zeros((16, 16), np.uint8)], env_to_map=[0, 1])
+    assert _create(cfg, badmap)[0] == sparrow.EINVAL
+    h = C.c_void_p()
+    assert lib.sparrow_create(None, None, None, C.byref(h)) == sparrow.EINVAL
+
+
+def test_null_handle_calls_are_einval(lib):
+    assert lib.sparrow_reset(None, None) == sparrow.EINVAL
+    assert lib.sparrow_step(None, None, None, None, None, None, None) == sparrow.EINVAL
+    assert lib.sparrow_rollout(None, 4, 0, None, None, None, None) == sparrow.EINVAL
+    assert lib.sparrow_status(None) == sparrow.EINVAL
+    assert lib.sparrow_set_variant(None, 0, 8, 32) == sparrow.EINVAL
+    lib.sparrow_destroy(None)
+
+
+def test_valid_config_without_gpu_fails_cleanly(lib):
+    """On a host without a gfx950 device, create reports EHIP or EUNSUPPORTED."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = inputs.workload("c1", n_envs=2)
+    maps = inputs.single_maps([np.zeros((16, 16), np.uint8)], n_envs=2)
+    rc, h, _ = _create(cfg, maps)
+    assert rc in (sparrow.EHIP, sparrow.EUNSUPPORTED)
+    assert not h.value
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import importlib
+    mod = importlib.reload(sparrow)
+    saved = mod._lib
+    try:
+        mod._lib = None
+        with pytest.raises(RuntimeError):
+            mod.lib(str(tmp_path / "missing.so"))
+    finally:
+        mod._lib = saved
+
+
+def test_vem_epsilon_binding_matches_schedule():
+    import oracle
+    for n, m in ((8192, 8192), (16, 3), (10, 1), (5, 0)):
+        a = sparrow.vem_epsilon(n, m, 0.01, 0.29)
+        b = oracle.vem_epsilon(n, m, 0.01, 0.29)
+        assert np.array_equal(a, b), (n, m)

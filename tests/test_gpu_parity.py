@@ -1,0 +1,314 @@
+"""GPU parity: the HIP library (through its C-ABI) against the CPU oracle.
+
+Every case prints its name, sizes and seed before touching the GPU.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2305_04180_amd import inputs
+from tests.parity_util import compare_exact, compare_obs, compare_state, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def make(cfg, maps, torch_gpu):
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    env = sparrow.Env(cfg, maps)
+    orc = oracle.Oracle(cfg, maps)
+    return env, orc
+
+
+def run_steps(env, orc, steps, torch_gpu, noisy, final_obs=True, check_state_every=1,
+              actions_fn=None, where=""):
+    torch = torch_gpu
+    n, nr, D = env.n, env.n_rays, env.obs_dim
+    fo = torch.zeros(n, D, dtype=torch.float32, device=env.device) if final_obs else None
+    flags = torch.zeros(n, dtype=torch.uint8, device=env.device)
+    total_done = 0
+    for s in range(steps):
+        a_o = orc.uniform_actions() if actions_fn is None else actions_fn(s)
+        a_g = env.random_actions()
+        if actions_fn is None:
+            compare_exact(to_np(a_g), a_o, "uniform actions", f"{where} step {s}")
+        else:
+            a_g.copy_(torch.as_tensor(a_o))
+        if fo is not None:
+            fo.zero_()
+        env.step(a_g, flags=flags, final_obs=fo)
+        r = orc.step(a_o, final_obs=final_obs, hit_k=True)
+        w = f"{where} step {s}"
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", w)
+        compare_exact(to_np(env.done), r["done"], "done", w)
+        compare_exact(to_np(flags), r["flags"], "flags", w)
+        compare_exact(to_np(env.reward), r["reward"], "reward", w)
+        compare_obs(to_np(env.obs), r["obs"], nr, noisy, w)
+        if final_obs:
+            dn = r["done"].astype(bool)
+            if dn.any():
+                compare_obs(to_np(fo)[dn], r["final_obs"][dn], nr, noisy, w + " final_obs")
+        if check_state_every and (s % check_state_every == 0 or s == steps - 1):
+            gf, gi = env.get_state()
+            of, oi = orc.get_state()
+            compare_state(gf, gi, of, oi, w)
+        total_done += int(r["done"].sum())
+    return total_done
+
+
+def test_reset_parity_c1(torch_gpu):
+    cfg = inputs.workload("c1")
+    banner(f"reset c1 N={cfg['n_envs']} seed={cfg['seed']}")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch_gpu)
+    env.reset()
+    o_obs, rc, o_hk = orc.reset(hit_k=True)
+    assert rc == 0 and env.status() == 0
+    compare_exact(to_np(env.debug_hits()), o_hk, "hit_k", "reset")
+    compare_obs(to_np(env.obs), o_obs, env.n_rays, noisy=False, where="reset")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, "reset")
+
+
+def test_step_parity_c1_1000_steps(torch_gpu):
+    """The minimum slice: C1 (N=16, 128^2, 32 rays), 1000 steps, bit-exact."""
+    cfg = inputs.workload("c1")
+    banner(f"step c1 N={cfg['n_envs']} 1000 steps")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch_gpu)
+    env.reset()
+    orc.reset()
+    dones = run_steps(env, orc, 1000, torch_gpu, noisy=False, check_state_every=10, where="c1")
+    assert dones > 50  # episodes end and AutoReset runs
+    assert env.status() == 0
+
+
+@pytest.mark.parametrize("variant", [(1, 16), (2, 32), (4, 32), (8, 64), (4, 16), (8, 32)])
+def test_step_parity_c2_ragged(torch_gpu, variant):
+    """C2 physics (366^2 mixed maps, full randomisation, noise, delay) with a
+    ragged batch of 37 envs, every step kernel variant."""
+    cfg = inputs.workload("c2", n_envs=37)
+    banner(f"step c2 N=37 variant={variant} 150 steps")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch_gpu)
+    env.set_variant(0, *variant)
+    env.reset()
+    orc.reset()
+    run_steps(env, orc, 150, torch_gpu, noisy=True, check_state_every=5, where=f"c2 {variant}")
+
+
+def test_step_parity_uneven_maps_64_rays(torch_gpu):
+    """C3-style uneven map sides with 64 rays and range 128, 29 envs."""
+    cfg = inputs.workload("c3", n_envs=29)
+    banner("step c3-style N=29 uneven sides, 64 rays, 100 steps")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch_gpu)
+    env.reset()
+    orc.reset()
+    run_steps(env, orc, 100, torch_gpu, noisy=True, check_state_every=10, where="c3")
+
+
+def test_rollout_uniform_parity(torch_gpu):
+    """Persistent rollout with uniform actions == the oracle stepped K times."""
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=45)
+    K = 24
+    banner(f"rollout uniform c2 N=45 K={K}")
+    maps = inputs.make_maps(cfg)
+    for variant in [(8, 64), (8, 32), (4, 32), (2, 16)]:
+        env, orc = make(cfg, maps, torch)
+        env.set_variant(1, *variant)
+        env.reset()
+        orc.reset()
+        acts, rew, done, obs = env.rollout(K, use_qnet=False)
+        torch.cuda.synchronize()
+        for t in range(K):
+            a = orc.uniform_actions()
+            r = orc.step(a, hit_k=True)
+            w = f"rollout {variant} t={t}"
+            compare_exact(to_np(acts[t]), a, "actions", w)
+            compare_exact(to_np(rew[t]), r["reward"], "reward", w)
+            compare_exact(to_np(done[t]), r["done"], "done", w)
+        compare_obs(to_np(obs), r["obs"], env.n_rays, True, "rollout final obs")
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", "rollout final")
+        gf, gi = env.get_state()
+        of, oi = orc.get_state()
+        compare_state(gf, gi, of, oi, f"rollout {variant} final")
+        assert env.global_step == orc.global_step
+        # a second rollout replays the cached graph with the new step counter
+        acts2, rew2, done2, obs2 = env.rollout(K, use_qnet=False)
+        torch.cuda.synchronize()
+        for t in range(K):
+            a = orc.uniform_actions()
+            r = orc.step(a)
+            compare_exact(to_np(rew2[t]), r["reward"], "reward", f"replay t={t}")
+            compare_exact(to_np(done2[t]), r["done"], "done", f"replay t={t}")
+        gf, gi = env.get_state()
+        of, oi = orc.get_state()
+        compare_state(gf, gi, of, oi, f"rollout replay {variant}")
+
+
+def test_reset_failure_reports_ereset(torch_gpu):
+    from paper_2305_04180_amd import sparrow
+    cfg = inputs.workload("c1", n_envs=3)
+    banner("reset failure on a full map")
+    g = np.ones((32, 32), np.uint8)
+    maps = inputs.single_maps([g], n_envs=3)
+    env = sparrow.Env(cfg, maps)
+    env.reset()
+    assert env.status() == sparrow.ERESET
+
+
+def _qnet_setup(cfg, env):
+    dims = (env.obs_dim, 256, 256, 7)
+    w, b, _ = inputs.qnet_weights(dims)
+    from paper_2305_04180_amd import sparrow
+    eps = sparrow.vem_epsilon(env.n, env.n, 0.01, 0.29)
+    env.set_qnet(dims, w, b, eps)
+    return dims, w, b, eps
+
+
+def test_qnet_forward_parity(torch_gpu):
+    """BF16 MFMA Q-network vs the FP64 oracle on identical observations."""
+    import oracle
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=64)
+    banner("qnet forward 36-256-256-7 on 2112 observations")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch)
+    dims, w, b, eps = _qnet_setup(cfg, env)
+    rows = [orc.reset()[0]]
+    for _ in range(16):
+        rows.append(orc.step(orc.uniform_actions())["obs"])
+    rng = np.random.default_rng(9)
+    rows.append(rng.uniform(-1.2, 1.2, size=(1024, 36)).astype(np.float32))
+    obs = np.concatenate(rows)
+    obs_t = torch.as_tensor(obs).cuda()
+    q, greedy = env.qnet_forward(obs_t)
+    torch.cuda.synchronize()
+    q = to_np(q).astype(np.float64)
+    greedy = to_np(greedy)
+    q64 = oracle.qnet_f64(dims, w, b, obs, round_act=False)    # FP64 reference
+    # First-order error bound of the kernel's arithmetic (Higham): hidden
+    # activations stored in bf16 (relative u = 2^-9 each) and FP32
+    # accumulation over K terms (gamma_K ~ K 2^-24), propagated with |W|:
+    #   |dQ| <= (u + g) (|W3| a2 + |W3| |W2| a1) + g |W3| a2
+    wf = (w.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    d0, h1, h2 = dims[0], dims[1], dims[2]
+    W1 = wf[:h1 * d0].reshape(h1, d0)
+    W2 = wf[h1 * d0:h1 * d0 + h2 * h1].reshape(h2, h1)
+    W3 = wf[h1 * d0 + h2 * h1:].reshape(7, h2)
+    xb = (np.array([oracle.bf16_rne(float(v)) for v in obs.reshape(-1)], np.uint32) << 16)
+    xb = xb.view(np.float32).reshape(obs.shape).astype(np.float64)
+    a1 = np.maximum(xb @ W1.T + b[:h1], 0)
+    a2 = np.maximum(a1 @ W2.T + b[h1:h1 + h2], 0)
+    u, gam = 2.0 ** -9, 256 * 2.0 ** -24
+    bound = (u + gam) * (a2 @ np.abs(W3).T + (a1 @ np.abs(W2).T) @ np.abs(W3).T) + 1e-6
+    dq = np.abs(q - q64)
+    assert np.all(dq <= bound), (dq.max(), (dq / bound).max())
+    assert np.array_equal(greedy, q.argmax(1))
+    agree = (greedy == q64.argmax(1)).mean()
+    order = np.argsort(-q64, 1)
+    top, second = order[:, 0], order[:, 1]
+    rows_i = np.arange(len(q64))
+    gap = q64[rows_i, top] - q64[rows_i, second]
+    clear = gap > bound[rows_i, top] + bound[rows_i, second]
+    print(f"max|dQ| vs fp64 {dq.max():.2e} (max dQ/bound {(dq / bound).max():.3f}), "
+          f"agreement {agree:.5f}, clear-gap agreement "
+          f"{(greedy[clear] == top[clear]).mean():.5f} ({clear.sum()} of {len(clear)} rows)")
+    assert agree >= 0.995
+    assert np.array_equal(greedy[clear], top[clear])
+    # partial rows and n = 0
+    q5, g5 = env.qnet_forward(obs_t[:5].contiguous())
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(g5), greedy[:5])
+
+
+def test_act_kernel_vem(torch_gpu):
+    """The separate actor kernel = greedy of the GPU Q-network, replaced by
+    the oracle's VEM draw where it explores."""
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=300)
+    banner("actor kernel (qnet + VEM) N=300")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch)
+    dims, w, b, eps = _qnet_setup(cfg, env)
+    env.reset()
+    orc.reset()
+    env.global_step = orc.global_step = 7
+    q, greedy = env.qnet_forward(env.obs)
+    a = env.act(env.obs)
+    torch.cuda.synchronize()
+    qq = np.zeros((300, 7))
+    qq[np.arange(300), to_np(greedy)] = 1.0
+    a_o, ex = orc.vem(qq, eps)
+    compare_exact(to_np(a), a_o, "actions", "act")
+    assert 0 < ex.sum() < 300
+
+
+def test_fused_rollout_parity(torch_gpu):
+    """Fused BF16 actor + step rollout: exploration draws bit-exact, greedy
+    actions agree with the FP64 oracle, and the oracle stepped with the
+    GPU's actions reproduces rewards, dones and the final state bit-exactly."""
+    import oracle
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=45)
+    K = 16
+    banner(f"fused rollout N=45 K={K}")
+    maps = inputs.make_maps(cfg)
+    for variant in [(8, 64), (8, 32), (4, 16)]:
+        env, orc = make(cfg, maps, torch)
+        dims, w, b, eps = _qnet_setup(cfg, env)
+        env.set_variant(1, *variant)
+        env.reset()
+        o_obs, _ = orc.reset()
+        acts, rew, done, obs = env.rollout(K, use_qnet=True)
+        torch.cuda.synchronize()
+        acts, rew, done = to_np(acts), to_np(rew), to_np(done)
+        n_greedy = n_agree = 0
+        for t in range(K):
+            q64 = oracle.qnet_f64(dims, w, b, o_obs)
+            a_vem, ex = orc.vem(q64, eps)
+            exb = ex.astype(bool)
+            w_ = f"fused {variant} t={t}"
+            compare_exact(acts[t][exb], a_vem[exb], "explored actions", w_)
+            n_greedy += int((~exb).sum())
+            n_agree += int((acts[t][~exb] == a_vem[~exb]).sum())
+            r = orc.step(acts[t])
+            compare_exact(rew[t], r["reward"], "reward", w_)
+            compare_exact(done[t], r["done"], "done", w_)
+            o_obs = r["obs"]
+        assert n_agree >= 0.99 * n_greedy, (n_agree, n_greedy)
+        compare_obs(to_np(obs), o_obs, env.n_rays, True, f"fused {variant} final obs")
+        gf, gi = env.get_state()
+        of, oi = orc.get_state()
+        compare_state(gf, gi, of, oi, f"fused {variant} final")
+
+
+def test_autotune_preserves_state(torch_gpu):
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=40)
+    banner("autotune then step N=40")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch)
+    _qnet_setup(cfg, env)
+    env.reset()
+    orc.reset()
+    rep = env.autotune(steps=3)
+    assert "chosen" in rep and len(rep["step"]) == 12
+    assert env.global_step == orc.global_step
+    run_steps(env, orc, 20, torch, noisy=True, check_state_every=5, where="after autotune")
