@@ -49,7 +49,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=512)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mb):
+    """A plain copy kernel of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = mb * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
 
 
 def cpu_baseline(cfg, maps, w, b, eps, seconds):
@@ -113,6 +128,9 @@ def main():
     from paper_2305_04180_amd import inputs, sparrow
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.copy_mb:
+        copy_calibration(args.copy_mb)
+        return
     cfg = inputs.workload(args.workload)
     N = cfg["n_envs"]
     log(f"[bench] generating {N} maps ({cfg['sides']})")
@@ -129,7 +147,7 @@ def main():
     tune = {}
     if not args.no_tune:
         tune = env.autotune(steps=8)
-        log(f"[bench] autotune: {json.dumps(tune)[:400]}")
+        log(f"[bench] autotune: {json.dumps(tune)}")
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 

@@ -72,8 +72,17 @@ __device__ __forceinline__ void stage_maps(const Params& p, int grp, uint32_t* l
     if (sl.x < 0) break;
     const uint4* src = reinterpret_cast<const uint4*>(p.words + p.meta[sl.y].off);
     uint4* dst = reinterpret_cast<uint4*>(lds + sl.z);
-    const int n4 = sl.w >> 2;
-    for (int w = threadIdx.x; w < n4; w += blockDim.x) dst[w] = src[w];
+    const int n4 = sl.w >> 2, bd = blockDim.x;
+    int w = threadIdx.x;
+    // eight 16-byte loads in flight per lane before their LDS stores
+    for (; w + 7 * bd < n4; w += 8 * bd) {
+      uint4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[w + u * bd];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dst[w + u * bd] = v[u];
+    }
+    for (; w < n4; w += bd) dst[w] = src[w];
   }
 }
 
@@ -100,6 +109,7 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   if (sl.x < 0) return;
   const int i = sl.x;
   const Lanes<L> ln(threadIdx.x);
+  const RayDirs<L> rd = load_rays<L>(p.rays, p.n_rays, ln.q);
   const Slot m = make_slot(p, sl, lds);
   const float inv_dn = p.inv_dn[sl.y];
   const int D = p.obs_dim;
@@ -107,29 +117,29 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   float* orow = p.obs + (size_t)i * D;
   float* crow = p.cur_obs + (size_t)i * D;
   int16_t* hk = p.hit_k + (size_t)i * p.n_rays;
-  if (mode == 1) {
-    const bool ok = reset_env<L>(p, ln, m, e, i, p.g);
-    if (!ok && ln.q == 0) p.err[0] = SPARROW_ERESET;
-    observe<L>(p, ln, m, e, i, p.g, kNoiseReset, inv_dn, orow, crow, hk, nullptr);
-    if (ln.q == 0) store_env(p.s, i, e);
-    return;
+  StepOut o{};
+  bool reset_now = mode == 1;
+  if (mode == 0) {
+    o = step_env<L>(p, ln, m, e, p.actions[i]);
+    reset_now = o.done != 0;
+    if (reset_now && p.final_obs)
+      observe<L>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D, nullptr,
+                 nullptr, nullptr, false);
   }
-  const StepOut o = step_env<L>(p, ln, m, e, p.actions[i]);
-  if (o.done) {
-    if (p.final_obs)
-      observe<L>(p, ln, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D, nullptr,
-                 nullptr, nullptr);
-    const bool ok = reset_env<L>(p, ln, m, e, i, p.g);
-    if (!ok && ln.q == 0) p.err[0] = SPARROW_ERESET;
-    observe<L>(p, ln, m, e, i, p.g, kNoiseReset, inv_dn, orow, crow, hk, nullptr);
-  } else {
-    observe<L>(p, ln, m, e, i, p.g, kNoise, inv_dn, orow, crow, hk, nullptr);
+  bool free_pose = true;  // not done: the step's collision test passed
+  if (reset_now) {
+    free_pose = reset_env<L>(p, ln, m, e, i, p.g);
+    if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
   }
+  observe<L>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
+             nullptr, free_pose);
   if (ln.q == 0) {
     store_env(p.s, i, e);
-    p.reward[i] = o.reward;
-    p.done[i] = o.done;
-    if (p.flags) p.flags[i] = o.flags;
+    if (mode == 0) {
+      p.reward[i] = o.reward;
+      p.done[i] = o.done;
+      if (p.flags) p.flags[i] = o.flags;
+    }
   }
 }
 
@@ -141,13 +151,14 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
   constexpr bool kQ = QC::kOn;
   const int slot = threadIdx.x / L;
   const Lanes<L> ln(threadIdx.x);
+  const RayDirs<L> rd = load_rays<L>(p.rays, p.n_rays, ln.q);
   const int N = p.n_envs, D = p.obs_dim;
   typename QC::Weights qw;
   qw.load(qp, threadIdx.x);
   if constexpr (kQ) {
     // clear the actor's LDS so padded rows and columns hold finite values
     uint32_t* a = lds + qp.lds_base_words;
-    const int nw = (int)(qnet_region_a_bytes(qp) + qnet_region_b_bytes(qp)) / 4;
+    const int nw = (int)qnet_lds_bytes(qp) / 4;
     for (int k = threadIdx.x; k < nw; k += blockDim.x) a[k] = 0u;
   }
   for (int grp = blockIdx.x; grp < p.n_groups; grp += gridDim.x) {
@@ -178,8 +189,10 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       const uint32_t g = p.g + (uint32_t)t;
       int a_hat = 0;
       if constexpr (kQ) {
-        qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);  // barriers inside
-        if (live) a_hat = qnet_vem_action(qp, lds, slot, i, g, eps, p.key0, p.key1);
+        // barriers inside; the wave's env columns are slot % 16
+        const f32x4 tile = qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);
+        const int a_q = qnet_vem_action(qp, tile, slot & 15, i, g, eps, p.key0, p.key1);
+        if (live) a_hat = a_q;
       } else {
         const U4 w = philox((uint32_t)i, g, kActionUniform, 0u, p.key0, p.key1);
         a_hat = scale_u32(w.x, kNumActions);
@@ -190,13 +203,13 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
         float* orow = last ? p.obs + (size_t)i * D : nullptr;
         float* crow = (last || !kQ) ? p.cur_obs + (size_t)i * D : nullptr;
         int16_t* hk = last ? p.hit_k + (size_t)i * p.n_rays : nullptr;
+        bool free_pose = true;  // not done: the step's collision test passed
         if (o.done) {
-          const bool ok = reset_env<L>(p, ln, m, e, i, g);
-          if (!ok && ln.q == 0) p.err[0] = SPARROW_ERESET;
-          observe<L>(p, ln, m, e, i, g, kNoiseReset, inv_dn, orow, crow, hk, act_in);
-        } else {
-          observe<L>(p, ln, m, e, i, g, kNoise, inv_dn, orow, crow, hk, act_in);
+          free_pose = reset_env<L>(p, ln, m, e, i, g);
+          if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
         }
+        observe<L>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
+                   act_in, free_pose);
         if (ln.q == 0) {
           const size_t o_idx = (size_t)t * N + i;
           p.r_reward[o_idx] = o.reward;
@@ -223,7 +236,7 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
   typename QC::Weights qw;
   qw.load(qp, threadIdx.x);
   {
-    const int nw = (int)(qnet_region_a_bytes(qp) + qnet_region_b_bytes(qp)) / 4;
+    const int nw = (int)qnet_lds_bytes(qp) / 4;
     for (int k = threadIdx.x; k < nw; k += blockDim.x) lds[k] = 0u;
   }
   for (int r0 = blockIdx.x * kQRows; r0 < n; r0 += gridDim.x * kQRows) {
@@ -233,11 +246,14 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
       uint16_t* row = qnet_input_row(qp, lds, r);
       row[k] = (r0 + r < n && k < qp.d0) ? bf16_rne(obs[(size_t)(r0 + r) * qp.d0 + k]) : 0;
     }
-    qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);
-    if (threadIdx.x < kQRows && r0 + (int)threadIdx.x < n) {
-      const int r = threadIdx.x, row = r0 + r;
-      float qa[kNumActions];
-      const int gi = qnet_q_values(qp, lds, r, qa);
+    __syncthreads();
+    const f32x4 tile = qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);
+    // wave 0 reports the 16 rows; lane r < 16 takes row r
+    const int r = threadIdx.x & 15;
+    float qa[kNumActions];
+    const int gi = qnet_q_values(qp, tile, r, qa);
+    if (threadIdx.x < kQRows && r0 + r < n) {
+      const int row = r0 + r;
       if (q)
         for (int a = 0; a < kNumActions; ++a) q[(size_t)row * kNumActions + a] = qa[a];
       if (greedy) greedy[row] = gi;
@@ -387,6 +403,10 @@ Params base_params(sparrow_env* e) {
   p.n_rays = c.n_rays;
   p.obs_dim = obs_dim(e);
   p.M = (int32_t)std::floor((double)c.range_cells / (double)c.march_step);
+  p.k_free = 0;
+  while (p.k_free <= p.M &&
+         (double)p.k_free * c.march_step * (1.0 + 1e-6) + 1e-3 <= (double)c.robot_radius)
+    ++p.k_free;
   p.t_max = c.timeout_steps;
   p.delay_lo = c.delay_lo;
   p.delay_hi = c.delay_hi;

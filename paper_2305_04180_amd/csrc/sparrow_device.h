@@ -37,10 +37,15 @@ constexpr float kTwoPiF = (float)(2.0 * kPiD);
 constexpr float kTwoOverPiF = (float)(2.0 / kPiD);
 constexpr float kInvPiF = (float)(1.0 / kPiD);
 constexpr float kTwoM24 = 5.9604644775390625e-08f;
+constexpr float kMinusTwoLn2 = (float)(-2.0 * 0.69314718055994530942);
 
-// Target velocity table: (fraction of v_max, fraction of omega_max).
-__constant__ const float kActV[7] = {0.02f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 0.02f};
-__constant__ const float kActW[7] = {1.0f, 1.0f, 0.5f, 0.0f, -0.5f, -1.0f, -1.0f};
+// Target velocity of action a: (fraction of v_max, fraction of omega_max) =
+// (0.02, 1) (1, 1) (1, 0.5) (1, 0) (1, -0.5) (1, -1) (0.02, -1); evaluated
+// with selects so no table is read from memory inside the step.
+__device__ __forceinline__ float act_v(int a) { return (a == 0 || a == 6) ? 0.02f : 1.0f; }
+__device__ __forceinline__ float act_w(int a) {
+  return a <= 1 ? 1.0f : a == 2 ? 0.5f : a == 3 ? 0.0f : a == 4 ? -0.5f : -1.0f;
+}
 
 // ------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11), counter (env, step, purpose, sub).
@@ -136,6 +141,7 @@ struct Params {
   const int4* slots;        // [n_groups][epw]: {env (-1: empty), map, LDS word offset, words}
   int32_t n_groups, epw;
   int32_t n_envs, n_rays, obs_dim, M, t_max, delay_lo, delay_hi;
+  int32_t k_free;           // samples with t_k (1 + 1e-6) + 1e-3 <= robot radius
   float ds, range, inv_R, robot_r, arrive_r, omega_max;
   float dt_lo, dt_span, K_lo, K_span, mu_lo, mu_span, vmax_lo, vmax_span, sigma_lo,
       sigma_span;
@@ -224,16 +230,17 @@ __device__ __forceinline__ int med3i(int x, int lo, int hi) {
 struct Slot {
   const uint32_t* w1;
   int32_t W, H, wpr;
-  // word index (relative to w1) and bit of cell (ix, iy), clamped to the ring
-  __device__ __forceinline__ int word_of(int ix, int iy, int& bit) const {
+  // LDS byte address of cell (ix, iy)'s word and its bit, clamped to the ring
+  __device__ __forceinline__ const uint32_t* word_of(int ix, int iy, int& bit) const {
     ix = med3i(ix, -1, W);
     iy = med3i(iy, -1, H);
     bit = ix + 1;
-    return __mul24(iy, wpr) + (bit >> 5);
+    const char* row = reinterpret_cast<const char*>(w1) + __mul24(iy, wpr * 4);
+    return reinterpret_cast<const uint32_t*>(row + ((uint32_t)bit >> 5) * 4u);
   }
   __device__ __forceinline__ bool occ(int ix, int iy) const {
     int bit;
-    const uint32_t word = w1[word_of(ix, iy, bit)];
+    const uint32_t word = *word_of(ix, iy, bit);
     return __builtin_amdgcn_ubfe(word, (uint32_t)bit, 1u) != 0u;
   }
 };
@@ -269,7 +276,7 @@ __device__ __forceinline__ bool collides_seq(const Slot& m, float px, float py, 
     uint64_t acc = 0;
     for (int j = j0; j <= j1; ++j) {
       // the second word may be the next row's first one: in range, masked off
-      const uint32_t* row = m.w1 + j * m.wpr + wlo;
+      const uint32_t* row = m.w1 + __mul24(j, m.wpr) + wlo;
       const uint64_t v = (uint64_t)row[0] | ((uint64_t)row[1] << 32);
       acc |= (v >> sh) & mask;
     }
@@ -299,7 +306,10 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
   return ln.ballot(hit) != 0ull;
 }
 
-constexpr int kUnroll = 4;  // samples per lane per iteration (independent LDS reads)
+#ifndef SPARROW_UNROLL
+#define SPARROW_UNROLL 4
+#endif
+constexpr int kUnroll = SPARROW_UNROLL;  // samples per lane per iteration (independent LDS reads)
 constexpr int kNoHit = 1 << 30;
 
 // Distance of sample k. With ds == 1 it is (float)k; otherwise (float)k * ds.
@@ -315,17 +325,18 @@ __device__ __forceinline__ float sample_t(int k, float ds) {
 template <bool UNIT>
 __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, float ux, float uy,
                                             float ds, int M, int k0, int stride) {
-  int idx[kUnroll], bit[kUnroll];
+  const uint32_t* adr[kUnroll];
+  int bit[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     const float tk = sample_t<UNIT>(k0 + u * stride, ds);
     const float px = x + tk * ux;
     const float py = y + tk * uy;
-    idx[u] = m.word_of(cvt_flr(px), cvt_flr(py), bit[u]);
+    adr[u] = m.word_of(cvt_flr(px), cvt_flr(py), bit[u]);
   }
   uint32_t wv[kUnroll];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) wv[u] = m.w1[idx[u]];
+  for (int u = 0; u < kUnroll; ++u) wv[u] = *adr[u];
   int kh = kNoHit;
 #pragma unroll
   for (int u = kUnroll - 1; u >= 0; --u) {
@@ -335,11 +346,12 @@ __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, flo
   return kh;
 }
 
-// First hit of one ray marched by one lane. Returns -1 when no sample up to M hits.
+// First hit of one ray marched by one lane, from sample k_start (earlier
+// samples are known to be free). Returns -1 when no sample up to M hits.
 template <bool UNIT>
 __device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float ux, float uy,
-                                          float ds, int M) {
-  for (int k0 = 0; k0 <= M; k0 += kUnroll) {
+                                          float ds, int M, int k_start) {
+  for (int k0 = k_start; k0 <= M; k0 += kUnroll) {
     const int kh = sample_block<UNIT>(m, x, y, ux, uy, ds, M, k0, 1);
     if (kh != kNoHit) return kh;
   }
@@ -351,23 +363,66 @@ __device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float
 // the minimum hit, so the ray stops at the first iteration with any hit.
 template <bool UNIT>
 __device__ __forceinline__ int march_split(const Slot& m, float x, float y, float ux, float uy,
-                                           float ds, int M, int P, int phase, int Lr, int L) {
+                                           float ds, int M, int P, int phase, int Lr, int L,
+                                           int k_start) {
   const int span = P * kUnroll;
   for (int it = 0;; ++it) {
-    int kl = sample_block<UNIT>(m, x, y, ux, uy, ds, M, it * span + phase, P);
-    for (int s = Lr; s < L; s <<= 1) kl = min(kl, __shfl_xor(kl, s));
+    const int kb = k_start + it * span;
+    int kl = sample_block<UNIT>(m, x, y, ux, uy, ds, M, kb + phase, P);
+    if (L == 64 && Lr == 32) {
+      // partner lane is lane ^ 32: v_permlane32_swap leaves {own, partner}
+      // in the two results of every lane, with no LDS round trip
+      const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)kl, (uint32_t)kl, false, false);
+      kl = min((int)sw[0], (int)sw[1]);
+    } else {
+      for (int s = Lr; s < L; s <<= 1) kl = min(kl, __shfl_xor(kl, s));
+    }
     if (kl != kNoHit) return kl;
-    if (it * span + span - 1 >= M) return -1;
+    if (kb + span - 1 >= M) return -1;
   }
+}
+
+// ------------------------------------------------------------------------
+// The lane's ray offset directions (cos, sin), loaded once per kernel.
+// ------------------------------------------------------------------------
+// At most 128 rays: a lane of an env on L lanes marches up to 128 / L rays.
+template <int L>
+struct RayDirs {
+  static constexpr int kMaxRPL = 128 / L;
+  float c[kMaxRPL], s[kMaxRPL];
+};
+
+template <int L>
+__device__ __forceinline__ RayDirs<L> load_rays(const float2* rays, int nr, int q) {
+  constexpr int kMaxRPL = RayDirs<L>::kMaxRPL;
+  int R2 = 1;
+  while (R2 < nr) R2 <<= 1;
+  const int Lr = L >= R2 ? R2 : L;
+  const int RPL = L >= R2 ? 1 : R2 / L;
+  RayDirs<L> d;
+#pragma unroll
+  for (int rr = 0; rr < kMaxRPL; ++rr) {
+    const int j = q % Lr + rr * Lr;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (rr < RPL && j < nr) v = rays[j];
+    d.c[rr] = v.x;
+    d.s[rr] = v.y;
+  }
+  return d;
 }
 
 // ------------------------------------------------------------------------
 // Observation of one env: rays (march + noise), velocities, target.
 // ------------------------------------------------------------------------
 template <int L>
-__device__ void observe(const Params& p, const Lanes<L>& ln, const Slot& m, const Env& e,
-                        int i, uint32_t g, uint32_t purpose, float inv_dn, float* dst, float* dst2,
-                        int16_t* hk, uint16_t* dst_bf16) {
+__device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, const RayDirs<L>& rd, const Slot& m,
+                        const Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
+                        float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
+                        bool disk_free) {
+  // With the robot disk known to be collision-free, every sample closer to
+  // the centre than the radius lies in a cell a collision test would have
+  // flagged, so none of the first k_free samples can hit.
+  const int k_start = disk_free ? p.k_free : 0;
   float s, c;
   sincos_f32(e.phi, s, c);
   const float fx = -c, fy = -s;  // heading: direction of motion in Eq. (6)
@@ -378,31 +433,35 @@ __device__ void observe(const Params& p, const Lanes<L>& ln, const Slot& m, cons
   const int Lr = L >= R2 ? R2 : L;      // rays handled side by side
   const int RPL = L >= R2 ? 1 : R2 / L; // rays per lane
   const int j0 = ln.q % Lr, phase = ln.q / Lr;
-  for (int rr = 0; rr < RPL; ++rr) {
+#pragma unroll
+  for (int rr = 0; rr < RayDirs<L>::kMaxRPL; ++rr) {
+    if (rr >= RPL) break;
     const int j = j0 + rr * Lr;
     const bool valid = j < nr;
     float ux = 0.0f, uy = 0.0f;
     if (valid) {
-      const float2 cs = p.rays[j];
-      ux = fx * cs.x - fy * cs.y;
-      uy = fy * cs.x + fx * cs.y;
+      ux = fx * rd.c[rr] - fy * rd.s[rr];
+      uy = fy * rd.c[rr] + fx * rd.s[rr];
     }
     int kh = -1;
     if (valid) {
       const bool unit = p.ds == 1.0f;
       if (P == 1)
-        kh = unit ? march_lane<true>(m, e.x, e.y, ux, uy, p.ds, p.M)
-                  : march_lane<false>(m, e.x, e.y, ux, uy, p.ds, p.M);
+        kh = unit ? march_lane<true>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                  : march_lane<false>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start);
       else
-        kh = unit ? march_split<true>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L)
-                  : march_split<false>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L);
+        kh = unit ? march_split<true>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L, k_start)
+                  : march_split<false>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L, k_start);
     }
     if (valid && phase == 0) {
       const float d = kh < 0 ? p.range : (float)kh * p.ds;
       const U4 w = philox((uint32_t)i, g, purpose, (uint32_t)j, p.key0, p.key1);
+      // Box-Muller with the hardware transcendentals: v_log_f32 is log2 and
+      // v_cos_f32 takes revolutions, so cos(2 pi u2) needs no range reduction
       const float u1 = (float)((w.x >> 8) + 1u) * kTwoM24;
       const float u2 = (float)(w.y >> 8) * kTwoM24;
-      const float z = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+      const float rad = __builtin_amdgcn_sqrtf(kMinusTwoLn2 * __builtin_amdgcn_logf(u1));
+      const float z = rad * __builtin_amdgcn_cosf(u2);
       float dn = d + e.sigma * z;
       dn = fminf(fmaxf(dn, 0.0f), p.range);
       const float o = dn * p.inv_R;
@@ -516,8 +575,8 @@ __device__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m, 
   }
   float cl = 0.0f, ca = 0.0f;
   if (a != kStop) {
-    cl = e.mu * (kActV[a] * e.vmax);
-    ca = e.mu * (kActW[a] * p.omega_max);
+    cl = e.mu * (act_v(a) * e.vmax);
+    ca = e.mu * (act_w(a) * p.omega_max);
   }
   // Eq. (5)
   const float omk = 1.0f - e.K;

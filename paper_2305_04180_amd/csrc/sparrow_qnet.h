@@ -9,7 +9,9 @@
 // Layout. Eight waves serve 16 rows (envs) at a time. Each wave keeps its
 // slice of the weights resident in VGPRs for the whole kernel (weight-
 // stationary): layer 1 and layer 2 are split by output tiles of 16 hidden
-// units, layer 3 by 32-wide K steps whose partial sums meet in LDS. One MFMA
+// units; every wave computes the whole (16-row) layer 3 for the 16 envs so
+// that its own envs' Q values need no cross-wave reduction (its 8 KB of
+// weights are read per pass from the L1 cache). One MFMA
 // v_mfma_f32_16x16x32_bf16 computes D[h][env] += W[h][k] * X[env][k] over a
 // 16 x 16 x 32 block: A = weight rows, B = activation rows from LDS, D rows =
 // hidden units, D columns = envs. Activations live in LDS as bf16 rows [env][k]
@@ -41,22 +43,23 @@ struct QParams {
   int32_t lds_base_words;  // first LDS word of the actor's buffers
 };
 
-// LDS: region A holds the bf16 input rows and, later in the same pass, the
-// second hidden layer; region B holds the first hidden layer and then the
-// layer-3 partial sums.
+// LDS: region A holds the bf16 input rows, region B the first hidden layer,
+// region C the second hidden layer.
 __host__ __device__ inline int qnet_stride0(const QParams& q) { return q.d0p + 8; }
 __host__ __device__ inline int qnet_stride1(const QParams& q) { return q.h1 + 8; }
 __host__ __device__ inline int qnet_stride2(const QParams& q) { return q.h2 + 8; }
 __host__ __device__ inline int qnet_region_a_bytes(const QParams& q) {
-  const int a0 = kQRows * qnet_stride0(q) * 2, a2 = kQRows * qnet_stride2(q) * 2;
-  return ((a0 > a2 ? a0 : a2) + 15) & ~15;
+  return (kQRows * qnet_stride0(q) * 2 + 15) & ~15;
 }
 __host__ __device__ inline int qnet_region_b_bytes(const QParams& q) {
-  const int b1 = kQRows * qnet_stride1(q) * 2, bp = kQWaves * kQRows * 16 * 4;
-  return ((b1 > bp ? b1 : bp) + 15) & ~15;
+  return (kQRows * qnet_stride1(q) * 2 + 15) & ~15;
 }
-inline size_t qnet_lds_bytes(const QParams& q) {
-  return (size_t)qnet_region_a_bytes(q) + (size_t)qnet_region_b_bytes(q);
+__host__ __device__ inline int qnet_region_c_bytes(const QParams& q) {
+  return (kQRows * qnet_stride2(q) * 2 + 15) & ~15;
+}
+__host__ __device__ inline size_t qnet_lds_bytes(const QParams& q) {
+  return (size_t)qnet_region_a_bytes(q) + (size_t)qnet_region_b_bytes(q) +
+         (size_t)qnet_region_c_bytes(q);
 }
 
 __device__ __forceinline__ uint16_t* qnet_region_a(const QParams& q, uint32_t* lds) {
@@ -65,6 +68,10 @@ __device__ __forceinline__ uint16_t* qnet_region_a(const QParams& q, uint32_t* l
 __device__ __forceinline__ uint16_t* qnet_region_b(const QParams& q, uint32_t* lds) {
   return reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds + q.lds_base_words) +
                                      qnet_region_a_bytes(q));
+}
+__device__ __forceinline__ uint16_t* qnet_region_c(const QParams& q, uint32_t* lds) {
+  return reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds + q.lds_base_words) +
+                                     qnet_region_a_bytes(q) + qnet_region_b_bytes(q));
 }
 __device__ __forceinline__ uint16_t* qnet_input_row(const QParams& q, uint32_t* lds, int row) {
   return qnet_region_a(q, lds) + row * qnet_stride0(q);
@@ -78,14 +85,13 @@ struct QNetCfg {
   static constexpr int K1 = D0P / 32;
   static constexpr int T2 = H2 / 16 / kQWaves;
   static constexpr int K2 = H1 / 32;
-  static constexpr int K3 = H2 / 32 / kQWaves;  // layer-3 K steps per wave
-  static_assert(T1 >= 1 && T2 >= 1 && K3 >= 1, "hidden sizes must be multiples of 256");
-  static_assert(H1 % (16 * kQWaves) == 0 && H2 % (32 * kQWaves) == 0, "unsupported sizes");
+  static constexpr int K3 = H2 / 32;  // layer-3 K steps (every wave does all)
+  static_assert(T1 >= 1 && T2 >= 1, "hidden sizes must be multiples of 128");
+  static_assert(H1 % (16 * kQWaves) == 0 && H2 % (16 * kQWaves) == 0, "unsupported sizes");
 
   struct Weights {
     bf16x8 a1[T1][K1];
     bf16x8 a2[T2][K2];
-    bf16x8 a3[K3];
     f32x4 bias1[T1];
     f32x4 bias2[T2];
 
@@ -110,9 +116,6 @@ struct QNetCfg {
         const int hb = (w * T2 + t) * 16 + (l >> 4) * 4;
         bias2[t] = f32x4{q.b2[hb], q.b2[hb + 1], q.b2[hb + 2], q.b2[hb + 3]};
       }
-#pragma unroll
-      for (int ks = 0; ks < K3; ++ks)
-        a3[ks] = *reinterpret_cast<const bf16x8*>(q.w3 + (size_t)r * H2 + (w * K3 + ks) * 32 + kq);
     }
   };
 };
@@ -140,70 +143,73 @@ __device__ __forceinline__ void qnet_layer(const bf16x8 (&a)[T][KS], const f32x4
                                            const uint16_t* in, int in_stride, uint16_t* out,
                                            int out_stride, int tile0, int l) {
   const int env = l & 15, kq = (l >> 4) * 8, hq = (l >> 4) * 4;
-  bf16x8 b[KS];
+  f32x4 acc[T];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks)
-    b[ks] = *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq);
+  for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // K outer, tiles inner: one B fragment live at a time
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq);
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = mfma16x16x32(a[t][ks], b, acc[t]);
+  }
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) acc = mfma16x16x32(a[t][ks], b[ks], acc);
-    acc += bias[t];
+    const f32x4 v4 = acc[t] + bias[t];
     uint2 v;
-    v.x = pack_relu_bf16x2(acc[0], acc[1]);
-    v.y = pack_relu_bf16x2(acc[2], acc[3]);
+    v.x = pack_relu_bf16x2(v4[0], v4[1]);
+    v.y = pack_relu_bf16x2(v4[2], v4[3]);
     *reinterpret_cast<uint2*>(out + env * out_stride + (tile0 + t) * 16 + hq) = v;
   }
 }
 
-// Forward pass over the 16 input rows in LDS region A. Ends with a barrier
-// after which the layer-3 partial sums are in region B.
+// Forward pass over the 16 input rows in LDS region A (the caller has made
+// them visible with a barrier). Returns this lane's layer-3 tile: Q[a][env]
+// for actions a = 4 * (lane / 16) + 0..3 and env = lane % 16.
 template <class QC>
-__device__ __forceinline__ void qnet_forward_group(const QParams& q,
-                                                   const typename QC::Weights& W,
-                                                   uint32_t* lds, int tid) {
+__device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
+                                                    const typename QC::Weights& W,
+                                                    uint32_t* lds, int tid) {
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
   if constexpr (QC::kOn) {
     const int w = tid >> 6, l = tid & 63;
+    const int env = l & 15, kq = (l >> 4) * 8;
+    // layer-3 weights (8 KB shared by the workgroup, L1-resident): loaded
+    // here so the reads overlap layers 1 and 2 and the registers are live
+    // only during the forward pass
+    bf16x8 a3[QC::K3];
+#pragma unroll
+    for (int ks = 0; ks < QC::K3; ++ks)
+      a3[ks] = *reinterpret_cast<const bf16x8*>(q.w3 + (size_t)env * q.h2 + ks * 32 + kq);
     uint16_t* ra = qnet_region_a(q, lds);
     uint16_t* rb = qnet_region_b(q, lds);
-    __syncthreads();  // input rows complete
+    uint16_t* rc = qnet_region_c(q, lds);
     qnet_layer<QC::T1, QC::K1>(W.a1, W.bias1, ra, qnet_stride0(q), rb, qnet_stride1(q),
                                w * QC::T1, l);
     __syncthreads();
-    qnet_layer<QC::T2, QC::K2>(W.a2, W.bias2, rb, qnet_stride1(q), ra, qnet_stride2(q),
+    qnet_layer<QC::T2, QC::K2>(W.a2, W.bias2, rb, qnet_stride1(q), rc, qnet_stride2(q),
                                w * QC::T2, l);
     __syncthreads();
-    {
-      const int env = l & 15, kq = (l >> 4) * 8;
-      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int ks = 0; ks < QC::K3; ++ks) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(ra + env * qnet_stride2(q) +
-                                                          (w * QC::K3 + ks) * 32 + kq);
-        acc = mfma16x16x32(W.a3[ks], b, acc);
-      }
-      // partial[w][env][action], actions 4*(l/16) .. +3
-      float* part = reinterpret_cast<float*>(rb);
-      *reinterpret_cast<f32x4*>(part + (w * kQRows + env) * 16 + (l >> 4) * 4) = acc;
+    for (int ks = 0; ks < QC::K3; ++ks) {
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq);
+      acc = mfma16x16x32(a3[ks], b, acc);
     }
-    __syncthreads();
   }
+  return acc;
 }
 
-// Q values of row `row` (bias + partial sums in a fixed order); returns the
+// Q values of env column `row` of a wave's layer-3 tile (plus bias), gathered
+// from the lanes that hold them; every calling lane gets all of them and the
 // lowest index of the maximum.
-__device__ __forceinline__ int qnet_q_values(const QParams& q, uint32_t* lds, int row,
+__device__ __forceinline__ int qnet_q_values(const QParams& q, const f32x4& tile, int row,
                                              float (&qa)[kNumActions]) {
-  const float* part = reinterpret_cast<const float*>(qnet_region_b(q, lds));
   int best = 0;
 #pragma unroll
   for (int a = 0; a < kNumActions; ++a) {
-    float v = q.b3[a];
-#pragma unroll
-    for (int w = 0; w < kQWaves; ++w) v += part[(w * kQRows + row) * 16 + a];
-    qa[a] = v;
-    if (v > qa[best]) best = a;
+    const float v = __shfl(tile[a & 3], row + 16 * (a >> 2));
+    qa[a] = q.b3[a] + v;
+    if (qa[a] > qa[best]) best = a;
   }
   return best;
 }
@@ -216,11 +222,11 @@ __device__ __forceinline__ int vem_select(int greedy, int env, uint32_t g, float
   return unit24(w.x) < eps ? scale_u32(w.y, kNumActions) : greedy;
 }
 
-__device__ __forceinline__ int qnet_vem_action(const QParams& q, uint32_t* lds, int row, int env,
-                                               uint32_t g, float eps, uint32_t key0,
+__device__ __forceinline__ int qnet_vem_action(const QParams& q, const f32x4& tile, int row,
+                                               int env, uint32_t g, float eps, uint32_t key0,
                                                uint32_t key1) {
   float qa[kNumActions];
-  return vem_select(qnet_q_values(q, lds, row, qa), env, g, eps, key0, key1);
+  return vem_select(qnet_q_values(q, tile, row, qa), env, g, eps, key0, key1);
 }
 
 }  // namespace sp

@@ -668,3 +668,25 @@ def test_paper_constants_fixture():
         o.step([ident])
         assert abs(get(o, "vl")[0] / 10.0 - a["v_cm_s"] / vmax) < 1e-7
         assert get(o, "va")[0] == np.float32(a["w_rad_s"])
+
+
+def test_free_disk_means_no_hit_inside_radius():
+    """For a collision-free pose, no ray can hit at a sample closer than the
+    robot radius (such a cell would have been a collision): the first
+    k_free = 3 samples (t = 0, 1, 2 < r = 3) never hit. The HIP march starts
+    at k_free for such poses, so this property is what keeps it exact."""
+    cfg = inputs.workload("c2", n_envs=8)
+    maps = inputs.make_maps(cfg)
+    o = oracle.Oracle(cfg, maps)
+    rng = np.random.default_rng(21)
+    checked = 0
+    for _ in range(3000):
+        m = int(rng.integers(0, 8))
+        x, y = (float(np.float32(v)) for v in rng.uniform(-2, 368, 2))
+        if o.collides(m, x, y):
+            continue
+        for th in rng.uniform(-math.pi, math.pi, 8):
+            k = o.march(m, x, y, float(np.float32(math.cos(th))), float(np.float32(math.sin(th))))
+            assert k == -1 or k >= 3, (m, x, y, th, k)
+            checked += 1
+    assert checked > 5000
