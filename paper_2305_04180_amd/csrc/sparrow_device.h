@@ -66,10 +66,9 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
   return U4{c0, c1, c2, c3};
 }
 
-// float -> bf16 bits, round to nearest even (finite inputs)
+// float -> bf16 bits, round to nearest even (v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
-  const uint32_t u = __builtin_bit_cast(uint32_t, f);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 __device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * kTwoM24; }
@@ -172,6 +171,7 @@ struct Params {
 struct Env {
   float x, y, phi, vl, va, tx, ty, dprev, dt, K, mu, vmax, sigma;
   int32_t t, delay, q0, q1;
+  float sphi, cphi;  // sincos_f32(phi), kept current with phi
 };
 
 __device__ __forceinline__ Env load_env(const State& s, int i) {
@@ -181,6 +181,7 @@ __device__ __forceinline__ Env load_env(const State& s, int i) {
   e.mu = s.mu[i]; e.vmax = s.vmax[i]; e.sigma = s.sigma[i]; e.t = s.t[i];
   const uint32_t c = s.ctl[i];
   e.delay = (int)(c & 0xFFu); e.q0 = (int)((c >> 8) & 0xFFu); e.q1 = (int)((c >> 16) & 0xFFu);
+  sincos_f32(e.phi, e.sphi, e.cphi);
   return e;
 }
 
@@ -311,15 +312,12 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
 #endif
 constexpr int kUnroll = SPARROW_UNROLL;  // samples per lane per iteration (independent LDS reads)
 constexpr int kNoHit = 1 << 30;
-
-// Distance of sample k. With ds == 1 it is (float)k; otherwise (float)k * ds.
-template <bool UNIT>
-__device__ __forceinline__ float sample_t(int k, float ds) {
-  return UNIT ? (float)k : (float)k * ds;
-}
+static_assert(kUnroll <= 32, "hit bits of one block fit a word");
 
 // kUnroll samples k0 + u * stride of one ray: all addresses first, then all
-// LDS reads, then the tests, so the reads are in flight together. Returns the
+// LDS reads, then the tests, so the reads are in flight together. Sample
+// distances are t_k = (float)k * ds; with ds == 1 that is (float)k, formed
+// here as (float)k0 + (float)(u * stride), exact for k < 2^24. Returns the
 // smallest hitting k <= M, or kNoHit. Samples past M stay inside the slot
 // (clamped to the ring) and are never reported.
 template <bool UNIT>
@@ -327,9 +325,10 @@ __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, flo
                                             float ds, int M, int k0, int stride) {
   const uint32_t* adr[kUnroll];
   int bit[kUnroll];
+  const float tk0 = (float)k0;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
-    const float tk = sample_t<UNIT>(k0 + u * stride, ds);
+    const float tk = UNIT ? tk0 + (float)(u * stride) : (float)(k0 + u * stride) * ds;
     const float px = x + tk * ux;
     const float py = y + tk * uy;
     adr[u] = m.word_of(cvt_flr(px), cvt_flr(py), bit[u]);
@@ -337,13 +336,11 @@ __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, flo
   uint32_t wv[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) wv[u] = *adr[u];
-  int kh = kNoHit;
+  uint32_t hits = 0;
 #pragma unroll
-  for (int u = kUnroll - 1; u >= 0; --u) {
-    const int k = k0 + u * stride;
-    if (__builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) != 0u && k <= M) kh = k;
-  }
-  return kh;
+  for (int u = 0; u < kUnroll; ++u) hits |= __builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) << u;
+  const int kh = hits ? k0 + (int)__builtin_ctz(hits) * stride : kNoHit;
+  return kh <= M ? kh : kNoHit;
 }
 
 // First hit of one ray marched by one lane, from sample k_start (earlier
@@ -416,16 +413,15 @@ __device__ __forceinline__ RayDirs<L> load_rays(const float2* rays, int nr, int 
 // ------------------------------------------------------------------------
 template <int L>
 __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, const RayDirs<L>& rd, const Slot& m,
-                        const Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
+                        Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
                         float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
                         bool disk_free) {
   // With the robot disk known to be collision-free, every sample closer to
   // the centre than the radius lies in a cell a collision test would have
   // flagged, so none of the first k_free samples can hit.
   const int k_start = disk_free ? p.k_free : 0;
-  float s, c;
-  sincos_f32(e.phi, s, c);
-  const float fx = -c, fy = -s;  // heading: direction of motion in Eq. (6)
+  sincos_f32(e.phi, e.sphi, e.cphi);  // also the next step's Eq. (6) heading
+  const float fx = -e.cphi, fy = -e.sphi;  // heading: direction of motion in Eq. (6)
   const int nr = p.n_rays;
   int R2 = 1;
   while (R2 < nr) R2 <<= 1;
@@ -584,11 +580,9 @@ __device__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m, 
   float va = e.K * e.va + omk * ca;
   vl = fminf(fmaxf(vl, -e.vmax), e.vmax);
   va = fminf(fmaxf(va, -p.omega_max), p.omega_max);
-  // Eq. (6): new velocity, old heading
-  float s, c;
-  sincos_f32(e.phi, s, c);
-  e.x = e.x - e.dt * (vl * c);
-  e.y = e.y - e.dt * (vl * s);
+  // Eq. (6): new velocity, old heading (its sin/cos are current in e)
+  e.x = e.x - e.dt * (vl * e.cphi);
+  e.y = e.y - e.dt * (vl * e.sphi);
   float phi = e.phi + e.dt * va;
   if (phi > kPiF) phi -= kTwoPiF;
   else if (phi <= -kPiF) phi += kTwoPiF;

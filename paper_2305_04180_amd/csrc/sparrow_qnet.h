@@ -131,10 +131,12 @@ __device__ __forceinline__ f32x4 mfma16x16x32(const bf16x8& a, const bf16x8& b, 
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU, then two values to packed bf16 with round to nearest even
 __device__ __forceinline__ uint32_t pack_relu_bf16x2(float lo, float hi) {
-  lo = fmaxf(lo, 0.0f);
-  hi = fmaxf(hi, 0.0f);
-  return (uint32_t)bf16_rne(lo) | ((uint32_t)bf16_rne(hi) << 16);
+  const bf16x2 v = {(__bf16)fmaxf(lo, 0.0f), (__bf16)fmaxf(hi, 0.0f)};
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 // One dense layer for this wave's output tiles: out[env][h] = relu(W x + b).
