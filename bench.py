@@ -30,8 +30,28 @@ sys.path.insert(0, ROOT)
 MI355X_HBM_GBS = 8000.0
 MI355X_CUS, MI355X_CLOCK_GHZ = 256, 2.4
 MI355X_LDS_GBS = MI355X_CUS * 128 * MI355X_CLOCK_GHZ  # 128 B/clk/CU
-MI355X_VALU_GOPS = MI355X_CUS * 64 * MI355X_CLOCK_GHZ  # wave64 lane-ops per second (non-packed)
+# 32-bit vector lane-ops per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and packed FP32 as 2)
+MI355X_VALU_TOPS = MI355X_CUS * 4 * 16 * MI355X_CLOCK_GHZ / 1e3
 MI355X_BF16_TFLOPS = 2500.0
+
+# Algorithmic work of one env-step, from the method's definition (not from
+# the kernel's instruction count):
+#   per marched ray sample: t_k (1), position x + t*u, y + t*u (4),
+#     floor (2), outside-map clamp (2), row multiply-add (1), word shift (1),
+#     address add (1), bit test (1)                              = 13 lane-ops
+#   per ray: Philox4x32-10 (10 rounds x (2 mul-lo, 2 mul-hi, 4 xor,
+#     2 key adds)) = 100, Box-Muller + noise add + clip + scale = 10 -> 110
+#   per env: delay FIFO, command, Eq. (5), Eq. (6), wrap (~30), sincos (~30),
+#     disk collision over <= 49 cells x 10 (~490), arrival/reward (~12),
+#     observation scalars incl. atan2 (~40), VEM draw (~105)      = 707
+ALG_OPS_PER_SAMPLE = 13
+ALG_OPS_PER_RAY = 110
+ALG_OPS_PER_ENV = 707
+# HBM bytes of one plain step of one env: its packed map (staged into LDS
+# every step) + SoA state read and written (15 x 4 B x 2) + action (4) +
+# obs and the library's copy (2 x 4 x obs_dim) + reward (4) + done (1) +
+# per-ray hit indices (2 x n_rays)
 
 
 def log(*a):
@@ -114,6 +134,64 @@ def cpu_baseline(cfg, maps, w, b, eps, seconds):
             "kind": "oracle",
             "sample": f"{n_sample} of the {cfg['n_envs']} envs (same maps/physics), {steps} steps, "
                       f"FP64 Q-network + VEM + FP32 step, {dt:.1f} s"}
+
+
+def kernel_source_hash():
+    """sha1 of the HIP sources and the C-ABI header: identifies the kernel
+    build that a counter summary in profiles/ was taken from."""
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2305_04180_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    with open(os.path.join(ROOT, "include", "sparrow.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE x calibration + WRITE_SIZE), or None when the summary was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters_m4096.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip().strip("|").strip()
+        if ":" in line and line.split(":")[0].strip() in ("source_sha1", kernel_key):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha1") != kernel_source_hash() or kernel_key not in vals:
+        return None
+    return int(vals[kernel_key])
+
+
+def env_map_bytes(maps):
+    """Packed LDS-ready bytes of all maps: rows of ceil((W + 2) / 32) words,
+    H + 2 rows (the occupied ring), padded to 16 bytes."""
+    tot = 0
+    for g in maps.grids:
+        H, W = g.shape
+        words = ((W + 2 + 31) // 32) * (H + 2)
+        tot += ((words + 3) // 4) * 16
+    return tot
+
+
+def greedy_agreement(env, obs, dims, w, b):
+    """BF16 MFMA actor vs the FP64 oracle on the rollout's own final
+    observations (oracle leg of the benchmark)."""
+    import torch
+    import oracle
+    q, g = env.qnet_forward(obs)
+    torch.cuda.synchronize()
+    o = obs.cpu().numpy()
+    q64 = oracle.qnet_f64(dims, w, b, o)
+    qg = q.cpu().numpy().astype(np.float64)
+    agree = float((g.cpu().numpy() == q64.argmax(1)).mean())
+    return {"rows": int(o.shape[0]), "greedy_agreement_vs_fp64": round(agree, 5),
+            "max_abs_dq": float(np.abs(qg - q64).max())}
 
 
 def main():
@@ -219,21 +297,49 @@ def main():
     log(f"[bench] plain+actor: {pa_rate / 1e6:.1f} M env-steps/s")
 
     # ---------------- roofline of the fused kernel ----------------
-    # Algorithmic LDS traffic: one 4-byte word per marched ray sample; the
-    # sample count per env-step is taken from the last step's hit indices.
+    # The sample count per env-step (rays marched from k = 0 to the first hit,
+    # the definition's count) is taken from the last step's hit indices.
     samples_per_env_step = samples_last / N
-    lds_bytes_per_launch = samples_per_env_step * 4.0 * N * K
+    nr = cfg["n_rays"]
+    ops_per_env_step = (ALG_OPS_PER_SAMPLE * samples_per_env_step + ALG_OPS_PER_RAY * nr
+                        + ALG_OPS_PER_ENV)
     avg_launch_s = float(launch_ms.mean()) / 1e3
-    lds_gbs = lds_bytes_per_launch / avg_launch_s / 1e9
-    roofline = {"bound": "lds", "achieved": round(lds_gbs, 1), "peak": MI355X_LDS_GBS,
-                "unit": "GB/s", "frac": round(lds_gbs / MI355X_LDS_GBS, 4), "traffic": None,
-                "kernel": "k_rollout (fused actor)", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-                "samples_per_env_step": round(samples_per_env_step, 2)}
+    alu_tops = ops_per_env_step * N * K / avg_launch_s / 1e12
+    lds_gbs = samples_per_env_step * 4.0 * N * K / avg_launch_s / 1e9  # one word per sample
+    D = env.obs_dim
+    # HBM per launch: maps staged once per group, state in and out, the final
+    # observation, per-step reward/done/action (the actor weights, 153 KB,
+    # come from L2 after the first read and are left out)
+    hbm_bytes = (env_map_bytes(maps) + N * (15 * 4 * 2 + 4 * D * 2 + 2 * nr + 4)
+                 + K * N * (4 + 1 + 4))
+    hbm_gbs = hbm_bytes / avg_launch_s / 1e9
+    mlp_flops = 2.0 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3])
+    roofline = {"bound": "alu", "achieved": round(alu_tops, 3), "peak": MI355X_VALU_TOPS,
+                "unit": "TFLOP/s", "frac": round(alu_tops / MI355X_VALU_TOPS, 4),
+                "traffic": counter_traffic("traffic_bytes_per_launch_k_rollout"),
+                "traffic_alg_bytes": int(hbm_bytes),
+                "kernel": "k_rollout<64, QNetCfg<64,256,256>> (fused actor + step)",
+                "units": "32-bit lane-ops from the definition (13/sample, 110/ray, 707/env)",
+                "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                "samples_per_env_step": round(samples_per_env_step, 2),
+                "lds_frac": round(lds_gbs / MI355X_LDS_GBS, 5),
+                "hbm_frac": round(hbm_gbs / MI355X_HBM_GBS, 5),
+                "mfma_frac": round(mlp_flops * N * K / avg_launch_s / 1e12 / MI355X_BF16_TFLOPS, 5)}
+    step_bytes = env_map_bytes(maps) + N * (15 * 4 * 2 + 4 + 4 * D * 2 + 4 + 1 + 2 * nr)
+    plain_hbm = step_bytes * P / (plain_ms / 1e3) / 1e9
+    plain_roofline = {"bound": "hbm", "achieved": round(plain_hbm, 1), "peak": MI355X_HBM_GBS,
+                      "unit": "GB/s", "frac": round(plain_hbm / MI355X_HBM_GBS, 4),
+                      "traffic": counter_traffic("traffic_bytes_per_launch_k_step"),
+                      "traffic_alg_bytes": int(step_bytes),
+                      "kernel": "k_step (one launch per step) + k_actions"}
 
     cpu = None
+    precision = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(cfg, maps, w, b, eps, args.cpu_seconds)
+        precision = greedy_agreement(env, obs, dims, w, b)
+        log(f"[bench] precision: {precision}")
 
     out = {
         "metric": "env-steps/s at N=4096, 366^2 maps, 32 rays; fused BF16 vs plain; % HBM/LDS peak",
@@ -256,8 +362,11 @@ def main():
         "fused_over_plain": round(fused_rate / plain_rate, 3),
         "wall_s_timed": round(wall, 4),
         "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)},
+        "kernel_source_sha1": kernel_source_hash(),
         "roofline": roofline,
+        "plain_roofline": plain_roofline,
         "cpu_baseline": cpu,
+        "precision": precision,
     }
     print(json.dumps(out), flush=True)
 

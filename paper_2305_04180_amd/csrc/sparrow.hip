@@ -322,9 +322,10 @@ struct sparrow_env {
   // host copies
   std::vector<MapMeta> h_meta;
   std::vector<int32_t> h_env_map;
-  // variants: 0 = step/reset, 1 = rollout
-  int var_epw[2] = {4, 8};
-  int var_L[2] = {32, 64};
+  // variants: 0 = step/reset, 1 = rollout (defaults: the autotuner's choice
+  // for 4096 envs on 366^2 maps with 32 rays)
+  int var_epw[2] = {1, 8};
+  int var_L[2] = {64, 64};
   std::map<std::pair<int, int>, Groups> groups;  // (epw, budget words)
   std::map<std::tuple<int, int, int, int, void*, void*, void*, void*>, GraphEntry> graphs;
   // actor
