@@ -1,0 +1,131 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration the
+benchmark times (autotuned default variants, K = 64 rollouts from the graph
+cache): every env where the oracle can afford it, sampled envs otherwise."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2305_04180_amd import inputs
+from tests.parity_util import compare_exact, compare_obs, compare_state, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def m_maps():
+    return inputs.make_maps(inputs.workload("m"))
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def test_m4096_fused_rollout_every_env(torch_gpu, m_maps):
+    """4096 envs, 366^2 maps, BF16 actor: one K = 32 fused rollout from the
+    graph cache, then the oracle steps every env with the GPU's actions."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload("m")
+    N, K = cfg["n_envs"], 32
+    banner(f"fused rollout N={N} K={K} default variant")
+    dims = cfg["qnet"]
+    w, b, _ = inputs.qnet_weights(dims)
+    eps = sparrow.vem_epsilon(N, N, 0.01, 0.29)
+    env = sparrow.Env(cfg, m_maps)
+    env.set_qnet(dims, w, b, eps)
+    assert env.get_variant(1) == (8, 64)
+    orc = oracle.Oracle(cfg, m_maps)
+    env.reset()
+    o_obs, _ = orc.reset()
+    compare_obs(to_np(env.obs), o_obs, cfg["n_rays"], True, "reset")
+    acts, rew, done, obs = env.rollout(K, True)
+    torch.cuda.synchronize()
+    acts, rew, done = to_np(acts), to_np(rew), to_np(done)
+    n_g = n_a = 0
+    for t in range(K):
+        q64 = oracle.qnet_f64(dims, w, b, o_obs)
+        a_vem, ex = orc.vem(q64, eps)
+        exb = ex.astype(bool)
+        compare_exact(acts[t][exb], a_vem[exb], "explored actions", f"t={t}")
+        n_g += int((~exb).sum())
+        n_a += int((acts[t][~exb] == a_vem[~exb]).sum())
+        r = orc.step(acts[t])
+        compare_exact(rew[t], r["reward"], "reward", f"t={t}")
+        compare_exact(done[t], r["done"], "done", f"t={t}")
+        o_obs = r["obs"]
+    print(f"greedy agreement {n_a / n_g:.5f} over {n_g} greedy actions")
+    assert n_a >= 0.995 * n_g
+    compare_obs(to_np(obs), o_obs, cfg["n_rays"], True, "final obs")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, "final state")
+
+
+def test_m4096_plain_step_every_env(torch_gpu, m_maps):
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload("m")
+    banner("plain step N=4096, 8 steps, default variant")
+    env = sparrow.Env(cfg, m_maps)
+    assert env.get_variant(0) == (1, 64)
+    orc = oracle.Oracle(cfg, m_maps)
+    env.reset()
+    orc.reset()
+    flags = torch.zeros(env.n, dtype=torch.uint8, device=env.device)
+    for s in range(8):
+        a = env.random_actions()
+        env.step(a, flags=flags)
+        r = orc.step(orc.uniform_actions(), hit_k=True)
+        w = f"step {s}"
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", w)
+        compare_exact(to_np(env.done), r["done"], "done", w)
+        compare_exact(to_np(flags), r["flags"], "flags", w)
+        compare_exact(to_np(env.reward), r["reward"], "reward", w)
+        compare_obs(to_np(env.obs), r["obs"], cfg["n_rays"], True, w)
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, "plain final")
+
+
+def test_c3_uneven_sides_rollout_sampled(torch_gpu):
+    """C3: 16384 envs with sides {64,128,256,366,512}, 64 rays, range 128,
+    one persistent 64-step rollout (graph) after autotuning; the oracle steps
+    every 32nd env."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload("c3")
+    N, K = cfg["n_envs"], 64
+    banner(f"c3 rollout N={N} K={K}, sampled oracle")
+    maps = inputs.make_maps(cfg)
+    env = sparrow.Env(cfg, maps)
+    env.reset()
+    rep = env.autotune(steps=4)
+    print("autotune chose", rep.get("chosen"), flush=True)
+    orc = oracle.Oracle(cfg, maps)
+    orc.reset()
+    acts, rew, done, obs = env.rollout(K, False)
+    torch.cuda.synchronize()
+    acts, rew, done = to_np(acts), to_np(rew), to_np(done)
+    ids = np.arange(0, N, 32)
+    for t in range(K):
+        a = orc.uniform_actions()
+        compare_exact(acts[t], a, "uniform actions", f"t={t}")
+        r = orc.step_envs(ids, a)
+        compare_exact(rew[t][ids], r["reward"][ids], "reward", f"t={t}")
+        compare_exact(done[t][ids], r["done"][ids], "done", f"t={t}")
+    compare_obs(to_np(obs)[ids], r["obs"][ids], cfg["n_rays"], True, "c3 final obs")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf[ids], gi[ids], of[ids], oi[ids], "c3 final state")
