@@ -10,7 +10,9 @@ A "step" is one vectorized step of all N envs: actor + simulator step.
           replayed from a cached HIP graph; the headline value
   plain : per step, uniform random actions + the plain step kernel
   plain+actor : per step, the separate actor kernel + the plain step kernel
-Prints one JSON line (rank 0, N=1 only).
+The fused path is timed over --repeats runs of exactly --steps steps each
+(HIP events on the launch stream); value is the median run. Prints one JSON
+line (rank 0, N=1 only).
 """
 from __future__ import annotations
 
@@ -61,8 +63,9 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2048)
+    ap.add_argument("--steps", type=int, default=10000, help="timed vectorized steps per run")
     ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs; the median is reported")
     ap.add_argument("--workload", default="m")
     ap.add_argument("--rollout", type=int, default=64, help="steps per fused rollout launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -87,13 +90,23 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes": n * 4, "launches": 3}), flush=True)
 
 
-def cpu_baseline(cfg, maps, w, b, eps, seconds):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, maps, w, b, eps, seconds, cores=None):
     """The oracle (FP32 step + FP64 Q-network + VEM) on the host cores, on a
     bounded sample of envs, one Python thread per core over env shards (the
     C calls release the GIL)."""
     import oracle
     n_sample = 256
-    cores = min(os.cpu_count() or 1, 16)
+    cores = cores or min(os.cpu_count() or 1, 16)
     sub = dict(cfg, n_envs=n_sample)
     from paper_2305_04180_amd import inputs
     smaps = inputs.Maps(grids=maps.grids[:n_sample], env_to_map=np.arange(n_sample, dtype=np.int32))
@@ -169,12 +182,12 @@ def counter_traffic(kernel_key):
 
 
 def env_map_bytes(maps):
-    """Packed LDS-ready bytes of all maps: rows of ceil((W + 2) / 32) words,
-    H + 2 rows (the occupied ring), padded to 16 bytes."""
+    """Packed LDS-ready bytes of all maps: one set word, then H + 2 rows of
+    ceil((W + 1) / 32) words, padded to 16 bytes."""
     tot = 0
     for g in maps.grids:
         H, W = g.shape
-        words = ((W + 2 + 31) // 32) * (H + 2)
+        words = 1 + ((W + 1 + 31) // 32) * (H + 2)
         tot += ((words + 3) // 4) * 16
     return tot
 
@@ -230,8 +243,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---------------- fused rollout ----------------
+    # Each run times exactly args.steps vectorized steps: full K-step
+    # launches plus one shorter launch for the remainder.
     K = args.rollout
-    n_roll = max(1, math.ceil(args.steps / K))
+    n_full, rem = divmod(args.steps, K)
     n_warm = max(1, math.ceil(args.warmup / K))
     acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
     rew = torch.zeros(K, N, dtype=torch.float32, device="cuda")
@@ -240,25 +255,39 @@ def main():
     log(f"[bench] fused warmup {n_warm} x {K} steps")
     for _ in range(n_warm):
         env.rollout(K, True, acts, rew, done, obs)
+    if rem:
+        env.rollout(rem, True, acts, rew, done, obs)
     torch.cuda.synchronize()
-    log("[bench] fused timed")
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(n_roll)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for i in range(n_roll):
-        ev[i][0].record(stream)
-        env.rollout(K, True, acts, rew, done, obs)
-        ev[i][1].record(stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    fused_ms = t_start.elapsed_time(t_end)
-    launch_ms = np.array([a.elapsed_time(b2) for a, b2 in ev])
-    steps_fused = n_roll * K
+
+    def fused_run():
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n_full)]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t_start.record(stream)
+        for i in range(n_full):
+            ev[i][0].record(stream)
+            env.rollout(K, True, acts, rew, done, obs)
+            ev[i][1].record(stream)
+        if rem:
+            env.rollout(rem, True, acts, rew, done, obs)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return (t_start.elapsed_time(t_end), time.perf_counter() - wall0,
+                [a.elapsed_time(b2) for a, b2 in ev])
+
+    runs = []
+    for r in range(args.repeats):
+        runs.append(fused_run())
+        log(f"[bench] fused run {r}: {N * args.steps / (runs[-1][0] / 1e3) / 1e6:.1f} M env-steps/s")
+    run_ms = [x[0] for x in runs]
+    med = int(np.argsort(run_ms)[len(run_ms) // 2])
+    fused_ms, wall, _ = runs[med]
+    # the K-step launches of every run (the remainder launch is left out)
+    launch_ms = np.array([d for x in runs for d in x[2]])
+    steps_fused = args.steps
     fused_rate = N * steps_fused / (fused_ms / 1e3)
     assert env.status() == 0
     hits = env.debug_hits().to(torch.int32)
@@ -338,6 +367,10 @@ def main():
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(cfg, maps, w, b, eps, args.cpu_seconds)
+        one = cpu_baseline(cfg, maps, w, b, eps, args.cpu_seconds / 3, cores=1)
+        cpu["single_thread_value"] = one["value"]
+        cpu["cpu_model"] = cpu_model()
+        cpu["nproc"] = os.cpu_count()
         precision = greedy_agreement(env, obs, dims, w, b)
         log(f"[bench] precision: {precision}")
 
@@ -347,7 +380,9 @@ def main():
         "unit": "env-steps/s",
         "n_gpus": 1,
         "steps": steps_fused,
-        "warmup": n_warm * K,
+        "warmup": n_warm * K + rem,
+        "repeats": args.repeats,
+        "run_values": [round(N * steps_fused / (m / 1e3), 1) for m in run_ms],
         "ms_per_step": round(fused_ms / steps_fused, 6),
         "higher_is_better": True,
         "scaling": "weak",

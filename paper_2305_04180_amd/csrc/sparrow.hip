@@ -30,25 +30,27 @@ using namespace sp;
 // Kernels
 // ===========================================================================
 
-// One 32-bit word per thread: map m's packed row r (= y + 1), word c covers
-// x + 1 in [32c, 32c + 32). Bits outside [0, W) x [0, H) are set.
+// One 32-bit word per thread. Word 0 of map m is all set; word 1 + r * wpr + c
+// holds row y = r - 1, cells x = 32 c .. 32 c + 31 (bit x & 31). Bits of cells
+// outside [0, W) x [0, H) are set (the ring, and the padding columns >= W
+// that double as column -1 of the next row).
 __global__ void k_pack(const uint8_t* __restrict__ cells, const int64_t* __restrict__ offs,
                        const MapMeta* __restrict__ meta, uint32_t* __restrict__ words,
                        int32_t n_maps) {
   const int m = blockIdx.y + blockIdx.z * 65535;
   if (m >= n_maps) return;
   const MapMeta mm = meta[m];
-  const int total = mm.wpr * (mm.H + 2);
+  const int total = 1 + mm.wpr * (mm.H + 2);
   const int padded = (total + 3) & ~3;
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < padded; w += gridDim.x * blockDim.x) {
     uint32_t v = 0xFFFFFFFFu;
-    if (w < total) {
-      const int row = w / mm.wpr, cw = w % mm.wpr;
+    if (w >= 1 && w < total) {
+      const int row = (w - 1) / mm.wpr, cw = (w - 1) % mm.wpr;
       const int y = row - 1;
       v = 0u;
       for (int b = 0; b < 32; ++b) {
-        const int x = cw * 32 + b - 1;
-        const bool occ = x < 0 || x >= mm.W || y < 0 || y >= mm.H ||
+        const int x = cw * 32 + b;
+        const bool occ = x >= mm.W || y < 0 || y >= mm.H ||
                          cells[offs[m] + (int64_t)y * mm.W + x] != 0;
         v |= (occ ? 1u : 0u) << b;
       }
@@ -89,7 +91,7 @@ __device__ __forceinline__ void stage_maps(const Params& p, int grp, uint32_t* l
 __device__ __forceinline__ Slot make_slot(const Params& p, const int4& sl, const uint32_t* lds) {
   const MapMeta mm = p.meta[sl.y];
   Slot m;
-  m.w1 = lds + sl.z + mm.wpr;
+  m.w1 = lds + sl.z + 1 + mm.wpr;
   m.W = mm.W;
   m.H = mm.H;
   m.wpr = mm.wpr;
@@ -178,7 +180,13 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if constexpr (kQ) eps = p.eps[i];
     }
     uint16_t* act_in = nullptr;
+    W3Frag<QC> w3;
+    // Per-step random draws (VEM exploration, or the uniform actions) are
+    // taken L steps at a time: lane q of the env draws for step g + q, and
+    // step t reads lane t % L of its env.
+    int draws = -1;
     if constexpr (kQ) {
+      qnet_load_w3<QC>(qp, threadIdx.x, w3);
       if (slot < kQRows) act_in = qnet_input_row(qp, lds, slot);
       // the current observation feeds the first actor step
       if (live)
@@ -187,15 +195,25 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
     __syncthreads();
     for (int t = 0; t < p.K_steps; ++t) {
       const uint32_t g = p.g + (uint32_t)t;
+      if (t % L == 0 && live) {
+        const uint32_t gq = g + (uint32_t)ln.q;
+        if constexpr (kQ) {
+          draws = vem_draw(i, gq, eps, p.key0, p.key1);
+        } else {
+          const U4 w = philox((uint32_t)i, gq, kActionUniform, 0u, p.key0, p.key1);
+          draws = scale_u32(w.x, kNumActions);
+        }
+      }
+      const int draw = __shfl(draws, (threadIdx.x & 63 & ~(L - 1)) + t % L);
       int a_hat = 0;
       if constexpr (kQ) {
         // barriers inside; the wave's env columns are slot % 16
-        const f32x4 tile = qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);
-        const int a_q = qnet_vem_action(qp, tile, slot & 15, i, g, eps, p.key0, p.key1);
-        if (live) a_hat = a_q;
+        const f32x4 tile = qnet_forward_group<QC>(qp, qw, w3, lds, threadIdx.x);
+        float qa[kNumActions];
+        const int greedy = qnet_q_values(qp, tile, slot & 15, qa);
+        if (live) a_hat = draw >= 0 ? draw : greedy;
       } else {
-        const U4 w = philox((uint32_t)i, g, kActionUniform, 0u, p.key0, p.key1);
-        a_hat = scale_u32(w.x, kNumActions);
+        a_hat = draw;
       }
       if (live) {
         const StepOut o = step_env<L>(p, ln, m, e, a_hat);
@@ -217,7 +235,10 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
           if (p.r_actions) p.r_actions[o_idx] = a_hat;
         }
       }
-      if constexpr (kQ) __syncthreads();
+      if constexpr (kQ) {
+        qnet_load_w3<QC>(qp, threadIdx.x, w3);  // next step's, in the barrier's shadow
+        __syncthreads();
+      }
     }
     if (live && ln.q == 0) store_env(p.s, i, e);
   }
@@ -235,6 +256,8 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
   extern __shared__ uint32_t lds[];
   typename QC::Weights qw;
   qw.load(qp, threadIdx.x);
+  W3Frag<QC> w3;
+  qnet_load_w3<QC>(qp, threadIdx.x, w3);
   {
     const int nw = (int)qnet_lds_bytes(qp) / 4;
     for (int k = threadIdx.x; k < nw; k += blockDim.x) lds[k] = 0u;
@@ -247,7 +270,7 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
       row[k] = (r0 + r < n && k < qp.d0) ? bf16_rne(obs[(size_t)(r0 + r) * qp.d0 + k]) : 0;
     }
     __syncthreads();
-    const f32x4 tile = qnet_forward_group<QC>(qp, qw, lds, threadIdx.x);
+    const f32x4 tile = qnet_forward_group<QC>(qp, qw, w3, lds, threadIdx.x);
     // wave 0 reports the 16 rows; lane r < 16 takes row r
     const int r = threadIdx.x & 15;
     float qa[kNumActions];
@@ -339,7 +362,7 @@ namespace {
 
 int obs_dim(const sparrow_env* e) { return e->cfg.n_rays + 4; }
 
-int words_of(const MapMeta& m) { return ((m.wpr * (m.H + 2)) + 3) & ~3; }
+int words_of(const MapMeta& m) { return (1 + m.wpr * (m.H + 2) + 3) & ~3; }
 
 // Envs sorted by packed size (largest first), packed greedily into groups of at
 // most epw envs whose maps fit the LDS budget together.
@@ -555,7 +578,7 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
     MapMeta mm;
     mm.W = maps->width[m];
     mm.H = maps->height[m];
-    mm.wpr = (mm.W + 2 + 31) / 32;
+    mm.wpr = (mm.W + 1 + 31) / 32;
     mm.off = (uint32_t)total_words;
     total_words += (uint64_t)words_of(mm);
     e->h_meta[m] = mm;
@@ -633,7 +656,7 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
     int max_words = 0;
     for (auto& mm : e->h_meta) max_words = std::max(max_words, words_of(mm));
     const int gy = std::min(maps->n_maps, 65535), gz = (maps->n_maps + 65534) / 65535;
-    dim3 grid((max_words + 255) / 256, gy, gz);
+    dim3 grid((max_words + 255) / 256, gy, gz);  // max_words covers the padding
     hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, nullptr, d_cells, d_offs, e->meta, e->words,
                        maps->n_maps);
     CREATE_TRY(hipGetLastError());

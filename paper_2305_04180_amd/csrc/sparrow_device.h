@@ -125,7 +125,7 @@ struct State {  // structure of arrays, [N] each
   uint32_t* ctl;  // delay | q0 << 8 | q1 << 16
 };
 
-struct MapMeta {  // packed map m: words [off, off + (H + 2) * wpr)
+struct MapMeta {  // packed map m: words [off, off + 1 + (H + 2) * wpr), 16-byte padded
   uint32_t off;
   int32_t W, H, wpr;
 };
@@ -224,20 +224,23 @@ __device__ __forceinline__ int med3i(int x, int lo, int hi) {
   return r;
 }
 
-// A map slot in LDS: bit (ix + 1) of row (iy + 1), ix in [-1, W], iy in [-1, H];
-// the ring around the map is set, so a coordinate clamped to the ring reads as
-// occupied: outside the map counts as an obstacle. w1 points at row 0 (y = 0),
-// so a clamped row index of -1 addresses the ring row in front of it.
+// A map slot in LDS. Row y (y = -1..H) is n = ceil((W + 1) / 32) words; cell
+// x >= 0 is bit x & 31 of word x >> 5 of its row, and column -1 is bit 31 of
+// the previous row's last word (a column >= W, so set), with one set word in
+// front of row -1. Every bit outside [0, W) x [0, H) is set, so a coordinate
+// clamped to [-1, W] x [-1, H] reads as occupied: outside the map counts as
+// an obstacle. w1 points at word 0 of row 0; the word of (x, y) is
+// w1[y * n + (x >> 5)] with an arithmetic shift, its bit x & 31.
 struct Slot {
   const uint32_t* w1;
   int32_t W, H, wpr;
-  // LDS byte address of cell (ix, iy)'s word and its bit, clamped to the ring
   __device__ __forceinline__ const uint32_t* word_of(int ix, int iy, int& bit) const {
     ix = med3i(ix, -1, W);
     iy = med3i(iy, -1, H);
-    bit = ix + 1;
-    const char* row = reinterpret_cast<const char*>(w1) + __mul24(iy, wpr * 4);
-    return reinterpret_cast<const uint32_t*>(row + ((uint32_t)bit >> 5) * 4u);
+    bit = ix;  // the bit-field extract uses its low five bits
+    int w = __mul24(iy, wpr) + (ix >> 5);
+    asm("" : "+v"(w));  // keep the word index whole: one shift-add forms the address
+    return w1 + w;
   }
   __device__ __forceinline__ bool occ(int ix, int iy) const {
     int bit;
@@ -246,46 +249,6 @@ struct Slot {
   }
 };
 
-// Exact disk test over the cell squares meeting [px - r, px + r] x [py - r, py + r].
-__device__ __forceinline__ bool collides_cells(const Slot& m, float px, float py, float r,
-                                               int i0, int i1, int j0, int j1) {
-  const float r2 = r * r;
-  bool hit = false;
-  for (int j = j0; j <= j1; ++j)
-    for (int i = i0; i <= i1; ++i) {
-      if (!m.occ(i, j)) continue;
-      const float fi = (float)i, fj = (float)j;
-      const float dx = fmaxf(fmaxf(fi - px, 0.0f), px - (fi + 1.0f));
-      const float dy = fmaxf(fmaxf(fj - py, 0.0f), py - (fj + 1.0f));
-      const float d2 = dx * dx + dy * dy;
-      hit |= d2 <= r2;
-    }
-  return hit;
-}
-
-// Disk of radius r at (px, py) against every occupied cell square that meets
-// the closed box [px - r, px + r] x [py - r, py + r] (distance <= r collides).
-// One lane. When the box lies inside the map, its bits are first read a row
-// at a time (at most two words per row): an empty box cannot collide.
-__device__ __forceinline__ bool collides_seq(const Slot& m, float px, float py, float r) {
-  const int i0 = (int)ceilf(px - r) - 1, i1 = (int)floorf(px + r);
-  const int j0 = (int)ceilf(py - r) - 1, j1 = (int)floorf(py + r);
-  if (i0 >= 0 && j0 >= 0 && i1 < m.W && j1 < m.H) {
-    const int b0 = i0 + 1, nb = i1 - i0 + 1;  // padded bit columns [b0, b0 + nb)
-    const int wlo = b0 >> 5, sh = b0 & 31;
-    const uint64_t mask = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
-    uint64_t acc = 0;
-    for (int j = j0; j <= j1; ++j) {
-      // the second word may be the next row's first one: in range, masked off
-      const uint32_t* row = m.w1 + __mul24(j, m.wpr) + wlo;
-      const uint64_t v = (uint64_t)row[0] | ((uint64_t)row[1] << 32);
-      acc |= (v >> sh) & mask;
-    }
-    if (acc == 0) return false;
-  }
-  return collides_cells(m, px, py, r, i0, i1, j0, j1);
-}
-
 // Same test with the cells spread over the env's L lanes.
 template <int L>
 __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, float px,
@@ -293,16 +256,22 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
   const float r2 = r * r;
   const int i0 = (int)ceilf(px - r) - 1, i1 = (int)floorf(px + r);
   const int j0 = (int)ceilf(py - r) - 1, j1 = (int)floorf(py + r);
-  const int nx = i1 - i0 + 1, nc = nx * (j1 - j0 + 1);
-  bool hit = false;
-  for (int c = ln.q; c < nc; c += L) {
-    const int i = i0 + c % nx, j = j0 + c / nx;
-    if (!m.occ(i, j)) continue;
+  const int nx = i1 - i0 + 1, ny = j1 - j0 + 1, nc = nx * ny;
+  auto test = [&](int i, int j) {
+    if (!m.occ(i, j)) return false;
     const float fi = (float)i, fj = (float)j;
     const float dx = fmaxf(fmaxf(fi - px, 0.0f), px - (fi + 1.0f));
     const float dy = fmaxf(fmaxf(fj - py, 0.0f), py - (fj + 1.0f));
     const float d2 = dx * dx + dy * dy;
-    hit |= d2 <= r2;
+    return d2 <= r2;
+  };
+  bool hit = false;
+  if (L == 64 && nx <= 8 && ny <= 8) {
+    // one cell per lane: lane q takes column q & 7, row q >> 3 of the box
+    const int cx = ln.q & 7, cy = ln.q >> 3;
+    if (cx < nx && cy < ny) hit = test(i0 + cx, j0 + cy);
+  } else {
+    for (int c = ln.q; c < nc; c += L) hit |= test(i0 + c % nx, j0 + c / nx);
   }
   return ln.ballot(hit) != 0ull;
 }
@@ -489,8 +458,9 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
 // ------------------------------------------------------------------------
 // AutoReset of one env (Sec. 3.2.5) with per-episode randomisation (Sec.
 // 3.2.4): physics draws, then start and target as the first collision-free
-// candidate cell centre in counter order; the env's lanes test candidates
-// side by side and a ballot takes the lowest accepted one.
+// candidate cell centre in counter order. Candidates are tested one after
+// the other (most are accepted within a few draws), each by the env's L
+// lanes splitting the disk's cells as in the per-step collision test.
 // Returns false when no candidate was accepted.
 // ------------------------------------------------------------------------
 template <int L>
@@ -512,26 +482,28 @@ __device__ bool reset_env(const Params& p, const Lanes<L>& ln, const Slot& m, En
 #pragma unroll
   for (int which = 0; which < 2; ++which) {
     const uint32_t purpose = which == 0 ? kResetStart : kResetTarget;
-    const U4 w0 = philox((uint32_t)i, g, purpose, 0u, p.key0, p.key1);
-    float bx = (float)scale_u32(w0.x, W) + 0.5f, by = (float)scale_u32(w0.y, H) + 0.5f;
+    float bx = 0.0f, by = 0.0f;
     bool found = false;
-    for (int n0 = 0; n0 < 16 * 64 && !found; n0 += L) {
-      const uint32_t n = (uint32_t)(n0 + ln.q);
+    for (uint32_t n = 0; n < 16u * 64u; ++n) {  // the same draw in every lane
       const U4 w = philox((uint32_t)i, g, purpose, n, p.key0, p.key1);
       const float px = (float)scale_u32(w.x, W) + 0.5f;
       const float py = (float)scale_u32(w.y, H) + 0.5f;
-      bool acc = !collides_seq(m, px, py, p.robot_r);
+      if (n == 0) {
+        bx = px;
+        by = py;
+      }
+      bool acc = true;
       if (which == 1) {
         const float dx = px - pos[0][0], dy = py - pos[0][1];
         const float d2 = dx * dx + dy * dy;
-        acc = acc && d2 > ra2;
+        acc = d2 > ra2;
       }
-      const uint64_t bal = ln.ballot(acc);
-      if (bal) {
-        const int src = __builtin_ctzll(bal);
-        bx = __shfl(px, src);
-        by = __shfl(py, src);
+      acc = acc && !collides_env<L>(ln, m, px, py, p.robot_r);
+      if (acc) {
+        bx = px;
+        by = py;
         found = true;
+        break;
       }
     }
     ok = ok && found;

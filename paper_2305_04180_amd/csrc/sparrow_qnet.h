@@ -122,6 +122,7 @@ struct QNetCfg {
 
 struct NoQ {
   static constexpr bool kOn = false;
+  static constexpr int K3 = 1;
   struct Weights {
     __device__ __forceinline__ void load(const QParams&, int) {}
   };
@@ -165,24 +166,37 @@ __device__ __forceinline__ void qnet_layer(const bf16x8 (&a)[T][KS], const f32x4
   }
 }
 
+// Layer-3 weight fragments of this lane (8 KB shared by the workgroup,
+// L1-resident). The rollout loads them while it waits at the end of a step,
+// so the reads are done when the next forward pass needs them.
+template <class QC>
+struct W3Frag {
+  bf16x8 a[QC::K3];
+};
+
+template <class QC>
+__device__ __forceinline__ void qnet_load_w3(const QParams& q, int tid, W3Frag<QC>& f) {
+  if constexpr (QC::kOn) {
+    const int l = tid & 63;
+    const int env = l & 15, kq = (l >> 4) * 8;
+#pragma unroll
+    for (int ks = 0; ks < QC::K3; ++ks)
+      f.a[ks] = *reinterpret_cast<const bf16x8*>(q.w3 + (size_t)env * q.h2 + ks * 32 + kq);
+  }
+}
+
 // Forward pass over the 16 input rows in LDS region A (the caller has made
 // them visible with a barrier). Returns this lane's layer-3 tile: Q[a][env]
 // for actions a = 4 * (lane / 16) + 0..3 and env = lane % 16.
 template <class QC>
 __device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
                                                     const typename QC::Weights& W,
-                                                    uint32_t* lds, int tid) {
+                                                    const W3Frag<QC>& w3, uint32_t* lds,
+                                                    int tid) {
   f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
   if constexpr (QC::kOn) {
     const int w = tid >> 6, l = tid & 63;
     const int env = l & 15, kq = (l >> 4) * 8;
-    // layer-3 weights (8 KB shared by the workgroup, L1-resident): loaded
-    // here so the reads overlap layers 1 and 2 and the registers are live
-    // only during the forward pass
-    bf16x8 a3[QC::K3];
-#pragma unroll
-    for (int ks = 0; ks < QC::K3; ++ks)
-      a3[ks] = *reinterpret_cast<const bf16x8*>(q.w3 + (size_t)env * q.h2 + ks * 32 + kq);
     uint16_t* ra = qnet_region_a(q, lds);
     uint16_t* rb = qnet_region_b(q, lds);
     uint16_t* rc = qnet_region_c(q, lds);
@@ -195,7 +209,7 @@ __device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
 #pragma unroll
     for (int ks = 0; ks < QC::K3; ++ks) {
       const bf16x8 b = *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq);
-      acc = mfma16x16x32(a3[ks], b, acc);
+      acc = mfma16x16x32(w3.a[ks], b, acc);
     }
   }
   return acc;
@@ -217,18 +231,19 @@ __device__ __forceinline__ int qnet_q_values(const QParams& q, const f32x4& tile
 }
 
 // VEM (Sec. 3.1.1): with probability eps the greedy action is replaced by a
-// uniform random one; the draw is Philox (env, step, EXPLORE, 0).
-__device__ __forceinline__ int vem_select(int greedy, int env, uint32_t g, float eps,
-                                          uint32_t key0, uint32_t key1) {
+// uniform random one; the draw is Philox (env, step, EXPLORE, 0). It does not
+// depend on Q, so the rollout draws it ahead of the forward pass. Returns the random
+// action, or -1 to keep the greedy one.
+__device__ __forceinline__ int vem_draw(int env, uint32_t g, float eps, uint32_t key0,
+                                        uint32_t key1) {
   const U4 w = philox((uint32_t)env, g, kExplore, 0u, key0, key1);
-  return unit24(w.x) < eps ? scale_u32(w.y, kNumActions) : greedy;
+  return unit24(w.x) < eps ? scale_u32(w.y, kNumActions) : -1;
 }
 
-__device__ __forceinline__ int qnet_vem_action(const QParams& q, const f32x4& tile, int row,
-                                               int env, uint32_t g, float eps, uint32_t key0,
-                                               uint32_t key1) {
-  float qa[kNumActions];
-  return vem_select(qnet_q_values(q, tile, row, qa), env, g, eps, key0, key1);
+__device__ __forceinline__ int vem_select(int greedy, int env, uint32_t g, float eps,
+                                          uint32_t key0, uint32_t key1) {
+  const int d = vem_draw(env, g, eps, key0, key1);
+  return d >= 0 ? d : greedy;
 }
 
 }  // namespace sp

@@ -105,6 +105,25 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _buf(t, dtype, numel, device, name, nullable=False):
+    """Check a caller's buffer before its pointer reaches a kernel: the
+    C-ABI takes raw pointers and cannot see sizes, so a short, strided or
+    mistyped tensor is rejected here rather than written out of bounds."""
+    if t is None:
+        if nullable:
+            return None
+        raise ValueError(f"{name}: buffer required")
+    if not hasattr(t, "data_ptr") or t.dtype != dtype:
+        raise ValueError(f"{name}: expected a {dtype} tensor, got {getattr(t, 'dtype', type(t))}")
+    if t.device != device:
+        raise ValueError(f"{name}: expected device {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: needs {numel} elements, has {t.numel()}")
+    return t
+
+
 def make_config(cfg: dict) -> Config:
     c = Config()
     c.n_envs, c.n_rays, c.n_actions = cfg["n_envs"], cfg["n_rays"], N_ACTIONS
@@ -158,21 +177,29 @@ class Env:
             pass
 
     # -- RL-API ---------------------------------------------------------------
+    def _b(self, t, dtype, numel, name, nullable=False):
+        return _buf(t, dtype, numel, self.device, name, nullable)
+
     def reset(self, obs=None):
-        obs = self.obs if obs is None else obs
+        t = self.torch
+        obs = self._b(self.obs if obs is None else obs, t.float32, self.n * self.obs_dim, "obs")
         _check(lib().sparrow_reset(self._h, _ptr(obs)))
         return obs
 
     def step(self, actions, obs=None, reward=None, done=None, flags=None, final_obs=None):
-        obs = self.obs if obs is None else obs
-        reward = self.reward if reward is None else reward
-        done = self.done if done is None else done
+        t, n, D = self.torch, self.n, self.obs_dim
+        actions = self._b(actions, t.int32, n, "actions")
+        obs = self._b(self.obs if obs is None else obs, t.float32, n * D, "obs")
+        reward = self._b(self.reward if reward is None else reward, t.float32, n, "reward")
+        done = self._b(self.done if done is None else done, t.uint8, n, "done")
+        flags = self._b(flags, t.uint8, n, "flags", nullable=True)
+        final_obs = self._b(final_obs, t.float32, n * D, "final_obs", nullable=True)
         _check(lib().sparrow_step(self._h, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done),
                                   _ptr(flags), _ptr(final_obs)))
         return obs, reward, done
 
     def random_actions(self, out=None):
-        out = self.actions if out is None else out
+        out = self._b(self.actions if out is None else out, self.torch.int32, self.n, "actions")
         _check(lib().sparrow_random_actions(self._h, _ptr(out)))
         return out
 
@@ -180,22 +207,34 @@ class Env:
     def set_qnet(self, dims, w_bf16, b_f32, eps):
         torch = self.torch
         d = (C.c_int32 * 4)(*[int(x) for x in dims])
+        nw = sum(int(dims[k]) * int(dims[k + 1]) for k in range(3))
+        nb = int(dims[1]) + int(dims[2]) + int(dims[3])
         w = torch.as_tensor(np.asarray(w_bf16).view(np.int16)).to(self.device)
         b = torch.as_tensor(np.asarray(b_f32, np.float32)).to(self.device)
         e = torch.as_tensor(np.asarray(eps, np.float32)).to(self.device)
+        for t, k, name in ((w, nw, "weights"), (b, nb, "biases"), (e, self.n, "eps")):
+            if t.numel() != k:
+                raise ValueError(f"{name}: expected {k} values for dims {tuple(dims)}, got {t.numel()}")
         _check(lib().sparrow_set_qnet(self._h, d, _ptr(w), _ptr(b), _ptr(e)))
         self._qkeep = (w, b, e)
 
     def qnet_forward(self, obs, q=None, greedy=None):
         torch = self.torch
         n = obs.shape[0]
+        self._b(obs, torch.float32, n * self.obs_dim, "obs")
+        if obs.dim() != 2 or obs.shape[1] != self.obs_dim:
+            raise ValueError(f"obs: expected shape [n, {self.obs_dim}], got {tuple(obs.shape)}")
         q = torch.zeros(n, N_ACTIONS, dtype=torch.float32, device=self.device) if q is None else q
         greedy = torch.zeros(n, dtype=torch.int32, device=self.device) if greedy is None else greedy
+        self._b(q, torch.float32, n * N_ACTIONS, "q")
+        self._b(greedy, torch.int32, n, "greedy")
         _check(lib().sparrow_qnet_forward(self._h, _ptr(obs), n, _ptr(q), _ptr(greedy)))
         return q, greedy
 
     def act(self, obs, actions=None):
-        actions = self.actions if actions is None else actions
+        t = self.torch
+        obs = self._b(obs, t.float32, self.n * self.obs_dim, "obs")
+        actions = self._b(self.actions if actions is None else actions, t.int32, self.n, "actions")
         _check(lib().sparrow_act(self._h, _ptr(obs), _ptr(actions)))
         return actions
 
@@ -206,6 +245,11 @@ class Env:
         reward = torch.zeros(K, self.n, dtype=torch.float32, device=dev) if reward is None else reward
         done = torch.zeros(K, self.n, dtype=torch.uint8, device=dev) if done is None else done
         obs = self.obs if obs is None else obs
+        n = self.n
+        self._b(actions, torch.int32, K * n, "actions", nullable=True)
+        self._b(reward, torch.float32, K * n, "reward")
+        self._b(done, torch.uint8, K * n, "done")
+        self._b(obs, torch.float32, n * self.obs_dim, "obs")
         _check(lib().sparrow_rollout(self._h, K, int(bool(use_qnet)), _ptr(actions),
                                      _ptr(reward), _ptr(done), _ptr(obs)))
         return actions, reward, done, obs

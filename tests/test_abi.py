@@ -113,3 +113,29 @@ def test_vem_epsilon_binding_matches_schedule():
         a = sparrow.vem_epsilon(n, m, 0.01, 0.29)
         b = oracle.vem_epsilon(n, m, 0.01, 0.29)
         assert np.array_equal(a, b), (n, m)
+
+
+def test_product_path_never_touches_the_oracle():
+    """The library sources and the binding name no oracle file or symbol."""
+    pkg = os.path.join(ROOT, "paper_2305_04180_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower() or f == "inputs.py" and "import oracle" not in text, f
+                assert "orc_" not in text, f
+
+
+def test_binding_rejects_bad_buffers():
+    """Short, strided, mistyped or misplaced buffers never reach the C-ABI."""
+    import torch
+    cpu = torch.device("cpu")
+    ok = torch.zeros(8, dtype=torch.float32)
+    assert sparrow._buf(ok, torch.float32, 8, cpu, "x") is ok
+    assert sparrow._buf(None, torch.float32, 8, cpu, "x", nullable=True) is None
+    for bad, kw in ((None, {}), (torch.zeros(7), {}), (torch.zeros(8, dtype=torch.float64), {}),
+                    (torch.zeros(4, 4)[:, ::2], {}), (np.zeros(8, np.float32), {})):
+        with pytest.raises(ValueError):
+            sparrow._buf(bad, torch.float32, 8, cpu, "x", **kw)
+    with pytest.raises(ValueError):
+        sparrow._buf(ok, torch.float32, 8, torch.device("cuda", 0), "x")

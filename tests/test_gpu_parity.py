@@ -312,3 +312,39 @@ def test_autotune_preserves_state(torch_gpu):
     assert "chosen" in rep and len(rep["step"]) == 12
     assert env.global_step == orc.global_step
     run_steps(env, orc, 20, torch, noisy=True, check_state_every=5, where="after autotune")
+
+
+def test_fused_rollout_64_rays_obs68(torch_gpu):
+    """The 68-wide observation actor (64 rays): Q-network 68-256-256-7 on
+    identical observations, and a fused rollout on uneven map sides."""
+    import oracle
+    torch = torch_gpu
+    cfg = inputs.workload("c3", n_envs=21)
+    K = 12
+    banner(f"fused rollout, 64 rays, obs 68, N=21, K={K}")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch)
+    dims, w, b, eps = _qnet_setup(cfg, env)
+    assert dims[0] == 68
+    env.reset()
+    o_obs, _ = orc.reset()
+    q, greedy = env.qnet_forward(env.obs)
+    torch.cuda.synchronize()
+    q64 = oracle.qnet_f64(dims, w, b, o_obs)
+    assert (to_np(greedy) == q64.argmax(1)).mean() >= 0.9
+    assert np.abs(to_np(q).astype(np.float64) - q64).max() < 0.05
+    acts, rew, done, obs = env.rollout(K, use_qnet=True)
+    torch.cuda.synchronize()
+    acts, rew, done = to_np(acts), to_np(rew), to_np(done)
+    for t in range(K):
+        a_vem, ex = orc.vem(oracle.qnet_f64(dims, w, b, o_obs), eps)
+        exb = ex.astype(bool)
+        compare_exact(acts[t][exb], a_vem[exb], "explored actions", f"t={t}")
+        r = orc.step(acts[t])
+        compare_exact(rew[t], r["reward"], "reward", f"t={t}")
+        compare_exact(done[t], r["done"], "done", f"t={t}")
+        o_obs = r["obs"]
+    compare_obs(to_np(obs), o_obs, env.n_rays, True, "obs68 final")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, "obs68 final")
