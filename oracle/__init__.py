@@ -16,6 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "sparrow_oracle.c")
+SRC_RING = os.path.join(HERE, "ring_oracle.c")
 
 STOP = 7
 N_ACTIONS = 7
@@ -30,7 +31,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with strict IEEE binary32 semantics."""
     if force or not os.path.exists(LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-o", LIB_PATH, SRC, "-lm"]
+               "-fPIC", "-shared", "-o", LIB_PATH, SRC, SRC_RING, "-lm"]
         subprocess.check_call(cmd)
     return LIB_PATH
 
@@ -104,6 +105,27 @@ def lib():
         L.orc_vem.argtypes = [P, P, C.c_int32, P, P, P]
         L.orc_uniform_actions.argtypes = [P, P]
         L.orc_vem_epsilon.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, P]
+        L.orc_ring_create.restype = P
+        L.orc_ring_create.argtypes = [C.c_int64, C.c_int32, C.c_uint64]
+        L.orc_ring_destroy.argtypes = [P]
+        L.orc_ring_size.restype = C.c_int64
+        L.orc_ring_size.argtypes = [P]
+        L.orc_ring_head.restype = C.c_int64
+        L.orc_ring_head.argtypes = [P]
+        L.orc_ring_push.restype = C.c_int32
+        L.orc_ring_push.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.orc_ring_gather.restype = C.c_int32
+        L.orc_ring_gather.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.orc_ring_sample.restype = C.c_int32
+        L.orc_ring_sample.argtypes = [P, C.c_int32, C.c_uint32, P, P, P, P, P, P]
+        L.orc_f16_rne.restype = C.c_uint16
+        L.orc_f16_rne.argtypes = [C.c_float]
+        L.orc_f16_to_f32.restype = C.c_float
+        L.orc_f16_to_f32.argtypes = [C.c_uint16]
+        L.orc_quant_u8.restype = C.c_uint8
+        L.orc_quant_u8.argtypes = [C.c_float]
+        L.orc_dequant_u8.restype = C.c_float
+        L.orc_dequant_u8.argtypes = [C.c_uint8]
         _lib = L
     return _lib
 
@@ -286,3 +308,78 @@ class Oracle:
         ex = np.zeros(self.n, np.uint8)
         lib().orc_vem(self._h, _p(q), q.shape[1], _p(eps), _p(a), _p(ex))
         return a, ex
+
+
+# ---------------------------------------------------------------------------
+# Experience buffer (Sec. 3.1.2: Alg. 1 step 5 adds, Alg. 2 step 1 samples).
+# Storage format and sampling rule: ring_oracle.h.
+# ---------------------------------------------------------------------------
+def f16_rne(f: float) -> int:
+    return int(lib().orc_f16_rne(C.c_float(f)))
+
+
+def f16_to_f32(h: int) -> float:
+    return float(lib().orc_f16_to_f32(C.c_uint16(h)))
+
+
+def quant_u8(o: float) -> int:
+    return int(lib().orc_quant_u8(C.c_float(o)))
+
+
+def dequant_u8(q: int) -> float:
+    return float(lib().orc_dequant_u8(C.c_uint8(q)))
+
+
+class Ring:
+    """Ring of `capacity` transitions of observations with n_rays ranges."""
+
+    def __init__(self, capacity: int, n_rays: int, seed: int):
+        self.capacity, self.n_rays, self.D = int(capacity), int(n_rays), int(n_rays) + 4
+        self._h = lib().orc_ring_create(self.capacity, self.n_rays, int(seed))
+        if not self._h:
+            raise MemoryError("orc_ring_create failed")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_ring_destroy(self._h)
+            self._h = None
+
+    @property
+    def size(self) -> int:
+        return int(lib().orc_ring_size(self._h))
+
+    @property
+    def head(self) -> int:
+        return int(lib().orc_ring_head(self._h))
+
+    def push(self, s, a, r, s_next, done, s_final=None):
+        n = len(a)
+        s = np.ascontiguousarray(s, np.float32).reshape(n, self.D)
+        s_next = np.ascontiguousarray(s_next, np.float32).reshape(n, self.D)
+        sf = None if s_final is None else np.ascontiguousarray(s_final, np.float32).reshape(n, self.D)
+        a = np.ascontiguousarray(a, np.int32)
+        r = np.ascontiguousarray(r, np.float32)
+        d = np.ascontiguousarray(done, np.uint8)
+        rc = lib().orc_ring_push(self._h, n, _p(s), _p(a), _p(r), _p(s_next), _p(sf), _p(d))
+        if rc:
+            raise ValueError("push rejected")
+
+    def _outs(self, n):
+        return (np.zeros((n, self.D), np.float32), np.zeros(n, np.int32), np.zeros(n, np.float32),
+                np.zeros((n, self.D), np.float32), np.zeros(n, np.uint8))
+
+    def gather(self, slots):
+        slots = np.ascontiguousarray(slots, np.int64)
+        s, a, r, sn, d = self._outs(len(slots))
+        rc = lib().orc_ring_gather(self._h, len(slots), _p(slots), _p(s), _p(a), _p(r), _p(sn), _p(d))
+        if rc:
+            raise IndexError("slot outside the stored range")
+        return s, a, r, sn, d
+
+    def sample(self, B: int, draw: int):
+        s, a, r, sn, d = self._outs(B)
+        idx = np.zeros(B, np.int64)
+        rc = lib().orc_ring_sample(self._h, B, draw, _p(s), _p(a), _p(r), _p(sn), _p(d), _p(idx))
+        if rc:
+            raise ValueError("empty ring")
+        return s, a, r, sn, d, idx
