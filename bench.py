@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=512)
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the full-collection leg (32768 envs, ring buffer)")
+    ap.add_argument("--c5-steps", type=int, default=2048)
+    ap.add_argument("--c5-warmup", type=int, default=64)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -149,6 +153,106 @@ def cpu_baseline(cfg, maps, w, b, eps, seconds, cores=None):
                       f"FP64 Q-network + VEM + FP32 step, {dt:.1f} s"}
 
 
+def collection_c5(cfg, maps, steps, warmup):
+    """The full collection loop (Alg. 1 steps 2-5 with Alg. 2 step 1's
+    sampling): per step the 68-512-512-7 actor + VEM (separate kernel), the
+    step with AutoReset, and an add of the N transitions to the 2^22-slot
+    device ring; every 8 steps a uniform mini-batch of 256."""
+    import torch
+    from paper_2305_04180_amd import inputs, sparrow
+    N, nr = cfg["n_envs"], cfg["n_rays"]
+    D = nr + 4
+    dims = cfg["qnet"]
+    w, b, _ = inputs.qnet_weights(dims)
+    eps = sparrow.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
+    env = sparrow.Env(cfg, maps)
+    env.set_qnet(dims, w, b, eps)
+    ring = sparrow.Ring(1 << 22, nr, seed=cfg["seed"])
+    cur = env.reset()
+    env.autotune(steps=4)
+    dev = env.device
+    nxt = torch.zeros_like(cur)
+    fo = torch.zeros_like(cur)
+    act = torch.zeros(N, dtype=torch.int32, device=dev)
+    rew = torch.zeros(N, dtype=torch.float32, device=dev)
+    done = torch.zeros(N, dtype=torch.uint8, device=dev)
+    B = 256
+    sb = (torch.zeros(B, D, device=dev), torch.zeros(B, dtype=torch.int32, device=dev),
+          torch.zeros(B, device=dev), torch.zeros(B, D, device=dev),
+          torch.zeros(B, dtype=torch.uint8, device=dev))
+    sidx = torch.zeros(B, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    state = {"cur": cur, "nxt": nxt, "t": 0}
+
+    def one(ev=None):
+        c, n_, t = state["cur"], state["nxt"], state["t"]
+        marks = [] if ev is not None else None
+
+        def mark():
+            if marks is not None:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(stream)
+                marks.append(e)
+        mark()
+        env.act(c, act)
+        mark()
+        env.step(act, obs=n_, reward=rew, done=done, final_obs=fo)
+        mark()
+        ring.push(c, act, rew, n_, done, fo)
+        mark()
+        if t % 8 == 7:
+            ring.sample(B, t // 8, outs=sb, idx=sidx)
+        mark()
+        state["cur"], state["nxt"], state["t"] = n_, c, t + 1
+        if ev is not None:
+            ev.append(marks)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert env.status() == 0 and ring.status() == 0
+    # per-phase times from a separate pass with events between the calls
+    evs = []
+    for _ in range(64):
+        one(evs)
+    torch.cuda.synchronize()
+    names = ("act", "step", "add", "sample")
+    phase = {k: float(np.mean([m[i].elapsed_time(m[i + 1]) for m in evs])) for i, k in
+             enumerate(names)}
+    mlp_flops = 2.0 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3])
+    map_bytes = env_map_bytes(maps)
+    step_bytes = map_bytes + N * (15 * 4 * 2 + 4 + 4 * D * 2 + 4 + 1 + 2 * nr)
+    add_bytes = N * (3 * 4 * D + 4 + 4 + 1) + N * (2 * nr + 2 * 8 + 1 + 4)
+    return {
+        "metric": "env-steps/s of the full collection loop: actor 68-512-512-7 bf16 + VEM, step, "
+                  "add to a 2^22-slot device ring, 256-draw sample every 8 steps",
+        "value": round(N * steps / (ms / 1e3), 1), "unit": "env-steps/s",
+        "n_envs": N, "steps": steps, "warmup": warmup, "ms_per_step": round(ms / steps, 5),
+        "config": {"workload": "32768 envs, own map each, sides {256,366,512}, 64 rays/270 deg/"
+                               "range 128, full DR, Q-MLP 68-512-512-7 bf16, eps linspace(0.01,0.3)",
+                   "ring_slots": 1 << 22, "bytes_per_transition": 2 * nr + 2 * 8 + 1 + 4 + 0.125,
+                   "minibatch": B, "sample_every": 8},
+        "variants": {"step": env.get_variant(0)},
+        "phase_ms_per_step": {k: round(v, 4) for k, v in phase.items()},
+        "actor_mfma": {"achieved_tflops": round(mlp_flops * N / (phase["act"] / 1e3) / 1e12, 2),
+                       "peak": MI355X_BF16_TFLOPS,
+                       "frac": round(mlp_flops * N / (phase["act"] / 1e3) / 1e12 / MI355X_BF16_TFLOPS, 4)},
+        "step_hbm": {"alg_bytes": int(step_bytes),
+                     "achieved_gbs": round(step_bytes / (phase["step"] / 1e3) / 1e9, 1),
+                     "frac": round(step_bytes / (phase["step"] / 1e3) / 1e9 / MI355X_HBM_GBS, 4)},
+        "add_hbm": {"alg_bytes": int(add_bytes),
+                    "achieved_gbs": round(add_bytes / (phase["add"] / 1e3) / 1e9, 1)},
+    }
+
+
 def kernel_source_hash():
     """sha1 of the HIP sources and the C-ABI header: identifies the kernel
     build that a counter summary in profiles/ was taken from."""
@@ -218,10 +322,18 @@ def main():
 
     from paper_2305_04180_amd import inputs, sparrow
 
-    assert torch.cuda.is_available(), "bench.py needs the GPU"
     if args.copy_mb:
+        assert torch.cuda.is_available(), "bench.py needs the GPU"
         copy_calibration(args.copy_mb)
         return
+    maps5 = None
+    if not args.no_c5:
+        # generated with a process pool before this process touches the GPU
+        cfg5 = inputs.workload("c5")
+        t0 = time.time()
+        maps5 = inputs.make_maps(cfg5, workers=max(1, min(16, os.cpu_count() or 1)))
+        log(f"[bench] c5: {len(maps5.grids)} maps in {time.time() - t0:.1f}s")
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
     cfg = inputs.workload(args.workload)
     N = cfg["n_envs"]
     log(f"[bench] generating {N} maps ({cfg['sides']})")
@@ -374,6 +486,12 @@ def main():
         precision = greedy_agreement(env, obs, dims, w, b)
         log(f"[bench] precision: {precision}")
 
+    c5 = None
+    if maps5 is not None:
+        log("[bench] c5 full collection loop")
+        c5 = collection_c5(cfg5, maps5, args.c5_steps, args.c5_warmup)
+        log(f"[bench] c5: {c5['value'] / 1e6:.1f} M env-steps/s, phases {c5['phase_ms_per_step']}")
+
     out = {
         "metric": "env-steps/s at N=4096, 366^2 maps, 32 rays; fused BF16 vs plain; % HBM/LDS peak",
         "value": round(fused_rate, 1),
@@ -402,6 +520,7 @@ def main():
         "plain_roofline": plain_roofline,
         "cpu_baseline": cpu,
         "precision": precision,
+        "collection_c5": c5,
     }
     print(json.dumps(out), flush=True)
 

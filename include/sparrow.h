@@ -130,11 +130,15 @@ int sparrow_step(sparrow_env *env, const int32_t *actions, float *obs, float *re
 int sparrow_random_actions(sparrow_env *env, int32_t *actions);
 
 /* Install the actor: Q-network dims[4] = {obs_dim, h1, h2, 7} (host), with
- * obs_dim = n_rays + 4, h1 and h2 multiples of 32 up to 512, h1*h2 <= 65536.
- * w_bf16: dev, bf16 bit patterns, [W1 (h1 x obs_dim) | W2 (h2 x h1) |
- * W3 (7 x h2)], each row-major [out][in] (Sec. 4.3.2 fully connected layers
- * with ReLU). b_f32: dev [h1 + h2 + 7]. eps: dev [N] per-env exploration
- * probability of VEM (Sec. 3.1.1). All three are copied. */
+ * obs_dim = n_rays + 4 <= 96 and h1 = h2 in {256, 512}. Width 256 keeps the
+ * weights resident in registers and drives the fused rollout; width 512
+ * streams them from L2 and serves sparrow_act and sparrow_qnet_forward only
+ * (a rollout with use_qnet = 1 returns EUNSUPPORTED). Other shapes return
+ * EUNSUPPORTED. w_bf16: dev, bf16 bit patterns, [W1 (h1 x obs_dim) |
+ * W2 (h2 x h1) | W3 (7 x h2)], each row-major [out][in] (Sec. 4.3.2 fully
+ * connected layers with ReLU). b_f32: dev [h1 + h2 + 7]. eps: dev [N]
+ * per-env exploration probability of VEM (Sec. 3.1.1). All three are
+ * copied. */
 int sparrow_set_qnet(sparrow_env *env, const int32_t *dims, const uint16_t *w_bf16,
                      const float *b_f32, const float *eps);
 
@@ -191,6 +195,51 @@ int sparrow_autotune(sparrow_env *env, int32_t steps, char *report, int32_t repo
 int sparrow_status(sparrow_env *env);
 void sparrow_destroy(sparrow_env *env);
 const char *sparrow_last_error(void);
+
+/* ---- Experience buffer ------------------------------------------------------
+ * The sharer's buffer of Sec. 3.1.2: Alg. 1 step 5 adds the batched
+ * transitions (s, a, r, s', done) and Alg. 2 step 1 samples a mini-batch
+ * (Table 6: 1 M transitions, mini-batch 256). It lives on the device as a
+ * ring of compact transitions, about 2 * n_rays + 21 bytes each:
+ *   ranges (obs entries [0, n_rays))  uint8 level = nearest integer to
+ *       255 * clamp(o, 0, 1) (product rounded to binary32, ties to even),
+ *       read back as the binary32 quotient level / 255;
+ *   the four scalar entries          binary16, round to nearest even, read
+ *       back exactly;
+ *   action int8, reward binary32, done one bit.
+ * A push of n writes slot (head + i) mod capacity for its i-th transition and
+ * advances head by n; size = min(total pushed, capacity). The handle is
+ * bound to the stream given at create, like sparrow_env. */
+typedef struct sparrow_ring sparrow_ring;
+
+/* capacity in [1, 2^26] slots, n_rays in [1, SPARROW_MAX_RAYS]; seed keys
+ * the sampler's Philox. Allocates the ring on the current device. */
+int sparrow_ring_create(int32_t capacity, int32_t n_rays, uint64_t seed, void *hip_stream,
+                        sparrow_ring **out);
+/* Add n <= capacity transitions (n = 0 does nothing and may pass NULL
+ * buffers). dev s, s_next: [n][n_rays + 4] FP32;
+ * a: int32 [n] in [0, 128); r: FP32 [n]; done: uint8 [n]. s_final (dev,
+ * nullable, [n][n_rays + 4]): where done[i] != 0, s' is row i of s_final
+ * (sparrow_step's final_obs, the terminal observation) instead of s_next. */
+int sparrow_ring_push(sparrow_ring *ring, int32_t n, const float *s, const int32_t *a,
+                      const float *r, const float *s_next, const float *s_final,
+                      const uint8_t *done);
+/* Mini-batch of B uniform draws over the stored slots: slot b is
+ * floor(w * size / 2^32), w the first word of Philox4x32-10 at counter
+ * (b, draw, 8, 0) under the ring's seed. Outputs (dev, read back to FP32):
+ * s, s_next [B][n_rays + 4], a int32 [B], r [B], done uint8 [B], idx int32
+ * [B] (nullable). EINVAL when the ring is empty. */
+int sparrow_ring_sample(sparrow_ring *ring, int32_t B, uint32_t draw, float *s, int32_t *a,
+                        float *r, float *s_next, uint8_t *done, int32_t *idx);
+/* The same read-back at the given slots (host int32 [n], each in
+ * [0, size), checked on the host before anything is launched). */
+int sparrow_ring_gather(sparrow_ring *ring, int32_t n, const int32_t *slots_host, float *s,
+                        int32_t *a, float *r, float *s_next, uint8_t *done);
+int64_t sparrow_ring_size(const sparrow_ring *ring);
+int64_t sparrow_ring_head(const sparrow_ring *ring);
+/* Synchronise the ring's stream; SPARROW_OK or the HIP error. */
+int sparrow_ring_status(sparrow_ring *ring);
+void sparrow_ring_destroy(sparrow_ring *ring);
 
 #ifdef __cplusplus
 }

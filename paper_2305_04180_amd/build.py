@@ -18,8 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparrow.so")
-SOURCES = [os.path.join(CSRC, "sparrow.hip")]
+SOURCES = [os.path.join(CSRC, "sparrow.hip"), os.path.join(CSRC, "sparrow_ring.hip")]
 HEADERS = [os.path.join(CSRC, "sparrow_device.h"), os.path.join(CSRC, "sparrow_qnet.h"),
+           os.path.join(CSRC, "sparrow_host.h"),
            os.path.join(ROOT, "include", "sparrow.h")]
 ARCH = "gfx950"
 
@@ -52,10 +53,13 @@ def build(verbose: bool = False) -> str:
 def asm(out_dir: str) -> list[str]:
     """Device assembly of the library (for inspection of our own build)."""
     os.makedirs(out_dir, exist_ok=True)
-    cmd = [hipcc(), *flags(), "--cuda-device-only", "-S", "-o",
-           os.path.join(out_dir, "sparrow-gfx950.s"), *SOURCES]
-    subprocess.check_call(cmd)
-    return [os.path.join(out_dir, "sparrow-gfx950.s")]
+    outs = []
+    for src in SOURCES:
+        stem = os.path.splitext(os.path.basename(src))[0]
+        out = os.path.join(out_dir, f"{stem}-gfx950.s")
+        subprocess.check_call([hipcc(), *flags(), "--cuda-device-only", "-S", "-o", out, src])
+        outs.append(out)
+    return outs
 
 
 if __name__ == "__main__":

@@ -22,6 +22,8 @@
 
 #include "../../include/sparrow.h"
 #include "sparrow_device.h"
+#include "sparrow_host.h"
+#include "sparrow_mlp.h"
 #include "sparrow_qnet.h"
 
 using namespace sp;
@@ -292,20 +294,15 @@ using Q96 = QNetCfg<96, 256, 256>;
 // Host side
 // ===========================================================================
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int code, const std::string& msg) {
+int sp::fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t _e = (expr);                                                             \
-    if (_e != hipSuccess)                                                               \
-      return fail(SPARROW_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));     \
-  } while (0)
+namespace {
 
 struct Groups {
   int epw = 0, G = 0, max_words = 0;
@@ -489,11 +486,16 @@ int launch_step(sparrow_env* e, Params p, int mode, int epw, int L) {
   return fail(SPARROW_EINVAL, "lanes_per_env must be 16, 32 or 64");
 }
 
-// 0: no actor network; 1: obs padded to 64; 2: obs padded to 96
+// 0: no actor network; 1, 2: width 256 (weights in registers), obs padded
+// to 64 or 96; 3, 4: width 512 (weights streamed from L2), obs padded to 64
+// or 96
 int qnet_kind(const QParams& q) {
-  if (q.h1 != 256 || q.h2 != 256) return -1;
-  return q.d0p == 64 ? 1 : q.d0p == 96 ? 2 : -1;
+  if (q.h1 != q.h2) return -1;
+  if (q.h1 == 256) return q.d0p == 64 ? 1 : q.d0p == 96 ? 2 : -1;
+  if (q.h1 == 512) return q.d0p == 64 ? 3 : q.d0p == 96 ? 4 : -1;
+  return -1;
 }
+bool qnet_in_registers(int kind) { return kind == 1 || kind == 2; }
 
 template <int L>
 const void* rollout_fn_L(int kind) {
@@ -511,7 +513,12 @@ const void* rollout_kernel(int L, int kind) {
 }
 
 const void* qnet_kernel(int kind) {
-  return kind == 2 ? (const void*)k_qnet<Q96> : (const void*)k_qnet<Q64>;
+  switch (kind) {
+    case 2: return (const void*)k_qnet<Q96>;
+    case 3: return (const void*)k_mlp<64, 512>;
+    case 4: return (const void*)k_mlp<96, 512>;
+    default: return (const void*)k_qnet<Q64>;
+  }
 }
 
 }  // namespace
@@ -726,8 +733,8 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
   if (!e || !dims || !w_bf16 || !b_f32 || !eps) return fail(SPARROW_EINVAL, "NULL argument");
   const int d0 = dims[0], h1 = dims[1], h2 = dims[2], A = dims[3];
   if (d0 != obs_dim(e) || A != SPARROW_N_ACTIONS) return fail(SPARROW_EINVAL, "qnet dims must be {n_rays + 4, h1, h2, 7}");
-  if (h1 != 256 || h2 != 256 || d0 > 96)
-    return fail(SPARROW_EUNSUPPORTED, "the register-resident actor supports h1 = h2 = 256, obs_dim <= 96");
+  if (h1 != h2 || (h1 != 256 && h1 != 512) || d0 > 96)
+    return fail(SPARROW_EUNSUPPORTED, "the actor supports h1 = h2 in {256, 512} and obs_dim <= 96");
   if (e->q_block) {
     (void)hipFree(e->q_block);
     e->q_block = nullptr;
@@ -774,16 +781,29 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
 
 static int launch_qnet(sparrow_env* e, const float* obs, int32_t n, float* q, int32_t* greedy,
                        int32_t* actions) {
-  const void* fn = qnet_kernel(qnet_kind(e->qp));
+  const int kind = qnet_kind(e->qp);
+  const void* fn = qnet_kernel(kind);
   QParams qp = e->qp;
   qp.lds_base_words = 0;
-  const size_t shmem = qnet_lds_bytes(qp);
-  HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  const int blocks = std::max(1, std::min((n + kQRows - 1) / kQRows, e->n_cu));
+  int blocks = 0;
+  size_t shmem = 0;
+  if (qnet_in_registers(kind)) {
+    shmem = qnet_lds_bytes(qp);
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    blocks = std::max(1, std::min((n + kQRows - 1) / kQRows, e->n_cu));
+  } else {
+    shmem = kind == 3 ? MlpCfg<64, 512>::kLdsBytes : MlpCfg<96, 512>::kLdsBytes;
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kMThreads, shmem));
+    if (per_cu < 1) return fail(SPARROW_EUNSUPPORTED, "actor kernel does not fit a CU");
+    blocks = std::max(1, std::min((n + kMRows - 1) / kMRows, per_cu * e->n_cu));
+  }
   const float* eps = e->eps;
   uint32_t g = e->g, k0 = (uint32_t)e->cfg.seed, k1 = (uint32_t)(e->cfg.seed >> 32);
   void* args[] = {&qp, &obs, &n, &q, &greedy, &eps, &g, &k0, &k1, &actions};
-  HIP_TRY(hipLaunchKernel(fn, dim3(blocks), dim3(kQThreads), args, shmem, e->stream));
+  HIP_TRY(hipLaunchKernel(fn, dim3(blocks), dim3(qnet_in_registers(kind) ? kQThreads : kMThreads),
+                          args, shmem, e->stream));
   return SPARROW_OK;
 }
 
@@ -866,6 +886,9 @@ int sparrow_rollout(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* action
                     uint8_t* done, float* obs) {
   if (!e || !reward || !done || !obs || K < 1) return fail(SPARROW_EINVAL, "bad argument");
   if (use_qnet && !e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
+  if (use_qnet && !qnet_in_registers(qnet_kind(e->qp)))
+    return fail(SPARROW_EUNSUPPORTED,
+                "the fused rollout needs a width-256 actor; use sparrow_act with width 512");
   if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
   return launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done,
                         obs, true);
@@ -1010,7 +1033,8 @@ int sparrow_autotune(sparrow_env* e, int32_t steps, char* report, int32_t report
             }
             return SPARROW_OK;
           }
-          return launch_rollout(e, K, e->has_qnet, epw, L, r_act, r_rew, r_done, obs, false);
+          return launch_rollout(e, K, e->has_qnet && qnet_in_registers(qnet_kind(e->qp)), epw, L,
+                                r_act, r_rew, r_done, obs, false);
         };
         int r = run();  // warm-up (also builds the slot table)
         restore();

@@ -1,0 +1,269 @@
+// sparrow_ring.hip -- the experience buffer on the device (Sec. 3.1.2: Alg. 1
+// step 5 adds each batch of transitions, Alg. 2 step 1 samples a mini-batch;
+// Table 6 sizes it at 1 M transitions and the mini-batch at 256).
+//
+// Storage, structure of arrays over the slots (every array indexed by slot):
+//   rs, rsn   uint8 [cap][n_rays]  range levels of s and s'
+//   cs, csn   uint16 [cap][4]      binary16 scalars of s and s'
+//   act       int8 [cap], rew float [cap], done one bit per slot (uint32 words)
+// A push writes a contiguous run of slots (one wrap at most), so a thread per
+// (transition, observation entry) reads its two FP32 inputs coalesced and
+// writes one byte (or half-word) of each encoded row next to its neighbours'.
+//
+// Kernels:
+//   k_ring_push   encode n transitions into slots head .. head + n - 1 (mod cap)
+//   k_ring_read   decode B slots (drawn by Philox, or given) back to FP32
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sparrow.h"
+#include "sparrow_device.h"
+#include "sparrow_host.h"
+
+using namespace sp;
+
+namespace {
+
+constexpr uint32_t kRingSample = 8;  // Philox counter word 2 of the sampler
+constexpr int kScalars = 4;
+constexpr int kRingThreads = 256;
+
+struct RingDev {
+  uint8_t* rs;
+  uint8_t* rsn;
+  uint16_t* cs;
+  uint16_t* csn;
+  int8_t* act;
+  float* rew;
+  uint32_t* done;
+  int32_t cap, nr;
+};
+
+// nearest level of 255 * clamp(o, 0, 1): the product rounds to binary32,
+// v_rndne_f32 rounds it to the nearest integer, ties to even; NaN -> 0
+__device__ __forceinline__ uint8_t quant_u8(float o) {
+  const float c = fminf(fmaxf(o, 0.0f), 1.0f);
+  return (uint8_t)__builtin_rintf(c * 255.0f);
+}
+__device__ __forceinline__ float dequant_u8(uint8_t q) { return (float)q / 255.0f; }
+// binary32 -> binary16 with v_cvt_f16_f32 (round to nearest even)
+__device__ __forceinline__ uint16_t f16_bits(float f) {
+  return __builtin_bit_cast(uint16_t, (_Float16)f);
+}
+__device__ __forceinline__ float f16_value(uint16_t h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+
+__global__ void __launch_bounds__(kRingThreads)
+k_ring_push(RingDev R, int64_t head, int32_t n, const float* __restrict__ s,
+            const int32_t* __restrict__ a, const float* __restrict__ r,
+            const float* __restrict__ sn, const float* __restrict__ sf,
+            const uint8_t* __restrict__ done) {
+  const int D = R.nr + kScalars;
+  const int64_t total = (int64_t)n * D;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int i = (int)(t / D), j = (int)(t - (int64_t)i * D);
+    int64_t slot = head + i;  // head < cap and i < n <= cap: at most one wrap
+    if (slot >= R.cap) slot -= R.cap;
+    const bool d = done[i] != 0;
+    const float v = s[t];
+    const float vn = (d && sf) ? sf[t] : sn[t];
+    if (j < R.nr) {
+      R.rs[slot * R.nr + j] = quant_u8(v);
+      R.rsn[slot * R.nr + j] = quant_u8(vn);
+    } else {
+      R.cs[slot * kScalars + (j - R.nr)] = f16_bits(v);
+      R.csn[slot * kScalars + (j - R.nr)] = f16_bits(vn);
+    }
+    if (j == 0) {
+      R.act[slot] = (int8_t)a[i];
+      R.rew[slot] = r[i];
+      const uint32_t bit = 1u << (uint32_t)(slot & 31);
+      if (d)
+        atomicOr(&R.done[slot >> 5], bit);
+      else
+        atomicAnd(&R.done[slot >> 5], ~bit);
+    }
+  }
+}
+
+// Decode B slots. With `slots` NULL, slot b is floor(w * size / 2^32) for the
+// first word w of Philox (b, draw, 8, 0); every entry of a row recomputes it,
+// which costs less than a second launch.
+__global__ void __launch_bounds__(kRingThreads)
+k_ring_read(RingDev R, uint32_t size, int32_t B, uint32_t draw, uint32_t key0, uint32_t key1,
+            const int32_t* __restrict__ slots, float* __restrict__ s, int32_t* __restrict__ a,
+            float* __restrict__ r, float* __restrict__ sn, uint8_t* __restrict__ done,
+            int32_t* __restrict__ idx) {
+  const int D = R.nr + kScalars;
+  const int total = B * D;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const int b = t / D, j = t - b * D;
+    int64_t slot;
+    if (slots) {
+      slot = slots[b];
+    } else {
+      const U4 w = philox((uint32_t)b, draw, kRingSample, 0u, key0, key1);
+      slot = scale_u32(w.x, size);
+    }
+    if (j < R.nr) {
+      if (s) s[t] = dequant_u8(R.rs[slot * R.nr + j]);
+      if (sn) sn[t] = dequant_u8(R.rsn[slot * R.nr + j]);
+    } else {
+      if (s) s[t] = f16_value(R.cs[slot * kScalars + (j - R.nr)]);
+      if (sn) sn[t] = f16_value(R.csn[slot * kScalars + (j - R.nr)]);
+    }
+    if (j == 0) {
+      if (a) a[b] = R.act[slot];
+      if (r) r[b] = R.rew[slot];
+      if (done) done[b] = (uint8_t)((R.done[slot >> 5] >> (uint32_t)(slot & 31)) & 1u);
+      if (idx) idx[b] = (int32_t)slot;
+    }
+  }
+}
+
+int grid_for(int64_t work) {
+  const int64_t blocks = (work + kRingThreads - 1) / kRingThreads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 4096));
+}
+
+}  // namespace
+
+struct sparrow_ring {
+  RingDev dev{};
+  void* block = nullptr;
+  int32_t* d_slots = nullptr;  // staging for sparrow_ring_gather
+  int32_t d_slots_cap = 0;
+  int64_t head = 0, size = 0;
+  uint32_t key0 = 0, key1 = 0;
+  hipStream_t stream = nullptr;
+};
+
+int sparrow_ring_create(int32_t capacity, int32_t n_rays, uint64_t seed, void* hip_stream,
+                        sparrow_ring** out) {
+  if (!out) return fail(SPARROW_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (capacity < 1 || capacity > (1 << 26)) return fail(SPARROW_EINVAL, "capacity must be in [1, 2^26]");
+  if (n_rays < 1 || n_rays > SPARROW_MAX_RAYS) return fail(SPARROW_EINVAL, "n_rays out of range");
+  auto* R = new sparrow_ring();
+  R->stream = (hipStream_t)hip_stream;
+  R->key0 = (uint32_t)seed;
+  R->key1 = (uint32_t)(seed >> 32);
+  const size_t cap = (size_t)capacity;
+  auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_r = align(cap * n_rays), b_c = align(cap * kScalars * 2), b_a = align(cap),
+               b_w = align(cap * 4), b_d = align((cap + 31) / 32 * 4);
+  const size_t bytes = 2 * b_r + 2 * b_c + b_a + b_w + b_d;
+  if (hipMalloc(&R->block, bytes) != hipSuccess) {
+    delete R;
+    return fail(SPARROW_ENOMEM, "hipMalloc of the ring failed");
+  }
+  char* p = (char*)R->block;
+  R->dev.rs = (uint8_t*)p;
+  p += b_r;
+  R->dev.rsn = (uint8_t*)p;
+  p += b_r;
+  R->dev.cs = (uint16_t*)p;
+  p += b_c;
+  R->dev.csn = (uint16_t*)p;
+  p += b_c;
+  R->dev.act = (int8_t*)p;
+  p += b_a;
+  R->dev.rew = (float*)p;
+  p += b_w;
+  R->dev.done = (uint32_t*)p;
+  R->dev.cap = capacity;
+  R->dev.nr = n_rays;
+  if (hipMemsetAsync(R->block, 0, bytes, R->stream) != hipSuccess ||
+      hipStreamSynchronize(R->stream) != hipSuccess) {
+    (void)hipFree(R->block);
+    delete R;
+    return fail(SPARROW_EHIP, "clearing the ring failed");
+  }
+  *out = R;
+  return SPARROW_OK;
+}
+
+int sparrow_ring_push(sparrow_ring* R, int32_t n, const float* s, const int32_t* a, const float* r,
+                      const float* s_next, const float* s_final, const uint8_t* done) {
+  if (!R) return fail(SPARROW_EINVAL, "NULL argument");
+  if (n < 0 || n > R->dev.cap) return fail(SPARROW_EINVAL, "push size must be in [0, capacity]");
+  if (n == 0) return SPARROW_OK;
+  if (!s || !a || !r || !s_next || !done) return fail(SPARROW_EINVAL, "NULL argument");
+  const int64_t work = (int64_t)n * (R->dev.nr + kScalars);
+  hipLaunchKernelGGL(k_ring_push, dim3(grid_for(work)), dim3(kRingThreads), 0, R->stream, R->dev,
+                     R->head, n, s, a, r, s_next, s_final, done);
+  HIP_TRY(hipGetLastError());
+  R->head = (R->head + n) % R->dev.cap;
+  R->size = std::min<int64_t>(R->size + n, R->dev.cap);
+  return SPARROW_OK;
+}
+
+static int ring_read(sparrow_ring* R, int32_t B, uint32_t draw, const int32_t* d_slots, float* s,
+                     int32_t* a, float* r, float* s_next, uint8_t* done, int32_t* idx) {
+  const int64_t work = (int64_t)B * (R->dev.nr + kScalars);
+  hipLaunchKernelGGL(k_ring_read, dim3(grid_for(work)), dim3(kRingThreads), 0, R->stream, R->dev,
+                     (uint32_t)R->size, B, draw, R->key0, R->key1, d_slots, s, a, r, s_next, done,
+                     idx);
+  HIP_TRY(hipGetLastError());
+  return SPARROW_OK;
+}
+
+int sparrow_ring_sample(sparrow_ring* R, int32_t B, uint32_t draw, float* s, int32_t* a, float* r,
+                        float* s_next, uint8_t* done, int32_t* idx) {
+  if (!R) return fail(SPARROW_EINVAL, "NULL argument");
+  if (B < 0 || (int64_t)B * (R->dev.nr + kScalars) > INT32_MAX)
+    return fail(SPARROW_EINVAL, "bad mini-batch size");
+  if (R->size == 0) return fail(SPARROW_EINVAL, "the ring is empty");
+  if (B == 0) return SPARROW_OK;
+  return ring_read(R, B, draw, nullptr, s, a, r, s_next, done, idx);
+}
+
+int sparrow_ring_gather(sparrow_ring* R, int32_t n, const int32_t* slots_host, float* s, int32_t* a,
+                        float* r, float* s_next, uint8_t* done) {
+  if (!R || (n > 0 && !slots_host)) return fail(SPARROW_EINVAL, "NULL argument");
+  if (n < 0 || (int64_t)n * (R->dev.nr + kScalars) > INT32_MAX)
+    return fail(SPARROW_EINVAL, "bad gather size");
+  for (int32_t b = 0; b < n; ++b)
+    if (slots_host[b] < 0 || slots_host[b] >= R->size)
+      return fail(SPARROW_EINVAL, "slot outside the stored range");
+  if (n == 0) return SPARROW_OK;
+  if (n > R->d_slots_cap) {
+    if (R->d_slots) HIP_TRY(hipFree(R->d_slots));
+    R->d_slots = nullptr;
+    R->d_slots_cap = 0;
+    if (hipMalloc((void**)&R->d_slots, sizeof(int32_t) * (size_t)n) != hipSuccess)
+      return fail(SPARROW_ENOMEM, "hipMalloc failed");
+    R->d_slots_cap = n;
+  }
+  // the previous gather may still read the staging buffer: order the copy
+  // after it on the ring's stream, and wait for the copy before returning
+  HIP_TRY(hipMemcpyAsync(R->d_slots, slots_host, sizeof(int32_t) * (size_t)n,
+                         hipMemcpyHostToDevice, R->stream));
+  const int rc = ring_read(R, n, 0u, R->d_slots, s, a, r, s_next, done, nullptr);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(R->stream));
+  return SPARROW_OK;
+}
+
+int64_t sparrow_ring_size(const sparrow_ring* R) { return R ? R->size : -1; }
+int64_t sparrow_ring_head(const sparrow_ring* R) { return R ? R->head : -1; }
+
+int sparrow_ring_status(sparrow_ring* R) {
+  if (!R) return fail(SPARROW_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(R->stream));
+  return SPARROW_OK;
+}
+
+void sparrow_ring_destroy(sparrow_ring* R) {
+  if (!R) return;
+  (void)hipStreamSynchronize(R->stream);
+  if (R->d_slots) (void)hipFree(R->d_slots);
+  if (R->block) (void)hipFree(R->block);
+  delete R;
+}

@@ -152,9 +152,24 @@ def mixed_map(side: int, rng: np.random.Generator) -> np.ndarray:
     return g
 
 
-def make_maps(cfg: dict, n_maps: int | None = None, first: int = 0) -> Maps:
-    """One map per env (env i uses map i), sides drawn per map from cfg['sides']."""
+def _maps_chunk(job):
+    cfg, first, n = job
+    return make_maps(cfg, n_maps=n, first=first).grids
+
+
+def make_maps(cfg: dict, n_maps: int | None = None, first: int = 0, workers: int = 1) -> Maps:
+    """One map per env (env i uses map i), sides drawn per map from cfg['sides'].
+    Map i depends only on (workload, i), so `workers` > 1 (a fork pool; call
+    it before the process touches the GPU) gives the same maps faster."""
     n = cfg["n_envs"] if n_maps is None else n_maps
+    if workers > 1 and n >= 4 * workers:
+        import multiprocessing as mp
+        step = -(-n // (4 * workers))
+        jobs = [(cfg, first + lo, min(step, n - lo)) for lo in range(0, n, step)]
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_maps_chunk, jobs)
+        return Maps(grids=[g for part in parts for g in part],
+                    env_to_map=np.arange(n, dtype=np.int32))
     wid = WORKLOAD_IDS.get(cfg.get("name", "c2"), 0)
     grids = []
     for i in range(first, first + n):

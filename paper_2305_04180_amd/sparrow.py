@@ -28,6 +28,8 @@ EXPORTS = (
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
+    "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
+    "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
 )
 
 
@@ -86,6 +88,14 @@ def lib(path: str = LIB_PATH):
             "sparrow_status": (I32, [P]),
             "sparrow_destroy": (None, [P]),
             "sparrow_last_error": (C.c_char_p, []),
+            "sparrow_ring_create": (I32, [I32, I32, C.c_uint64, P, C.POINTER(P)]),
+            "sparrow_ring_push": (I32, [P, I32, P, P, P, P, P, P]),
+            "sparrow_ring_sample": (I32, [P, I32, U32, P, P, P, P, P, P]),
+            "sparrow_ring_gather": (I32, [P, I32, P, P, P, P, P, P]),
+            "sparrow_ring_size": (C.c_int64, [P]),
+            "sparrow_ring_head": (C.c_int64, [P]),
+            "sparrow_ring_status": (I32, [P]),
+            "sparrow_ring_destroy": (None, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -306,3 +316,89 @@ def vem_epsilon(n: int, m: int, e_min: float, e_max: float) -> np.ndarray:
         frac = j / (m - 1) if m > 1 else np.ones(1)
         eps[n - m:] = e_min + e_max * frac
     return eps.astype(np.float32)
+
+
+class Ring:
+    """Device experience buffer (sparrow_ring_*): batched adds of transitions
+    (s, a, r, s', done) and uniform mini-batch sampling, on the current
+    device and torch stream."""
+
+    def __init__(self, capacity: int, n_rays: int, seed: int = 1, stream=None):
+        import torch
+        self.torch = torch
+        self.capacity, self.n_rays, self.D = int(capacity), int(n_rays), int(n_rays) + 4
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().sparrow_ring_create(self.capacity, self.n_rays, int(seed),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sparrow_ring_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _b(self, t, dtype, numel, name, nullable=False):
+        return _buf(t, dtype, numel, self.device, name, nullable)
+
+    @property
+    def size(self) -> int:
+        return int(lib().sparrow_ring_size(self._h))
+
+    @property
+    def head(self) -> int:
+        return int(lib().sparrow_ring_head(self._h))
+
+    def push(self, s, a, r, s_next, done, s_final=None):
+        t = self.torch
+        n = int(a.numel())
+        self._b(s, t.float32, n * self.D, "s")
+        self._b(a, t.int32, n, "a")
+        self._b(r, t.float32, n, "r")
+        self._b(s_next, t.float32, n * self.D, "s_next")
+        self._b(s_final, t.float32, n * self.D, "s_final", nullable=True)
+        self._b(done, t.uint8, n, "done")
+        _check(lib().sparrow_ring_push(self._h, n, _ptr(s), _ptr(a), _ptr(r), _ptr(s_next),
+                                       _ptr(s_final), _ptr(done)))
+
+    def _outs(self, n, outs):
+        t, dev = self.torch, self.device
+        if outs is not None:
+            s, a, r, sn, d = outs
+            self._b(s, t.float32, n * self.D, "s")
+            self._b(a, t.int32, n, "a")
+            self._b(r, t.float32, n, "r")
+            self._b(sn, t.float32, n * self.D, "s_next")
+            self._b(d, t.uint8, n, "done")
+            return outs
+        return (t.zeros(n, self.D, dtype=t.float32, device=dev), t.zeros(n, dtype=t.int32, device=dev),
+                t.zeros(n, dtype=t.float32, device=dev), t.zeros(n, self.D, dtype=t.float32, device=dev),
+                t.zeros(n, dtype=t.uint8, device=dev))
+
+    def sample(self, B: int, draw: int, outs=None, idx=None):
+        """B uniform draws over the stored slots (Philox counter (b, draw, 8, 0))."""
+        s, a, r, sn, d = self._outs(B, outs)
+        if idx is None:
+            idx = self.torch.zeros(B, dtype=self.torch.int32, device=self.device)
+        self._b(idx, self.torch.int32, B, "idx")
+        _check(lib().sparrow_ring_sample(self._h, B, int(draw) & 0xFFFFFFFF, _ptr(s), _ptr(a),
+                                         _ptr(r), _ptr(sn), _ptr(d), _ptr(idx)))
+        return s, a, r, sn, d, idx
+
+    def gather(self, slots):
+        """Read back the given slots (host integers, each in [0, size))."""
+        sl = np.ascontiguousarray(slots, np.int32)
+        s, a, r, sn, d = self._outs(len(sl), None)
+        _check(lib().sparrow_ring_gather(self._h, len(sl), sl.ctypes.data, _ptr(s), _ptr(a),
+                                         _ptr(r), _ptr(sn), _ptr(d)))
+        return s, a, r, sn, d
+
+    def status(self) -> int:
+        return lib().sparrow_ring_status(self._h)

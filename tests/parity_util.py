@@ -54,3 +54,135 @@ def compare_exact(g, o, name, where=""):
     else:
         bad = np.argwhere(g != o)
     assert bad.size == 0, f"{where}: {name} differs at {bad[:5]}: {g[tuple(bad[0])]} vs {o[tuple(bad[0])]}"
+
+
+# ---- the actor: which greedy choices the kernel's precision cannot flip -------
+def bf16_round(x):
+    """Values rounded to bf16 (nearest even), as float64."""
+    from paper_2305_04180_amd import inputs
+    bits = inputs._to_bf16_bits(np.asarray(x, np.float32)).astype(np.uint32) << 16
+    return bits.view(np.float32).astype(np.float64)
+
+
+def qnet_f64_weights(dims, w):
+    wf = (np.asarray(w).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    d0, h1, h2, A = dims
+    W1 = wf[:h1 * d0].reshape(h1, d0)
+    W2 = wf[h1 * d0:h1 * d0 + h2 * h1].reshape(h2, h1)
+    W3 = wf[h1 * d0 + h2 * h1:].reshape(A, h2)
+    return W1, W2, W3
+
+
+def qnet_bound(dims, w, b, obs, in_tol=0.0):
+    """First-order bound (Higham) on |Q_kernel - Q_fp64| per (row, action),
+    from oracle-side values only: hidden activations stored in bf16 (relative
+    u = 2^-9 each) and FP32 accumulation over K terms (gamma ~ K 2^-24),
+    propagated with |W|; plus, when the kernel's input may differ from `obs`
+    by up to in_tol per entry (noisy ranges, bearing), the change of every
+    entry whose bf16 rounding that can flip, pushed through |W1|, |W2|, |W3|."""
+    W1, W2, W3 = qnet_f64_weights(dims, w)
+    h1, h2 = dims[1], dims[2]
+    b = np.asarray(b, np.float64)
+    obs = np.asarray(obs, np.float32)
+    xb = bf16_round(obs)
+    a1 = np.maximum(xb @ W1.T + b[:h1], 0)
+    a2 = np.maximum(a1 @ W2.T + b[h1:h1 + h2], 0)
+    u, gam = 2.0 ** -9, max(h1, h2) * 2.0 ** -24
+    aW2, aW3 = np.abs(W2), np.abs(W3)
+    bound = (u + gam) * (a2 @ aW3.T + (a1 @ aW2.T) @ aW3.T) + 1e-6
+    if in_tol > 0:
+        lo = bf16_round(obs.astype(np.float64) - in_tol)
+        hi = bf16_round(obs.astype(np.float64) + in_tol)
+        dx = np.maximum(np.abs(hi - xb), np.abs(lo - xb))
+        if dx.any():
+            bound = bound + ((dx @ np.abs(W1).T) @ aW2.T) @ aW3.T
+    return bound
+
+
+def _bf16_relu(z):
+    """bf16(binary32(relu(z))): the kernel's activation store, monotone in z."""
+    return bf16_round(np.maximum(z, 0.0).astype(np.float32))
+
+
+def qnet_rounded_bound(dims, w, b, obs, in_tol=0.0):
+    """Bound per (row, action) on |Q_kernel - Q_bf16act|, where Q_bf16act is
+    the oracle's Q-network with hidden activations rounded to bf16
+    (qnet_f64(..., round_act=True)). The kernel accumulates each layer in
+    FP32 (error <= gamma_K sum |w x|, gamma_K ~ K 2^-24) before rounding to
+    bf16, so a stored activation can differ from the oracle's only where that
+    error (plus what earlier differences carry forward) reaches a bf16
+    rounding boundary; the monotone store maps the error interval of each
+    pre-activation to the interval of activations it can produce. Inputs may
+    differ from `obs` by in_tol per entry. Oracle-side values only."""
+    W1, W2, W3 = qnet_f64_weights(dims, w)
+    d0, h1, h2, _ = dims
+    b = np.asarray(b, np.float64)
+    b1, b2, b3 = b[:h1], b[h1:h1 + h2], b[h1 + h2:]
+    obs = np.asarray(obs, np.float32)
+    aW1, aW2, aW3 = np.abs(W1), np.abs(W2), np.abs(W3)
+    g = lambda k: (k + 2) * 2.0 ** -24  # FP32 sum of k products and a bias
+    xb = bf16_round(obs)
+    dx = np.zeros_like(xb)
+    if in_tol > 0:
+        lo = bf16_round(obs.astype(np.float64) - in_tol)
+        hi = bf16_round(obs.astype(np.float64) + in_tol)
+        dx = np.maximum(np.abs(hi - xb), np.abs(lo - xb))
+    z1 = xb @ W1.T + b1
+    e1 = g(d0) * ((np.abs(xb) + dx) @ aW1.T + np.abs(b1)) + dx @ aW1.T
+    a1 = _bf16_relu(z1)
+    d1 = np.maximum(np.abs(_bf16_relu(z1 + e1) - a1), np.abs(_bf16_relu(z1 - e1) - a1))
+    z2 = a1 @ W2.T + b2
+    e2 = g(h1) * ((a1 + d1) @ aW2.T + np.abs(b2)) + d1 @ aW2.T
+    a2 = _bf16_relu(z2)
+    d2 = np.maximum(np.abs(_bf16_relu(z2 + e2) - a2), np.abs(_bf16_relu(z2 - e2) - a2))
+    q = a2 @ W3.T + b3
+    eq = g(h2 + 8) * ((a2 + d2) @ aW3.T + np.abs(b3)) + d2 @ aW3.T + 1e-7 * (1 + np.abs(q))
+    return eq
+
+
+def settled_greedy(q64, bound):
+    """Oracle greedy action per row and whether no error within `bound` can
+    change it (gap to the runner-up above both rows' bounds)."""
+    order = np.argsort(-q64, 1, kind="stable")
+    top, second = order[:, 0], order[:, 1]
+    rows = np.arange(len(q64))
+    gap = q64[rows, top] - q64[rows, second]
+    return top, gap > bound[rows, top] + bound[rows, second]
+
+
+def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where):
+    """Step the oracle with its own FP64 actor + VEM next to a GPU rollout
+    (acts, rew, done: [K][N]) and compare. Explored actions equal the
+    oracle's draw; a greedy action equals the oracle's bf16-activation argmax
+    wherever qnet_rounded_bound settles it; an env stays compared while its
+    actions equal the FP64 actor's (its trajectory is then the oracle's).
+    Returns the mask of envs compared to the end and the oracle's last
+    observation."""
+    import oracle
+    K, N = acts.shape
+    live = np.ones(N, bool)
+    n_settled = n_greedy = n_agree = 0
+    for t in range(K):
+        q64 = oracle.qnet_f64(dims, w, b, o_obs)
+        a_o, ex = orc.vem(q64, eps)
+        exb = ex.astype(bool)
+        q_ra = oracle.qnet_f64(dims, w, b, o_obs, round_act=True)
+        top, settled = settled_greedy(q_ra, qnet_rounded_bound(dims, w, b, o_obs, RANGE_TOL))
+        w_ = f"{where} t={t}"
+        compare_exact(acts[t][live & exb], a_o[live & exb], "explored actions", w_)
+        m = live & ~exb & settled
+        compare_exact(acts[t][m], top[m], "settled greedy actions", w_)
+        n_greedy += int((live & ~exb).sum())
+        n_settled += int(m.sum())
+        n_agree += int((live & ~exb & (acts[t] == a_o)).sum())
+        live &= acts[t] == a_o
+        r = orc.step(a_o)
+        compare_exact(rew[t][live], r["reward"][live], "reward", w_)
+        compare_exact(done[t][live], r["done"][live], "done", w_)
+        o_obs = r["obs"]
+    print(f"{where}: {live.sum()} of {N} envs compared over {K} steps; {n_settled} of "
+          f"{n_greedy} greedy choices settled by the bound; agreement with the FP64 actor "
+          f"{n_agree / max(n_greedy, 1):.5f}", flush=True)
+    assert live.mean() >= 0.9, (live.sum(), N)
+    assert n_agree >= 0.99 * n_greedy
+    return live, o_obs

