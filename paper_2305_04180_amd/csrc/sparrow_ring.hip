@@ -6,9 +6,9 @@
 //   rs, rsn   uint8 [cap][n_rays]  range levels of s and s'
 //   cs, csn   uint16 [cap][4]      binary16 scalars of s and s'
 //   act       int8 [cap], rew float [cap], done one bit per slot (uint32 words)
-// A push writes a contiguous run of slots (one wrap at most), so a thread per
-// (transition, observation entry) reads its two FP32 inputs coalesced and
-// writes one byte (or half-word) of each encoded row next to its neighbours'.
+// A push writes a contiguous run of slots (one wrap at most); a wave per
+// transition reads its FP32 rows coalesced and writes the encoded rows next
+// to each other.
 //
 // Kernels:
 //   k_ring_push   encode n transitions into slots head .. head + n - 1 (mod cap)
@@ -58,37 +58,58 @@ __device__ __forceinline__ float f16_value(uint16_t h) {
   return (float)__builtin_bit_cast(_Float16, h);
 }
 
+// One wave per transition: lanes take the row's entries, so the FP32 rows
+// are read and the encoded rows written contiguously with no division.
 __global__ void __launch_bounds__(kRingThreads)
 k_ring_push(RingDev R, int64_t head, int32_t n, const float* __restrict__ s,
             const int32_t* __restrict__ a, const float* __restrict__ r,
             const float* __restrict__ sn, const float* __restrict__ sf,
             const uint8_t* __restrict__ done) {
   const int D = R.nr + kScalars;
-  const int64_t total = (int64_t)n * D;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-    const int i = (int)(t / D), j = (int)(t - (int64_t)i * D);
+  const int lane = threadIdx.x & 63;
+  const int waves = gridDim.x * (kRingThreads / 64);
+  for (int i = blockIdx.x * (kRingThreads / 64) + (threadIdx.x >> 6); i < n; i += waves) {
     int64_t slot = head + i;  // head < cap and i < n <= cap: at most one wrap
     if (slot >= R.cap) slot -= R.cap;
     const bool d = done[i] != 0;
-    const float v = s[t];
-    const float vn = (d && sf) ? sf[t] : sn[t];
-    if (j < R.nr) {
-      R.rs[slot * R.nr + j] = quant_u8(v);
-      R.rsn[slot * R.nr + j] = quant_u8(vn);
-    } else {
-      R.cs[slot * kScalars + (j - R.nr)] = f16_bits(v);
-      R.csn[slot * kScalars + (j - R.nr)] = f16_bits(vn);
+    const float* srow = s + (size_t)i * D;
+    const float* nrow = ((d && sf) ? sf : sn) + (size_t)i * D;
+    for (int j = lane; j < D; j += 64) {
+      const float v = srow[j], vn = nrow[j];
+      if (j < R.nr) {
+        R.rs[slot * R.nr + j] = quant_u8(v);
+        R.rsn[slot * R.nr + j] = quant_u8(vn);
+      } else {
+        R.cs[slot * kScalars + (j - R.nr)] = f16_bits(v);
+        R.csn[slot * kScalars + (j - R.nr)] = f16_bits(vn);
+      }
     }
-    if (j == 0) {
+    if (lane == 0) {
       R.act[slot] = (int8_t)a[i];
       R.rew[slot] = r[i];
-      const uint32_t bit = 1u << (uint32_t)(slot & 31);
-      if (d)
-        atomicOr(&R.done[slot >> 5], bit);
-      else
-        atomicAnd(&R.done[slot >> 5], ~bit);
     }
+  }
+  // Done bits: one thread owns each 32-slot word the add touches and
+  // rebuilds it, keeping the bits of slots outside the add, so no atomics.
+  // Without a wrap the touched words are one run; an add that wraps (rare)
+  // visits every word, so no word has two owners.
+  const bool wraps = head + n > R.cap;
+  const int64_t w0 = wraps ? 0 : head >> 5;
+  const int64_t w1 = wraps ? ((int64_t)R.cap - 1) >> 5 : (head + n - 1) >> 5;
+  for (int64_t w = w0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w <= w1;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t bits = 0, keep = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int64_t slot = w * 32 + b;
+      int64_t i = slot - head;  // index in the add, modulo the capacity
+      if (i < 0) i += R.cap;
+      if (slot < R.cap && i < n)
+        bits |= (done[i] != 0 ? 1u : 0u) << b;
+      else
+        keep |= 1u << b;
+    }
+    uint32_t* dst = &R.done[w];
+    *dst = keep ? ((*dst & keep) | bits) : bits;
   }
 }
 
@@ -195,9 +216,10 @@ int sparrow_ring_push(sparrow_ring* R, int32_t n, const float* s, const int32_t*
   if (n < 0 || n > R->dev.cap) return fail(SPARROW_EINVAL, "push size must be in [0, capacity]");
   if (n == 0) return SPARROW_OK;
   if (!s || !a || !r || !s_next || !done) return fail(SPARROW_EINVAL, "NULL argument");
-  const int64_t work = (int64_t)n * (R->dev.nr + kScalars);
-  hipLaunchKernelGGL(k_ring_push, dim3(grid_for(work)), dim3(kRingThreads), 0, R->stream, R->dev,
-                     R->head, n, s, a, r, s_next, s_final, done);
+  const int64_t rows_per_block = kRingThreads / 64;
+  hipLaunchKernelGGL(k_ring_push, dim3(grid_for(n * (int64_t)kRingThreads / rows_per_block)),
+                     dim3(kRingThreads), 0, R->stream, R->dev, R->head, n, s, a, r, s_next, s_final,
+                     done);
   HIP_TRY(hipGetLastError());
   R->head = (R->head + n) % R->dev.cap;
   R->size = std::min<int64_t>(R->size + n, R->dev.cap);
