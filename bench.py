@@ -296,19 +296,25 @@ def env_map_bytes(maps):
     return tot
 
 
-def greedy_agreement(env, obs, dims, w, b):
-    """BF16 MFMA actor vs the FP64 oracle on the rollout's own final
-    observations (oracle leg of the benchmark)."""
+def greedy_agreement(env, cfg, maps, dims, w, b):
+    """BF16 MFMA actor vs the FP64 oracle on observations the oracle itself
+    produced: its reset of the same envs and three uniform-action steps."""
     import torch
     import oracle
-    q, g = env.qnet_forward(obs)
+    o = oracle.Oracle(cfg, maps)
+    obs, _ = o.reset()
+    rows = [obs]
+    for _ in range(3):
+        rows.append(o.step(o.uniform_actions())["obs"])
+    x = np.concatenate(rows)
+    q, g = env.qnet_forward(torch.as_tensor(x).cuda())
     torch.cuda.synchronize()
-    o = obs.cpu().numpy()
-    q64 = oracle.qnet_f64(dims, w, b, o)
+    q64 = oracle.qnet_f64(dims, w, b, x)
     qg = q.cpu().numpy().astype(np.float64)
     agree = float((g.cpu().numpy() == q64.argmax(1)).mean())
-    return {"rows": int(o.shape[0]), "greedy_agreement_vs_fp64": round(agree, 5),
-            "max_abs_dq": float(np.abs(qg - q64).max())}
+    return {"rows": int(x.shape[0]), "greedy_agreement_vs_fp64": round(agree, 5),
+            "max_abs_dq": float(np.abs(qg - q64).max()),
+            "observations": "oracle reset + 3 uniform steps of the benchmark's envs"}
 
 
 def main():
@@ -483,7 +489,7 @@ def main():
         cpu["single_thread_value"] = one["value"]
         cpu["cpu_model"] = cpu_model()
         cpu["nproc"] = os.cpu_count()
-        precision = greedy_agreement(env, obs, dims, w, b)
+        precision = greedy_agreement(env, cfg, maps, dims, w, b)
         log(f"[bench] precision: {precision}")
 
     c5 = None
