@@ -105,6 +105,8 @@ def lib():
         L.orc_vem.argtypes = [P, P, C.c_int32, P, P, P]
         L.orc_uniform_actions.argtypes = [P, P]
         L.orc_vem_epsilon.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, P]
+        L.orc_vem_or.restype = C.c_int32
+        L.orc_vem_or.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int64]
         L.orc_ring_create.restype = P
         L.orc_ring_create.argtypes = [C.c_int64, C.c_int32, C.c_uint64]
         L.orc_ring_destroy.argtypes = [P]
@@ -177,6 +179,16 @@ def qnet_f64(dims, w_bf16, b_f32, obs, round_act=False):
     q = np.zeros((n, int(d[3])), np.float64)
     lib().orc_qnet_f64(_p(d), _p(w), _p(b), n, _p(o), int(bool(round_act)), _p(q))
     return q
+
+
+def vem_or(T, or_start, or_final, decay):
+    """Exploring-interval size after T transitions (linear decay, Sec. 3.1.1)."""
+    return int(lib().orc_vem_or(int(T), int(or_start), int(or_final), int(decay)))
+
+
+def vem_schedule_epsilon(n, g, e_min, e_max, or_start, or_final, decay):
+    """Per-env VEM probabilities at global step g (T = n * g transitions)."""
+    return vem_epsilon(n, vem_or(n * g, or_start, or_final, decay), e_min, e_max)
 
 
 def vem_epsilon(n, m, e_min, e_max):

@@ -642,6 +642,12 @@ void orc_vem_epsilon(int32_t n, int32_t m, double e_min, double e_max, float *ep
   }
 }
 
+int32_t orc_vem_or(int64_t T, int32_t or_start, int32_t or_final, int64_t decay) {
+  if (decay <= 0) return or_final;
+  const int64_t t = T < decay ? T : decay;
+  return or_start - (int32_t)(((int64_t)(or_start - or_final) * t) / decay);
+}
+
 void orc_sincos_batch(int32_t n, const float *phi, float *s, float *c) {
   for (int32_t i = 0; i < n; ++i) orc_sincos_f32(phi[i], s + i, c + i);
 }

@@ -128,6 +128,11 @@ void orc_uniform_actions(const orc_env *e, int32_t *actions);
 /* VEM exploration noise per env: the last m envs form the exploring
  * interval, linear from e_min to e_min + e_max; the rest hold e_min. */
 void orc_vem_epsilon(int32_t n, int32_t m, double e_min, double e_max, float *eps);
+/* Size of the exploring interval after T transitions when it shrinks
+ * linearly from or_start to or_final over `decay` transitions (Sec. 3.1.1;
+ * Table 6 "Linear Decay Steps of OR"): or_start - floor((or_start -
+ * or_final) * min(T, decay) / decay); decay = 0 gives or_final. */
+int32_t orc_vem_or(int64_t T, int32_t or_start, int32_t or_final, int64_t decay);
 
 #ifdef __cplusplus
 }

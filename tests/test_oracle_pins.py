@@ -690,3 +690,25 @@ def test_free_disk_means_no_hit_inside_radius():
             assert k == -1 or k >= 3, (m, x, y, th, k)
             checked += 1
     assert checked > 5000
+
+
+def test_vem_or_decays_linearly_table6():
+    """Table 6 (Sparrow): the exploring interval shrinks from 16 to 3 envs
+    over 500K transitions. A linear decay loses its k-th env when the line
+    16 - 13 T / decay first reaches 16 - k, i.e. at T = ceil(k decay / 13)."""
+    import json
+    from fractions import Fraction
+    hp = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))["table6_sparrow_framework"]
+    s, f, dec = hp["or_start"], hp["or_final"], hp["or_decay_steps_T"]
+    assert oracle.vem_or(0, s, f, dec) == s
+    assert oracle.vem_or(dec, s, f, dec) == f and oracle.vem_or(10 ** 12, s, f, dec) == f
+    for k in range(1, s - f + 1):
+        t_k = math.ceil(Fraction(k * dec, s - f))
+        assert oracle.vem_or(t_k, s, f, dec) == s - k, k
+        assert oracle.vem_or(t_k - 1, s, f, dec) == s - k + 1, k
+    assert oracle.vem_or(12345, s, f, 0) == f  # no decay: the final interval
+    # with the Table 6 probabilities the last env explores at E_min + E_max
+    e = oracle.vem_schedule_epsilon(16, 0, hp["E_min"], hp["E_max"], s, f, dec)
+    assert e[0] == np.float32(0.01) and e[-1] == np.float32(0.81)
+    e_end = oracle.vem_schedule_epsilon(16, dec, hp["E_min"], hp["E_max"], s, f, dec)
+    assert np.all(e_end[:13] == np.float32(0.01)) and np.allclose(e_end[13:], [0.01, 0.41, 0.81])
