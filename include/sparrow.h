@@ -142,6 +142,20 @@ int sparrow_random_actions(sparrow_env *env, int32_t *actions);
 int sparrow_set_qnet(sparrow_env *env, const int32_t *dims, const uint16_t *w_bf16,
                      const float *b_f32, const float *eps);
 
+/* VEM whose exploring interval shrinks during training (Sec. 3.1.1: "the OR
+ * is linearly diminished"; Table 6: OR 16 -> 3 over 500K transitions, E_min
+ * 0.01, E_max 0.8). From this call on, the actor (rollout and sparrow_act)
+ * uses for env i at global step g, with T = n_envs * g transitions,
+ *   m = or_start - floor((or_start - or_final) * min(T, decay) / decay)
+ *       (decay_transitions = 0: m = or_final),
+ *   eps_i = e_min for i < n_envs - m, else e_min + e_max * (i - (n_envs - m))
+ *       / (m - 1) (m = 1: e_min + e_max),
+ * in binary64 rounded once to binary32, instead of the eps array of
+ * sparrow_set_qnet. EINVAL unless e_min, e_max >= 0 and
+ * 0 <= or_final <= or_start <= n_envs, decay_transitions >= 0. */
+int sparrow_set_vem_schedule(sparrow_env *env, double e_min, double e_max, int32_t or_start,
+                             int32_t or_final, int64_t decay_transitions);
+
 /* Q-network forward on given observations (dev obs [n][obs_dim] -> dev q
  * [n][7] FP32, dev greedy [n] int32 = lowest argmax). Same MFMA code as the
  * fused actor: the observation is rounded to bf16 (RNE), layers accumulate in

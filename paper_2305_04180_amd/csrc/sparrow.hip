@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if (t % L == 0 && live) {
         const uint32_t gq = g + (uint32_t)ln.q;
         if constexpr (kQ) {
-          draws = vem_draw(i, gq, eps, p.key0, p.key1);
+          draws = vem_draw(i, gq, qp.vem.on ? vem_eps(qp.vem, i, gq) : eps, p.key0, p.key1);
         } else {
           const U4 w = philox((uint32_t)i, gq, kActionUniform, 0u, p.key0, p.key1);
           draws = scale_u32(w.x, kNumActions);
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
       if (q)
         for (int a = 0; a < kNumActions; ++a) q[(size_t)row * kNumActions + a] = qa[a];
       if (greedy) greedy[row] = gi;
-      if (actions) actions[row] = vem_select(gi, row, g, eps[row], key0, key1);
+      if (actions) actions[row] = vem_select(gi, row, g, actor_eps(qp, eps, row, g), key0, key1);
     }
   }
 }
@@ -350,6 +350,7 @@ struct sparrow_env {
   std::map<std::tuple<int, int, int, int, void*, void*, void*, void*>, GraphEntry> graphs;
   // actor
   bool has_qnet = false;
+  VemSchedule vem{};  // off until sparrow_set_vem_schedule
   QParams qp{};
   void* q_block = nullptr;
   float* eps = nullptr;
@@ -774,8 +775,29 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
                          e->stream));
   (void)w_elems;
   HIP_TRY(hipStreamSynchronize(e->stream));
+  qp.vem = e->vem;
   e->qp = qp;
   e->has_qnet = true;
+  return SPARROW_OK;
+}
+
+int sparrow_set_vem_schedule(sparrow_env* e, double e_min, double e_max, int32_t or_start,
+                             int32_t or_final, int64_t decay_transitions) {
+  if (!e) return fail(SPARROW_EINVAL, "NULL argument");
+  const int N = e->cfg.n_envs;
+  if (!(e_min >= 0.0) || !(e_max >= 0.0) || or_final < 0 || or_final > or_start || or_start > N ||
+      decay_transitions < 0)
+    return fail(SPARROW_EINVAL, "need e_min, e_max >= 0, 0 <= or_final <= or_start <= n_envs, decay >= 0");
+  VemSchedule v{};
+  v.on = 1;
+  v.n = N;
+  v.or_start = or_start;
+  v.or_final = or_final;
+  v.decay = decay_transitions;
+  v.e_min = e_min;
+  v.e_max = e_max;
+  e->vem = v;
+  e->qp.vem = v;
   return SPARROW_OK;
 }
 

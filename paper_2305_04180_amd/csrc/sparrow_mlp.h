@@ -192,7 +192,7 @@ k_mlp(QParams qp, const float* __restrict__ obs, int32_t n, float* __restrict__ 
       if (q)
         for (int a = 0; a < kNumActions; ++a) q[(size_t)row * kNumActions + a] = qa[a];
       if (greedy) greedy[row] = best;
-      if (actions) actions[row] = vem_select(best, row, g, eps[row], key0, key1);
+      if (actions) actions[row] = vem_select(best, row, g, actor_eps(qp, eps, row, g), key0, key1);
     }
   }
 }

@@ -32,6 +32,17 @@ constexpr int kQRows = 16;      // envs per MLP pass (MFMA N)
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// VEM with a shrinking exploring interval (Sec. 3.1.1): after T = n * g
+// transitions (g the global step) the last m(T) envs explore, m(T) =
+// or_start - floor((or_start - or_final) * min(T, decay) / decay), with
+// probabilities rising linearly across them from e_min to e_min + e_max.
+// on = 0: the per-env probabilities of the eps array are used instead.
+struct VemSchedule {
+  int32_t on, n, or_start, or_final;
+  int64_t decay;
+  double e_min, e_max;
+};
+
 struct QParams {
   const uint16_t* w1;  // [h1][d0p] bf16, zero-padded columns
   const uint16_t* w2;  // [h2][h1]
@@ -41,7 +52,27 @@ struct QParams {
   const float* b3;     // [16], entries >= 7 zero
   int32_t d0, d0p, h1, h2;
   int32_t lds_base_words;  // first LDS word of the actor's buffers
+  VemSchedule vem;
 };
+
+// Exploration probability of env i at global step g: binary64 arithmetic in
+// the order written, rounded once to binary32, so every draw compares
+// against the same value the definition gives.
+__device__ __forceinline__ float vem_eps(const VemSchedule& v, int i, uint32_t g) {
+  int32_t m = v.or_final;
+  if (v.decay > 0) {
+    const int64_t T = (int64_t)v.n * (int64_t)g;
+    const int64_t t = T < v.decay ? T : v.decay;
+    m = v.or_start - (int32_t)(((int64_t)(v.or_start - v.or_final) * t) / v.decay);
+  }
+  if (i < v.n - m) return (float)v.e_min;
+  const double frac = m > 1 ? (double)(i - (v.n - m)) / (double)(m - 1) : 1.0;
+  return (float)(v.e_min + v.e_max * frac);
+}
+
+__device__ __forceinline__ float actor_eps(const QParams& q, const float* eps, int i, uint32_t g) {
+  return q.vem.on ? vem_eps(q.vem, i, g) : eps[i];
+}
 
 // LDS: region A holds the bf16 input rows, region B the first hidden layer,
 // region C the second hidden layer.

@@ -28,6 +28,7 @@ EXPORTS = (
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
+    "sparrow_set_vem_schedule",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
     "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
 )
@@ -88,6 +89,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_status": (I32, [P]),
             "sparrow_destroy": (None, [P]),
             "sparrow_last_error": (C.c_char_p, []),
+            "sparrow_set_vem_schedule": (I32, [P, C.c_double, C.c_double, I32, I32, C.c_int64]),
             "sparrow_ring_create": (I32, [I32, I32, C.c_uint64, P, C.POINTER(P)]),
             "sparrow_ring_push": (I32, [P, I32, P, P, P, P, P, P]),
             "sparrow_ring_sample": (I32, [P, I32, U32, P, P, P, P, P, P]),
@@ -227,6 +229,11 @@ class Env:
                 raise ValueError(f"{name}: expected {k} values for dims {tuple(dims)}, got {t.numel()}")
         _check(lib().sparrow_set_qnet(self._h, d, _ptr(w), _ptr(b), _ptr(e)))
         self._qkeep = (w, b, e)
+
+    def set_vem_schedule(self, e_min, e_max, or_start, or_final, decay_transitions):
+        """VEM with an exploring interval shrinking linearly over training."""
+        _check(lib().sparrow_set_vem_schedule(self._h, float(e_min), float(e_max), int(or_start),
+                                              int(or_final), int(decay_transitions)))
 
     def qnet_forward(self, obs, q=None, greedy=None):
         torch = self.torch

@@ -152,7 +152,8 @@ def settled_greedy(q64, bound):
 
 def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where):
     """Step the oracle with its own FP64 actor + VEM next to a GPU rollout
-    (acts, rew, done: [K][N]) and compare. Explored actions equal the
+    (acts, rew, done: [K][N]) and compare; eps is the per-env VEM array, or
+    a function of the step index giving it. Explored actions equal the
     oracle's draw; a greedy action equals the oracle's bf16-activation argmax
     wherever qnet_rounded_bound settles it; an env stays compared while its
     actions equal the FP64 actor's (its trajectory is then the oracle's).
@@ -164,7 +165,7 @@ def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where):
     n_settled = n_greedy = n_agree = 0
     for t in range(K):
         q64 = oracle.qnet_f64(dims, w, b, o_obs)
-        a_o, ex = orc.vem(q64, eps)
+        a_o, ex = orc.vem(q64, eps(t) if callable(eps) else eps)
         exb = ex.astype(bool)
         q_ra = oracle.qnet_f64(dims, w, b, o_obs, round_act=True)
         top, settled = settled_greedy(q_ra, qnet_rounded_bound(dims, w, b, o_obs, RANGE_TOL))

@@ -153,3 +153,7 @@ def test_ring_argument_errors_without_device(lib):
     assert lib.sparrow_ring_status(None) == sparrow.EINVAL
     assert lib.sparrow_ring_size(None) == -1 and lib.sparrow_ring_head(None) == -1
     lib.sparrow_ring_destroy(None)
+
+
+def test_vem_schedule_null_handle(lib):
+    assert lib.sparrow_set_vem_schedule(None, 0.01, 0.8, 16, 3, 500000) == sparrow.EINVAL

@@ -330,3 +330,44 @@ def test_fused_rollout_64_rays_obs68(torch_gpu):
     gf, gi = env.get_state()
     of, oi = orc.get_state()
     compare_state(gf[live], gi[live], of[live], oi[live], "obs68 final")
+
+
+def test_vem_schedule_rollout_and_act(torch_gpu):
+    """VEM with the exploring interval shrinking from 45 envs to 3 over 10
+    vectorized steps (T = 450 transitions), inside a 16-step fused rollout and
+    in the separate actor kernel: every explored action equals the oracle's
+    draw at that step's scheduled probabilities."""
+    import oracle
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=45)
+    K, N = 16, 45
+    banner("VEM schedule: OR 45 -> 3 over 450 transitions, rollout K=16 and act")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps, torch)
+    dims, w, b, _ = _qnet_setup(cfg, env)
+    sched = (0.01, 0.8, N, 3, 10 * N)
+    env.set_vem_schedule(*sched)
+    env.reset()
+    o_obs, _ = orc.reset()
+    g0 = orc.global_step
+    eps_fn = lambda t: oracle.vem_schedule_epsilon(N, g0 + t, *sched)
+    # step 0 is global step 1 (after the reset): T = 45, m = 45 - floor(42 * 45 / 450) = 41
+    assert (eps_fn(0) > 0.01).sum() == 40 and (eps_fn(12) > 0.01).sum() == 2
+    acts, rew, done, obs = env.rollout(K, use_qnet=True)
+    torch.cuda.synchronize()
+    live, o_obs = actor_lockstep(orc, dims, w, b, eps_fn, o_obs, to_np(acts), to_np(rew),
+                                 to_np(done), "vem schedule")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf[live], gi[live], of[live], oi[live], "vem schedule final")
+    # the actor kernel at a step in the middle of the decay
+    env.global_step = orc.global_step = 5
+    a = env.act(torch.as_tensor(o_obs).cuda())
+    torch.cuda.synchronize()
+    a_o, ex = orc.vem(oracle.qnet_f64(dims, w, b, o_obs), eps_fn(5 - g0))
+    exb = ex.astype(bool)
+    assert exb.any()
+    compare_exact(to_np(a)[exb], a_o[exb], "explored actions", "act with schedule")
+    from paper_2305_04180_amd import sparrow
+    with pytest.raises(sparrow.SparrowError):
+        env.set_vem_schedule(0.01, 0.8, 3, 4, 10)  # or_final > or_start
