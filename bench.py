@@ -287,11 +287,11 @@ def counter_traffic(kernel_key):
 
 def env_map_bytes(maps):
     """Packed LDS-ready bytes of all maps: one set word, then H + 2 rows of
-    ceil((W + 1) / 32) words, padded to 16 bytes."""
+    ceil((W + 2) / 32) words, padded to 16 bytes."""
     tot = 0
     for g in maps.grids:
         H, W = g.shape
-        words = 1 + ((W + 1 + 31) // 32) * (H + 2)
+        words = 1 + ((W + 2 + 31) // 32) * (H + 2)
         tot += ((words + 3) // 4) * 16
     return tot
 

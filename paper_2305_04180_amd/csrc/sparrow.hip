@@ -586,7 +586,7 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
     MapMeta mm;
     mm.W = maps->width[m];
     mm.H = maps->height[m];
-    mm.wpr = (mm.W + 1 + 31) / 32;
+    mm.wpr = (mm.W + 2 + 31) / 32;  // at least two set padding columns
     mm.off = (uint32_t)total_words;
     total_words += (uint64_t)words_of(mm);
     e->h_meta[m] = mm;

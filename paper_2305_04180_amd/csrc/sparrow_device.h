@@ -224,16 +224,32 @@ __device__ __forceinline__ int med3i(int x, int lo, int hi) {
   return r;
 }
 
-// A map slot in LDS. Row y (y = -1..H) is n = ceil((W + 1) / 32) words; cell
-// x >= 0 is bit x & 31 of word x >> 5 of its row, and column -1 is bit 31 of
-// the previous row's last word (a column >= W, so set), with one set word in
-// front of row -1. Every bit outside [0, W) x [0, H) is set, so a coordinate
-// clamped to [-1, W] x [-1, H] reads as occupied: outside the map counts as
-// an obstacle. w1 points at word 0 of row 0; the word of (x, y) is
-// w1[y * n + (x >> 5)] with an arithmetic shift, its bit x & 31.
+// A map slot in LDS. Row y (y = -1..H) is n = ceil((W + 2) / 32) words; cell
+// x >= 0 is bit x & 31 of word x >> 5 of its row, and columns -1 and -2 are
+// bits 31 and 30 of the previous row's last word (columns >= W, so set), with
+// one set word in front of row -1. Every bit outside [0, W) x [0, H) is set,
+// so a coordinate clamped to [-1, W] x [-1, H] reads as occupied: outside the
+// map counts as an obstacle. w1 points at word 0 of row 0; the word of (x, y)
+// is w1[y * n + (x >> 5)] with an arithmetic shift, its bit x & 31.
 struct Slot {
   const uint32_t* w1;
   int32_t W, H, wpr;
+  // The march's address: no per-axis clamp, only the word index clamped to
+  // the slot, [-1 - n, (H + 1) n - 1] (the set word in front .. the last word
+  // of row H). Exact for a ray that starts inside the map: consecutive
+  // samples move at most ds |u| <= 1 (+ rounding, < 2 cells) per axis, so the
+  // first sample outside [0, W) x [0, H) lies within two cells of the map and
+  // its word and bit are set ones (rows -1 and H; the two padding columns,
+  // which are also columns -1 and -2 of the next row; the set word or the
+  // clamp for row -2 and row H + 1). Later samples of the same block may
+  // read any word of the slot; they are past the first hit and never count.
+  __device__ __forceinline__ const uint32_t* word_of_march(int ix, int iy, int& bit) const {
+    bit = ix;  // the bit-field extract uses its low five bits
+    int w = __mul24(iy, wpr) + (ix >> 5);
+    w = med3i(w, -1 - wpr, (H + 1) * wpr - 1);
+    asm("" : "+v"(w));
+    return w1 + w;
+  }
   __device__ __forceinline__ const uint32_t* word_of(int ix, int iy, int& bit) const {
     ix = med3i(ix, -1, W);
     iy = med3i(iy, -1, H);
@@ -280,18 +296,19 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
 #define SPARROW_UNROLL 4
 #endif
 constexpr int kUnroll = SPARROW_UNROLL;  // samples per lane per iteration (independent LDS reads)
-constexpr int kNoHit = 1 << 30;
-static_assert(kUnroll <= 32, "hit bits of one block fit a word");
+static_assert(kUnroll <= 31, "hit bits of one block and the sentinel fit a word");
 
 // kUnroll samples k0 + u * stride of one ray: all addresses first, then all
 // LDS reads, then the tests, so the reads are in flight together. Sample
 // distances are t_k = (float)k * ds; with ds == 1 that is (float)k, formed
 // here as (float)k0 + (float)(u * stride), exact for k < 2^24. Returns the
-// smallest hitting k <= M, or kNoHit. Samples past M stay inside the slot
-// (clamped to the ring) and are never reported.
-template <bool UNIT>
+// smallest hitting k of the block, or k0 + kUnroll * stride (one past the
+// block) when none hits; hits past M are the caller's to discard. CLAMPED
+// selects the per-axis clamp (any start) over the march address (a start
+// inside the map).
+template <bool UNIT, bool CLAMPED>
 __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, float ux, float uy,
-                                            float ds, int M, int k0, int stride) {
+                                            float ds, int k0, int stride) {
   const uint32_t* adr[kUnroll];
   int bit[kUnroll];
   const float tk0 = (float)k0;
@@ -300,41 +317,42 @@ __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, flo
     const float tk = UNIT ? tk0 + (float)(u * stride) : (float)(k0 + u * stride) * ds;
     const float px = x + tk * ux;
     const float py = y + tk * uy;
-    adr[u] = m.word_of(cvt_flr(px), cvt_flr(py), bit[u]);
+    adr[u] = CLAMPED ? m.word_of(cvt_flr(px), cvt_flr(py), bit[u])
+                     : m.word_of_march(cvt_flr(px), cvt_flr(py), bit[u]);
   }
   uint32_t wv[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) wv[u] = *adr[u];
-  uint32_t hits = 0;
+  uint32_t hits = 1u << kUnroll;  // sentinel: no hit -> one past the block
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) hits |= __builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) << u;
-  const int kh = hits ? k0 + (int)__builtin_ctz(hits) * stride : kNoHit;
-  return kh <= M ? kh : kNoHit;
+  return k0 + (int)__builtin_ctz(hits) * stride;
 }
 
 // First hit of one ray marched by one lane, from sample k_start (earlier
 // samples are known to be free). Returns -1 when no sample up to M hits.
-template <bool UNIT>
+template <bool UNIT, bool CLAMPED>
 __device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float ux, float uy,
                                           float ds, int M, int k_start) {
-  for (int k0 = k_start; k0 <= M; k0 += kUnroll) {
-    const int kh = sample_block<UNIT>(m, x, y, ux, uy, ds, M, k0, 1);
-    if (kh != kNoHit) return kh;
+  int k0 = k_start;
+  for (;; k0 += kUnroll) {
+    const int kh = sample_block<UNIT, CLAMPED>(m, x, y, ux, uy, ds, k0, 1);
+    if (kh < k0 + kUnroll) return kh <= M ? kh : -1;
+    if (k0 + kUnroll > M) return -1;
   }
-  return -1;
 }
 
 // P lanes per ray (P = L / Lr, a power of two): in iteration `it` lane
 // `phase` tests samples it*P*U + u*P + phase; the lanes of the ray then take
-// the minimum hit, so the ray stops at the first iteration with any hit.
-template <bool UNIT>
+// the minimum, so the ray stops at the first iteration with any hit.
+template <bool UNIT, bool CLAMPED>
 __device__ __forceinline__ int march_split(const Slot& m, float x, float y, float ux, float uy,
                                            float ds, int M, int P, int phase, int Lr, int L,
                                            int k_start) {
   const int span = P * kUnroll;
-  for (int it = 0;; ++it) {
-    const int kb = k_start + it * span;
-    int kl = sample_block<UNIT>(m, x, y, ux, uy, ds, M, kb + phase, P);
+  for (int kb = k_start;; kb += span) {
+    // a lane with no hit reports kb + phase + span: past the block either way
+    int kl = sample_block<UNIT, CLAMPED>(m, x, y, ux, uy, ds, kb + phase, P);
     if (L == 64 && Lr == 32) {
       // partner lane is lane ^ 32: v_permlane32_swap leaves {own, partner}
       // in the two results of every lane, with no LDS round trip
@@ -343,8 +361,8 @@ __device__ __forceinline__ int march_split(const Slot& m, float x, float y, floa
     } else {
       for (int s = Lr; s < L; s <<= 1) kl = min(kl, __shfl_xor(kl, s));
     }
-    if (kl != kNoHit) return kl;
-    if (kb + span - 1 >= M) return -1;
+    if (kl < kb + span) return kl <= M ? kl : -1;
+    if (kb + span > M) return -1;
   }
 }
 
@@ -398,6 +416,8 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
   const int Lr = L >= R2 ? R2 : L;      // rays handled side by side
   const int RPL = L >= R2 ? 1 : R2 / L; // rays per lane
   const int j0 = ln.q % Lr, phase = ln.q / Lr;
+  const int cx = cvt_flr(e.x), cy = cvt_flr(e.y);
+  const bool inside = cx >= 0 && cx < m.W && cy >= 0 && cy < m.H;
 #pragma unroll
   for (int rr = 0; rr < RayDirs<L>::kMaxRPL; ++rr) {
     if (rr >= RPL) break;
@@ -410,13 +430,19 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
     }
     int kh = -1;
     if (valid) {
-      const bool unit = p.ds == 1.0f;
-      if (P == 1)
-        kh = unit ? march_lane<true>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
-                  : march_lane<false>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start);
+      // the unclamped march address needs a start inside the map and steps
+      // of at most one cell (ds <= 1); anything else takes the clamped one
+      // (the generic path gives the same t_k = (float)k * 1 when ds == 1;
+      // 16-lane envs, which march several rays per lane, keep one path to
+      // stay within the register budget)
+      if (L >= 32 && p.ds == 1.0f && inside)
+        kh = P == 1 ? march_lane<true, false>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                    : march_split<true, false>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
+                                               k_start);
       else
-        kh = unit ? march_split<true>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L, k_start)
-                  : march_split<false>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L, k_start);
+        kh = P == 1 ? march_lane<false, true>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                    : march_split<false, true>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
+                                               k_start);
     }
     if (valid && phase == 0) {
       const float d = kh < 0 ? p.range : (float)kh * p.ds;
