@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       int a_hat = 0;
       if constexpr (kQ) {
         // barriers inside; the wave's env columns are slot % 16
-        const f32x4 tile = qnet_forward_group<QC>(qp, qw, w3, lds, threadIdx.x);
+        // LDS reads run ahead of the MFMAs where the registers allow it
+        const f32x4 tile = qnet_forward_group<QC, (L >= 32 ? 4 : 1)>(qp, qw, w3, lds, threadIdx.x);
         float qa[kNumActions];
         const int greedy = qnet_q_values(qp, tile, slot & 15, qa);
         if (live) a_hat = draw >= 0 ? draw : greedy;
@@ -272,7 +273,7 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
       row[k] = (r0 + r < n && k < qp.d0) ? bf16_rne(obs[(size_t)(r0 + r) * qp.d0 + k]) : 0;
     }
     __syncthreads();
-    const f32x4 tile = qnet_forward_group<QC>(qp, qw, w3, lds, threadIdx.x);
+    const f32x4 tile = qnet_forward_group<QC, 4>(qp, qw, w3, lds, threadIdx.x);
     // wave 0 reports the 16 rows; lane r < 16 takes row r
     const int r = threadIdx.x & 15;
     float qa[kNumActions];

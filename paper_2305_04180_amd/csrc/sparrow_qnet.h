@@ -172,7 +172,7 @@ __device__ __forceinline__ uint32_t pack_relu_bf16x2(float lo, float hi) {
 }
 
 // One dense layer for this wave's output tiles: out[env][h] = relu(W x + b).
-template <int T, int KS>
+template <int T, int KS, int AHEAD>
 __device__ __forceinline__ void qnet_layer(const bf16x8 (&a)[T][KS], const f32x4 (&bias)[T],
                                            const uint16_t* in, int in_stride, uint16_t* out,
                                            int out_stride, int tile0, int l) {
@@ -180,12 +180,23 @@ __device__ __forceinline__ void qnet_layer(const bf16x8 (&a)[T][KS], const f32x4
   f32x4 acc[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  // K outer, tiles inner: one B fragment live at a time
+  // B fragments run up to AHEAD K steps ahead of the MFMAs that use them,
+  // so the LDS reads overlap the multiplies (K outer, tiles inner); AHEAD = 1
+  // reads each fragment in its own step
+  constexpr int kAhead = KS < AHEAD ? KS : AHEAD;
+  bf16x8 b[kAhead];
+  if (kAhead > 1)
+#pragma unroll
+    for (int ks = 0; ks < kAhead; ++ks)
+      b[ks] = *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq);
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq);
+    const bf16x8 cur = kAhead == 1 ? *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq)
+                                   : b[ks % kAhead];
+    if (kAhead > 1 && ks + kAhead < KS)
+      b[ks % kAhead] = *reinterpret_cast<const bf16x8*>(in + env * in_stride + (ks + kAhead) * 32 + kq);
 #pragma unroll
-    for (int t = 0; t < T; ++t) acc[t] = mfma16x16x32(a[t][ks], b, acc[t]);
+    for (int t = 0; t < T; ++t) acc[t] = mfma16x16x32(a[t][ks], cur, acc[t]);
   }
 #pragma unroll
   for (int t = 0; t < T; ++t) {
@@ -219,7 +230,7 @@ __device__ __forceinline__ void qnet_load_w3(const QParams& q, int tid, W3Frag<Q
 // Forward pass over the 16 input rows in LDS region A (the caller has made
 // them visible with a barrier). Returns this lane's layer-3 tile: Q[a][env]
 // for actions a = 4 * (lane / 16) + 0..3 and env = lane % 16.
-template <class QC>
+template <class QC, int AHEAD>
 __device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
                                                     const typename QC::Weights& W,
                                                     const W3Frag<QC>& w3, uint32_t* lds,
@@ -231,17 +242,35 @@ __device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
     uint16_t* ra = qnet_region_a(q, lds);
     uint16_t* rb = qnet_region_b(q, lds);
     uint16_t* rc = qnet_region_c(q, lds);
-    qnet_layer<QC::T1, QC::K1>(W.a1, W.bias1, ra, qnet_stride0(q), rb, qnet_stride1(q),
-                               w * QC::T1, l);
+    qnet_layer<QC::T1, QC::K1, AHEAD>(W.a1, W.bias1, ra, qnet_stride0(q), rb, qnet_stride1(q),
+                                      w * QC::T1, l);
     __syncthreads();
-    qnet_layer<QC::T2, QC::K2>(W.a2, W.bias2, rb, qnet_stride1(q), rc, qnet_stride2(q),
-                               w * QC::T2, l);
+    qnet_layer<QC::T2, QC::K2, AHEAD>(W.a2, W.bias2, rb, qnet_stride1(q), rc, qnet_stride2(q),
+                                      w * QC::T2, l);
     __syncthreads();
+    // two accumulator chains (even and odd K steps) halve the dependent
+    // MFMA latency; their sum is one more FP32 rounding of the same terms
+    f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+    constexpr int kAhead = QC::K3 < AHEAD ? QC::K3 : AHEAD;
+    bf16x8 b[kAhead];
+    if (kAhead > 1)
+#pragma unroll
+      for (int ks = 0; ks < kAhead; ++ks)
+        b[ks] = *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq);
 #pragma unroll
     for (int ks = 0; ks < QC::K3; ++ks) {
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq);
-      acc = mfma16x16x32(w3.a[ks], b, acc);
+      const bf16x8 cur =
+          kAhead == 1 ? *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq)
+                      : b[ks % kAhead];
+      if (kAhead > 1 && ks + kAhead < QC::K3)
+        b[ks % kAhead] =
+            *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + (ks + kAhead) * 32 + kq);
+      if (ks & 1)
+        acc2 = mfma16x16x32(w3.a[ks], cur, acc2);
+      else
+        acc = mfma16x16x32(w3.a[ks], cur, acc);
     }
+    acc = acc + acc2;
   }
   return acc;
 }
