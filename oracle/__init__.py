@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "sparrow_oracle.c")
 SRC_RING = os.path.join(HERE, "ring_oracle.c")
+SRC_LEARNER = os.path.join(HERE, "learner_oracle.c")
 
 STOP = 7
 N_ACTIONS = 7
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with strict IEEE binary32 semantics."""
     if force or not os.path.exists(LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-o", LIB_PATH, SRC, SRC_RING, "-lm"]
+               "-fPIC", "-shared", "-o", LIB_PATH, SRC, SRC_RING, SRC_LEARNER, "-lm"]
         subprocess.check_call(cmd)
     return LIB_PATH
 
@@ -59,6 +60,12 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class LearnerConfig(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("adam_eps", C.c_double), ("huber_k", C.c_double),
+                ("target_every", C.c_int32)]
 
 
 _lib = None
@@ -120,6 +127,15 @@ def lib():
         L.orc_ring_gather.argtypes = [P, C.c_int32, P, P, P, P, P, P]
         L.orc_ring_sample.restype = C.c_int32
         L.orc_ring_sample.argtypes = [P, C.c_int32, C.c_uint32, P, P, P, P, P, P]
+        L.orc_learner_create.restype = P
+        L.orc_learner_create.argtypes = [P, P, P, C.POINTER(LearnerConfig)]
+        L.orc_learner_destroy.argtypes = [P]
+        L.orc_learner_update.restype = C.c_int32
+        L.orc_learner_update.argtypes = [P, C.c_int32, P, P, P, P, P, P, P, P]
+        L.orc_learner_get.argtypes = [P, P, P, P, P]
+        L.orc_learner_steps.restype = C.c_int64
+        L.orc_learner_steps.argtypes = [P]
+        L.orc_learner_q.argtypes = [P, C.c_int32, C.c_int32, P, P]
         L.orc_f16_rne.restype = C.c_uint16
         L.orc_f16_rne.argtypes = [C.c_float]
         L.orc_f16_to_f32.restype = C.c_float
@@ -395,3 +411,60 @@ class Ring:
         if rc:
             raise ValueError("empty ring")
         return s, a, r, sn, d, idx
+
+
+# ---------------------------------------------------------------------------
+# Learner (Alg. 2 step 2: DDQN update). Definitions: learner_oracle.h.
+# ---------------------------------------------------------------------------
+class Learner:
+    def __init__(self, dims, w, b, gamma=0.98, lr=1e-4, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                 huber_k=1.0, target_every=200):
+        self.dims = tuple(int(d) for d in dims)
+        d0, h1, h2, A = self.dims
+        self.nw = h1 * d0 + h2 * h1 + A * h2
+        self.nb = h1 + h2 + A
+        w = np.ascontiguousarray(w, np.float32)
+        b = np.ascontiguousarray(b, np.float32)
+        assert w.size == self.nw and b.size == self.nb
+        self.cfg = LearnerConfig(gamma, lr, beta1, beta2, adam_eps, huber_k, target_every)
+        d = np.asarray(self.dims, np.int32)
+        self._h = lib().orc_learner_create(_p(d), _p(w), _p(b), C.byref(self.cfg))
+        if not self._h:
+            raise MemoryError("orc_learner_create failed")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_learner_destroy(self._h)
+            self._h = None
+
+    def update(self, s, a, r, s_next, done):
+        B = len(a)
+        s = np.ascontiguousarray(s, np.float32)
+        s_next = np.ascontiguousarray(s_next, np.float32)
+        a = np.ascontiguousarray(a, np.int32)
+        r = np.ascontiguousarray(r, np.float32)
+        d = np.ascontiguousarray(done, np.uint8)
+        loss = np.zeros(1, np.float64)
+        gw = np.zeros(self.nw, np.float64)
+        gb = np.zeros(self.nb, np.float64)
+        rc = lib().orc_learner_update(self._h, B, _p(s), _p(a), _p(r), _p(s_next), _p(d),
+                                      _p(loss), _p(gw), _p(gb))
+        if rc:
+            raise ValueError("empty mini-batch")
+        return float(loss[0]), gw, gb
+
+    def params(self):
+        w, b = np.zeros(self.nw), np.zeros(self.nb)
+        wt, bt = np.zeros(self.nw), np.zeros(self.nb)
+        lib().orc_learner_get(self._h, _p(w), _p(b), _p(wt), _p(bt))
+        return w, b, wt, bt
+
+    @property
+    def steps(self):
+        return int(lib().orc_learner_steps(self._h))
+
+    def q(self, x, target=False):
+        x = np.ascontiguousarray(x, np.float32)
+        q = np.zeros((x.shape[0], self.dims[3]), np.float64)
+        lib().orc_learner_q(self._h, int(bool(target)), x.shape[0], _p(x), _p(q))
+        return q
