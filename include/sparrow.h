@@ -255,6 +255,50 @@ int64_t sparrow_ring_head(const sparrow_ring *ring);
 int sparrow_ring_status(sparrow_ring *ring);
 void sparrow_ring_destroy(sparrow_ring *ring);
 
+/* ---- Learner ---------------------------------------------------------------
+ * The learner's update of Alg. 2 step 2 (train the learner's model on a
+ * mini-batch with DDQN; Table 6: gamma 0.98, learning rate 1e-4, target
+ * network every 200 updates, mini-batch 256), on the device in FP32:
+ *   a*   = argmax_a Q_online(s') (lowest index on ties),
+ *   y    = r + gamma (1 - done) Q_target(s')[a*]  (a constant),
+ *   loss = mean over the batch of huber_k(Q_online(s)[a] - y),
+ * gradients by back-propagation (relu'(0) = 0), one Adam step (bias-
+ * corrected) on every weight and bias, and after every target_every-th
+ * update the target network becomes a copy of the online one. The network
+ * is that of sparrow_set_qnet (Sec. 4.3.2, ReLU), weights row-major
+ * [out][in], concatenated [W1 | W2 | W3], biases [b1 | b2 | b3]. */
+typedef struct {
+  float gamma, lr, beta1, beta2, adam_eps, huber_k;
+  int32_t target_every; /* 0: the target network never changes */
+  int32_t max_batch;    /* largest mini-batch (scratch is sized for it), <= 65535 */
+} sparrow_learner_config;
+typedef struct sparrow_learner sparrow_learner;
+
+/* dims (host) = {d0 <= 128, h1 <= 512, h2 <= 512, A <= 16}; w, b: host FP32
+ * initial weights (copied; the target network starts equal). */
+int sparrow_learner_create(const int32_t *dims, const float *w_host, const float *b_host,
+                           const sparrow_learner_config *cfg, void *hip_stream,
+                           sparrow_learner **out);
+/* One update on B <= max_batch transitions (dev: s, s_next [B][d0] FP32, a
+ * int32 [B], r FP32 [B], done uint8 [B]); loss (dev [1], nullable) receives
+ * the mini-batch loss. Asynchronous on the learner's stream. */
+int sparrow_learner_update(sparrow_learner *L, int32_t B, const float *s, const int32_t *a,
+                           const float *r, const float *s_next, const uint8_t *done,
+                           float *loss);
+/* Q of the online (which = 0) or target (1) network on n <= max_batch rows
+ * (dev x [n][d0] -> dev q [n][A]). */
+int sparrow_learner_q(sparrow_learner *L, int32_t which, int32_t n, const float *x, float *q);
+/* The online network for the actor (Alg. 2 step 3 uploads it to the
+ * sharer, Alg. 1 step 1 downloads it): weights rounded to bf16 (RNE, dev
+ * [nw] bit patterns) and biases (dev [nb] FP32), ready for sparrow_set_qnet. */
+int sparrow_learner_export_bf16(sparrow_learner *L, uint16_t *w_bf16, float *b);
+/* Synchronising copies to host (each nullable): online and target weights
+ * and biases, and the last update's gradients. */
+int sparrow_learner_read(sparrow_learner *L, float *w, float *b, float *wt, float *bt,
+                         float *gw, float *gb);
+int64_t sparrow_learner_steps(const sparrow_learner *L);
+void sparrow_learner_destroy(sparrow_learner *L);
+
 #ifdef __cplusplus
 }
 #endif

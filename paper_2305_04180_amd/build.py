@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparrow.so")
-SOURCES = [os.path.join(CSRC, "sparrow.hip"), os.path.join(CSRC, "sparrow_ring.hip")]
+SOURCES = [os.path.join(CSRC, "sparrow.hip"), os.path.join(CSRC, "sparrow_ring.hip"),
+           os.path.join(CSRC, "sparrow_learner.hip")]
 HEADERS = [os.path.join(CSRC, "sparrow_device.h"), os.path.join(CSRC, "sparrow_qnet.h"),
            os.path.join(CSRC, "sparrow_host.h"),
            os.path.join(ROOT, "include", "sparrow.h")]

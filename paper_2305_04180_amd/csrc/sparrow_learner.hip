@@ -1,0 +1,438 @@
+// sparrow_learner.hip -- the learner's update (Alg. 2 step 2: a mini-batch
+// sampled from the sharer's buffer trains the learner's model with DDQN;
+// Table 6: gamma, learning rate, target-network period, mini-batch 256).
+//
+// One update on B transitions (s, a, r, s', done), all in FP32 with every sum
+// in a fixed order (the products are small -- a 256-row mini-batch through a
+// 36-256-256-7 network is ~0.1 GFLOP per pass -- and latency-bound, so the
+// vector units serve them and keep them within FP32 rounding of binary64):
+//   k_learn_fwd   Q of the online network on s (its activations kept for
+//                 back-propagation), of the online and the target network on
+//                 s'; one workgroup per (pass, row), one thread per unit
+//   k_learn_loss  a* = argmax Q_online(s') (lowest index on ties), y = r +
+//                 gamma (1 - done) Q_target(s')[a*], delta = Q(s)[a] - y,
+//                 dloss/dQ[a] = clip(delta, -k, k) / B, loss = mean Huber
+//   k_learn_g3 / k_learn_g2 / k_learn_d1 / k_learn_g1
+//                 back-propagation: one thread per gradient entry, the sum
+//                 over the mini-batch in row order; relu'(0) = 0
+//   k_learn_adam  Adam on every weight and bias, then the transposed copies
+//                 the forward pass reads; every target_every-th update the
+//                 target network becomes a copy of the online one
+// Weights are row-major [out][in], concatenated [W1 | W2 | W3]; biases
+// [b1 | b2 | b3].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sparrow.h"
+#include "sparrow_device.h"
+#include "sparrow_host.h"
+
+using namespace sp;
+
+namespace {
+
+constexpr int kMaxUnits = 512;
+
+struct Net {  // device views of one network
+  const float* W1T;  // [d0][h1] (transposed copy for the forward pass)
+  const float* W2T;  // [h1][h2]
+  const float* W3;   // [A][h2]
+  const float* b1;
+  const float* b2;
+  const float* b3;
+};
+
+struct Dims {
+  int32_t d0, h1, h2, A;
+};
+
+// pass 0: online on s (activations kept), 1: online on s', 2: target on s'
+__global__ void __launch_bounds__(kMaxUnits)
+k_learn_fwd(Dims dm, Net on, Net tg, int32_t B, const float* __restrict__ s,
+            const float* __restrict__ sn, float* __restrict__ a1_out, float* __restrict__ a2_out,
+            float* __restrict__ q_out /* [3][B][A] */) {
+  __shared__ float x[128];
+  __shared__ float h1v[kMaxUnits];
+  __shared__ float h2v[kMaxUnits];
+  const int pass = blockIdx.y, row = blockIdx.x, tid = threadIdx.x;
+  const Net& n = pass == 2 ? tg : on;
+  const float* src = (pass == 0 ? s : sn) + (size_t)row * dm.d0;
+  for (int k = tid; k < dm.d0; k += blockDim.x) x[k] = src[k];
+  __syncthreads();
+  if (tid < dm.h1) {
+    float acc = n.b1[tid];
+    for (int k = 0; k < dm.d0; ++k) acc += n.W1T[(size_t)k * dm.h1 + tid] * x[k];
+    const float a = fmaxf(acc, 0.0f);
+    h1v[tid] = a;
+    if (pass == 0) a1_out[(size_t)row * dm.h1 + tid] = a;
+  }
+  __syncthreads();
+  if (tid < dm.h2) {
+    float acc = n.b2[tid];
+    for (int k = 0; k < dm.h1; ++k) acc += n.W2T[(size_t)k * dm.h2 + tid] * h1v[k];
+    const float a = fmaxf(acc, 0.0f);
+    h2v[tid] = a;
+    if (pass == 0) a2_out[(size_t)row * dm.h2 + tid] = a;
+  }
+  __syncthreads();
+  // output o: 32 lanes take every 32nd unit, then a fixed-order halving sum
+  const int o = tid >> 5, j = tid & 31;
+  float part = 0.0f;
+  if (o < dm.A)
+    for (int k = j; k < dm.h2; k += 32) part += n.W3[(size_t)o * dm.h2 + k] * h2v[k];
+  for (int off = 16; off > 0; off >>= 1) part += __shfl_down(part, off, 32);
+  if (o < dm.A && j == 0) q_out[((size_t)pass * B + row) * dm.A + o] = n.b3[o] + part;
+}
+
+// One workgroup: per-row targets and Huber gradients, then the mean loss by a
+// fixed-order tree.
+__global__ void __launch_bounds__(1024)
+k_learn_loss(Dims dm, int32_t B, float gamma, float k_h, const int32_t* __restrict__ a,
+             const float* __restrict__ r, const uint8_t* __restrict__ done,
+             const float* __restrict__ q, float* __restrict__ g_out, float* __restrict__ loss) {
+  __shared__ float part[1024];
+  const int tid = threadIdx.x;
+  float acc = 0.0f;
+  for (int b = tid; b < B; b += blockDim.x) {
+    const float* qon_s = q + (size_t)b * dm.A;
+    const float* qon_n = q + ((size_t)B + b) * dm.A;
+    const float* qtg_n = q + ((size_t)2 * B + b) * dm.A;
+    int best = 0;
+    for (int o = 1; o < dm.A; ++o)
+      if (qon_n[o] > qon_n[best]) best = o;
+    const float y = r[b] + gamma * (done[b] ? 0.0f : 1.0f) * qtg_n[best];
+    const float delta = qon_s[a[b]] - y;
+    const float ad = fabsf(delta);
+    acc += ad <= k_h ? 0.5f * delta * delta : k_h * (ad - 0.5f * k_h);
+    g_out[b] = fminf(fmaxf(delta, -k_h), k_h) / (float)B;
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && loss) loss[0] = part[0] / (float)B;
+}
+
+// layer 3: gW3[o][h] = sum_b [a_b == o] g_b a2[b][h]; gb3[o] likewise
+__global__ void k_learn_g3(Dims dm, int32_t B, const int32_t* __restrict__ a,
+                           const float* __restrict__ g, const float* __restrict__ a2,
+                           float* __restrict__ gW3, float* __restrict__ gb3) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= dm.A * (dm.h2 + 1)) return;
+  const int o = t / (dm.h2 + 1), h = t % (dm.h2 + 1);
+  float acc = 0.0f;
+  for (int b = 0; b < B; ++b)
+    if (a[b] == o) acc += g[b] * (h < dm.h2 ? a2[(size_t)b * dm.h2 + h] : 1.0f);
+  if (h < dm.h2)
+    gW3[(size_t)o * dm.h2 + h] = acc;
+  else
+    gb3[o] = acc;
+}
+
+// da2[b][o] = [a2 > 0] g_b W3[a_b][o]; layer 2: gW2[o][k] = sum_b da2[b][o] a1[b][k]
+__global__ void k_learn_g2(Dims dm, int32_t B, const int32_t* __restrict__ a,
+                           const float* __restrict__ g, const float* __restrict__ W3,
+                           const float* __restrict__ a1, const float* __restrict__ a2,
+                           float* __restrict__ gW2, float* __restrict__ gb2) {
+  const int o = blockIdx.y;  // one row of W2 per grid row
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > dm.h1) return;
+  float acc = 0.0f;
+  for (int b = 0; b < B; ++b) {
+    const float a2v = a2[(size_t)b * dm.h2 + o];
+    const float d2 = a2v > 0.0f ? g[b] * W3[(size_t)a[b] * dm.h2 + o] : 0.0f;
+    acc += d2 * (k < dm.h1 ? a1[(size_t)b * dm.h1 + k] : 1.0f);
+  }
+  if (k < dm.h1)
+    gW2[(size_t)o * dm.h1 + k] = acc;
+  else
+    gb2[o] = acc;
+}
+
+// da1[b][k] = [a1 > 0] sum_o da2[b][o] W2[o][k]
+__global__ void k_learn_d1(Dims dm, int32_t B, const int32_t* __restrict__ a,
+                           const float* __restrict__ g, const float* __restrict__ W2,
+                           const float* __restrict__ W3, const float* __restrict__ a1,
+                           const float* __restrict__ a2, float* __restrict__ da1) {
+  const int b = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= dm.h1) return;
+  const float gb = g[b];
+  const float* w3row = W3 + (size_t)a[b] * dm.h2;
+  float acc = 0.0f;
+  for (int o = 0; o < dm.h2; ++o) {
+    const float a2v = a2[(size_t)b * dm.h2 + o];
+    const float d2 = a2v > 0.0f ? gb * w3row[o] : 0.0f;
+    acc += d2 * W2[(size_t)o * dm.h1 + k];
+  }
+  da1[(size_t)b * dm.h1 + k] = a1[(size_t)b * dm.h1 + k] > 0.0f ? acc : 0.0f;
+}
+
+// layer 1: gW1[o][k] = sum_b da1[b][o] s[b][k]; gb1[o] likewise
+__global__ void k_learn_g1(Dims dm, int32_t B, const float* __restrict__ da1,
+                           const float* __restrict__ s, float* __restrict__ gW1,
+                           float* __restrict__ gb1) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= dm.h1 * (dm.d0 + 1)) return;
+  const int o = t / (dm.d0 + 1), k = t % (dm.d0 + 1);
+  float acc = 0.0f;
+  for (int b = 0; b < B; ++b)
+    acc += da1[(size_t)b * dm.h1 + o] * (k < dm.d0 ? s[(size_t)b * dm.d0 + k] : 1.0f);
+  if (k < dm.d0)
+    gW1[(size_t)o * dm.d0 + k] = acc;
+  else
+    gb1[o] = acc;
+}
+
+__global__ void k_learn_adam(int64_t n, float* __restrict__ p, float* __restrict__ m,
+                             float* __restrict__ v, const float* __restrict__ g, float lr,
+                             float beta1, float beta2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// W [rows][cols] -> WT [cols][rows]
+__global__ void k_learn_transpose(const float* __restrict__ W, float* __restrict__ WT, int rows,
+                                  int cols) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int r = t / cols, c = t % cols;
+  WT[(size_t)c * rows + r] = W[t];
+}
+
+__global__ void k_learn_bf16(int64_t n, const float* __restrict__ w, uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = bf16_rne(w[i]);
+}
+
+int blocks_for(int64_t n, int t) { return (int)std::max<int64_t>(1, (n + t - 1) / t); }
+
+}  // namespace
+
+struct sparrow_learner {
+  Dims dm{};
+  sparrow_learner_config cfg{};
+  int64_t nw = 0, nb = 0, steps = 0;
+  int32_t max_batch = 0;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+  // online (w, b), target (wt, bt), Adam moments, gradients, transposes
+  float *w = nullptr, *b = nullptr, *wt = nullptr, *bt = nullptr;
+  float *mw = nullptr, *vw = nullptr, *mb = nullptr, *vb = nullptr, *gw = nullptr, *gb = nullptr;
+  float *w1t = nullptr, *w2t = nullptr, *w1t_t = nullptr, *w2t_t = nullptr;
+  // per-batch scratch
+  float *a1 = nullptr, *a2 = nullptr, *q = nullptr, *g = nullptr, *da1 = nullptr;
+};
+
+namespace {
+
+int lalloc(sparrow_learner* L, float** p, size_t n) {
+  if (hipMalloc((void**)p, sizeof(float) * std::max<size_t>(n, 1)) != hipSuccess)
+    return fail(SPARROW_ENOMEM, "hipMalloc failed");
+  L->allocs.push_back(*p);
+  return SPARROW_OK;
+}
+
+Net net_of(const sparrow_learner* L, bool target) {
+  const Dims& d = L->dm;
+  const float* w = target ? L->wt : L->w;
+  const float* b = target ? L->bt : L->b;
+  Net n;
+  n.W1T = target ? L->w1t_t : L->w1t;
+  n.W2T = target ? L->w2t_t : L->w2t;
+  n.W3 = w + (size_t)d.h1 * d.d0 + (size_t)d.h2 * d.h1;
+  n.b1 = b;
+  n.b2 = b + d.h1;
+  n.b3 = b + d.h1 + d.h2;
+  return n;
+}
+
+int refresh_transposes(sparrow_learner* L, bool target) {
+  const Dims& d = L->dm;
+  const float* w = target ? L->wt : L->w;
+  const int n1 = d.h1 * d.d0, n2 = d.h2 * d.h1;
+  hipLaunchKernelGGL(k_learn_transpose, dim3(blocks_for(n1, 256)), dim3(256), 0, L->stream, w,
+                     target ? L->w1t_t : L->w1t, d.h1, d.d0);
+  hipLaunchKernelGGL(k_learn_transpose, dim3(blocks_for(n2, 256)), dim3(256), 0, L->stream,
+                     w + n1, target ? L->w2t_t : L->w2t, d.h2, d.h1);
+  HIP_TRY(hipGetLastError());
+  return SPARROW_OK;
+}
+
+}  // namespace
+
+int sparrow_learner_create(const int32_t* dims, const float* w_host, const float* b_host,
+                           const sparrow_learner_config* cfg, void* hip_stream,
+                           sparrow_learner** out) {
+  if (!dims || !w_host || !b_host || !cfg || !out) return fail(SPARROW_EINVAL, "NULL argument");
+  *out = nullptr;
+  const Dims d{dims[0], dims[1], dims[2], dims[3]};
+  if (d.d0 < 1 || d.d0 > 128 || d.h1 < 1 || d.h1 > kMaxUnits || d.h2 < 1 || d.h2 > kMaxUnits ||
+      d.A < 1 || d.A > 16)
+    return fail(SPARROW_EINVAL, "learner dims must be d0 <= 128, h1, h2 <= 512, A <= 16");
+  if (cfg->max_batch < 1 || cfg->max_batch > 65535 || !(cfg->lr >= 0.0f) ||
+      !(cfg->gamma >= 0.0f) || !(cfg->huber_k > 0.0f) || cfg->target_every < 0)
+    return fail(SPARROW_EINVAL, "bad learner configuration");
+  auto* L = new sparrow_learner();
+  L->dm = d;
+  L->cfg = *cfg;
+  L->max_batch = cfg->max_batch;
+  L->stream = (hipStream_t)hip_stream;
+  L->nw = (int64_t)d.h1 * d.d0 + (int64_t)d.h2 * d.h1 + (int64_t)d.A * d.h2;
+  L->nb = (int64_t)d.h1 + d.h2 + d.A;
+  const size_t B = (size_t)L->max_batch;
+  int rc = SPARROW_OK;
+  float** big[] = {&L->w, &L->wt, &L->mw, &L->vw, &L->gw};
+  float** small[] = {&L->b, &L->bt, &L->mb, &L->vb, &L->gb};
+  for (float** p : big)
+    if (!rc) rc = lalloc(L, p, (size_t)L->nw);
+  for (float** p : small)
+    if (!rc) rc = lalloc(L, p, (size_t)L->nb);
+  if (!rc) rc = lalloc(L, &L->w1t, (size_t)d.h1 * d.d0);
+  if (!rc) rc = lalloc(L, &L->w2t, (size_t)d.h2 * d.h1);
+  if (!rc) rc = lalloc(L, &L->w1t_t, (size_t)d.h1 * d.d0);
+  if (!rc) rc = lalloc(L, &L->w2t_t, (size_t)d.h2 * d.h1);
+  if (!rc) rc = lalloc(L, &L->a1, B * d.h1);
+  if (!rc) rc = lalloc(L, &L->a2, B * d.h2);
+  if (!rc) rc = lalloc(L, &L->da1, B * d.h1);
+  if (!rc) rc = lalloc(L, &L->q, 3 * B * d.A);
+  if (!rc) rc = lalloc(L, &L->g, B);
+  if (rc) {
+    sparrow_learner_destroy(L);
+    return rc;
+  }
+  auto up = [&](float* dst, const float* src, int64_t n) {
+    return hipMemcpyAsync(dst, src, sizeof(float) * n, hipMemcpyHostToDevice, L->stream);
+  };
+  hipError_t e = up(L->w, w_host, L->nw);
+  if (e == hipSuccess) e = up(L->wt, w_host, L->nw);
+  if (e == hipSuccess) e = up(L->b, b_host, L->nb);
+  if (e == hipSuccess) e = up(L->bt, b_host, L->nb);
+  for (float* p : {L->mw, L->vw})
+    if (e == hipSuccess) e = hipMemsetAsync(p, 0, sizeof(float) * L->nw, L->stream);
+  for (float* p : {L->mb, L->vb})
+    if (e == hipSuccess) e = hipMemsetAsync(p, 0, sizeof(float) * L->nb, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) {
+    sparrow_learner_destroy(L);
+    return fail(SPARROW_EHIP, std::string("learner upload: ") + hipGetErrorString(e));
+  }
+  rc = refresh_transposes(L, false);
+  if (!rc) rc = refresh_transposes(L, true);
+  if (rc) {
+    sparrow_learner_destroy(L);
+    return rc;
+  }
+  *out = L;
+  return SPARROW_OK;
+}
+
+static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const float* sn) {
+  const Dims& d = L->dm;
+  const int threads = std::max(64, ((std::max({d.h1, d.h2, 32 * d.A}) + 63) / 64) * 64);
+  hipLaunchKernelGGL(k_learn_fwd, dim3(B, 3), dim3(threads), 0, L->stream, d, net_of(L, false),
+                     net_of(L, true), B, s, sn, L->a1, L->a2, L->q);
+  HIP_TRY(hipGetLastError());
+  return SPARROW_OK;
+}
+
+int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const int32_t* a,
+                           const float* r, const float* s_next, const uint8_t* done,
+                           float* loss) {
+  if (!L || !s || !a || !r || !s_next || !done) return fail(SPARROW_EINVAL, "NULL argument");
+  if (B < 1 || B > L->max_batch) return fail(SPARROW_EINVAL, "mini-batch size out of range");
+  const Dims& d = L->dm;
+  int rc = learner_forward(L, B, s, s_next);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_learn_loss, dim3(1), dim3(1024), 0, L->stream, d, B, L->cfg.gamma,
+                     L->cfg.huber_k, a, r, done, L->q, L->g, loss);
+  const int64_t off2 = (int64_t)d.h1 * d.d0, off3 = off2 + (int64_t)d.h2 * d.h1;
+  const float* W2 = L->w + off2;
+  const float* W3 = L->w + off3;
+  hipLaunchKernelGGL(k_learn_g3, dim3(blocks_for((int64_t)d.A * (d.h2 + 1), 256)), dim3(256), 0,
+                     L->stream, d, B, a, L->g, L->a2, L->gw + off3, L->gb + d.h1 + d.h2);
+  hipLaunchKernelGGL(k_learn_g2, dim3(blocks_for(d.h1 + 1, 256), d.h2), dim3(256), 0, L->stream,
+                     d, B, a, L->g, W3, L->a1, L->a2, L->gw + off2, L->gb + d.h1);
+  hipLaunchKernelGGL(k_learn_d1, dim3(blocks_for(d.h1, 256), B), dim3(256), 0, L->stream, d, B, a,
+                     L->g, W2, W3, L->a1, L->a2, L->da1);
+  hipLaunchKernelGGL(k_learn_g1, dim3(blocks_for((int64_t)d.h1 * (d.d0 + 1), 256)), dim3(256), 0,
+                     L->stream, d, B, L->da1, s, L->gw, L->gb);
+  HIP_TRY(hipGetLastError());
+  L->steps += 1;
+  const double c1 = 1.0 - std::pow((double)L->cfg.beta1, (double)L->steps);
+  const double c2 = 1.0 - std::pow((double)L->cfg.beta2, (double)L->steps);
+  hipLaunchKernelGGL(k_learn_adam, dim3(blocks_for(L->nw, 256)), dim3(256), 0, L->stream, L->nw,
+                     L->w, L->mw, L->vw, L->gw, L->cfg.lr, L->cfg.beta1, L->cfg.beta2,
+                     L->cfg.adam_eps, (float)c1, (float)c2);
+  hipLaunchKernelGGL(k_learn_adam, dim3(blocks_for(L->nb, 256)), dim3(256), 0, L->stream, L->nb,
+                     L->b, L->mb, L->vb, L->gb, L->cfg.lr, L->cfg.beta1, L->cfg.beta2,
+                     L->cfg.adam_eps, (float)c1, (float)c2);
+  HIP_TRY(hipGetLastError());
+  rc = refresh_transposes(L, false);
+  if (rc) return rc;
+  if (L->cfg.target_every > 0 && L->steps % L->cfg.target_every == 0) {
+    HIP_TRY(hipMemcpyAsync(L->wt, L->w, sizeof(float) * L->nw, hipMemcpyDeviceToDevice, L->stream));
+    HIP_TRY(hipMemcpyAsync(L->bt, L->b, sizeof(float) * L->nb, hipMemcpyDeviceToDevice, L->stream));
+    rc = refresh_transposes(L, true);
+    if (rc) return rc;
+  }
+  return SPARROW_OK;
+}
+
+int sparrow_learner_q(sparrow_learner* L, int32_t which, int32_t n, const float* x, float* q) {
+  if (!L || !x || !q || n < 1 || n > L->max_batch || (which != 0 && which != 1))
+    return fail(SPARROW_EINVAL, "bad argument");
+  // pass 1 computes the online net on its second input, pass 2 the target
+  int rc = learner_forward(L, n, x, x);
+  if (rc) return rc;
+  const size_t A = (size_t)L->dm.A;
+  HIP_TRY(hipMemcpyAsync(q, L->q + (size_t)(which ? 2 : 1) * n * A, sizeof(float) * n * A,
+                         hipMemcpyDeviceToDevice, L->stream));
+  return SPARROW_OK;
+}
+
+int sparrow_learner_export_bf16(sparrow_learner* L, uint16_t* w_bf16, float* b) {
+  if (!L || !w_bf16 || !b) return fail(SPARROW_EINVAL, "NULL argument");
+  hipLaunchKernelGGL(k_learn_bf16, dim3(blocks_for(L->nw, 256)), dim3(256), 0, L->stream, L->nw,
+                     L->w, w_bf16);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(b, L->b, sizeof(float) * L->nb, hipMemcpyDeviceToDevice, L->stream));
+  return SPARROW_OK;
+}
+
+int sparrow_learner_read(sparrow_learner* L, float* w, float* b, float* wt, float* bt, float* gw,
+                         float* gb) {
+  if (!L) return fail(SPARROW_EINVAL, "NULL argument");
+  HIP_TRY(hipStreamSynchronize(L->stream));
+  auto down = [&](float* dst, const float* src, int64_t n) {
+    return dst ? hipMemcpy(dst, src, sizeof(float) * n, hipMemcpyDeviceToHost) : hipSuccess;
+  };
+  HIP_TRY(down(w, L->w, L->nw));
+  HIP_TRY(down(b, L->b, L->nb));
+  HIP_TRY(down(wt, L->wt, L->nw));
+  HIP_TRY(down(bt, L->bt, L->nb));
+  HIP_TRY(down(gw, L->gw, L->nw));
+  HIP_TRY(down(gb, L->gb, L->nb));
+  return SPARROW_OK;
+}
+
+int64_t sparrow_learner_steps(const sparrow_learner* L) { return L ? L->steps : -1; }
+
+void sparrow_learner_destroy(sparrow_learner* L) {
+  if (!L) return;
+  if (L->stream) (void)hipStreamSynchronize(L->stream);
+  for (void* p : L->allocs) (void)hipFree(p);
+  delete L;
+}

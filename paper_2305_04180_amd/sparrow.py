@@ -31,6 +31,9 @@ EXPORTS = (
     "sparrow_set_vem_schedule",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
     "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
+    "sparrow_learner_create", "sparrow_learner_update", "sparrow_learner_q",
+    "sparrow_learner_export_bf16", "sparrow_learner_read", "sparrow_learner_steps",
+    "sparrow_learner_destroy",
 )
 
 
@@ -51,6 +54,12 @@ class Config(C.Structure):
         ("sigma_hi", C.c_float), ("delay_lo", C.c_int32), ("delay_hi", C.c_int32),
         ("seed", C.c_uint64),
     ]
+
+
+class LearnerConfig(C.Structure):
+    _fields_ = [("gamma", C.c_float), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float), ("huber_k", C.c_float),
+                ("target_every", C.c_int32), ("max_batch", C.c_int32)]
 
 
 class MapsStruct(C.Structure):
@@ -90,6 +99,13 @@ def lib(path: str = LIB_PATH):
             "sparrow_destroy": (None, [P]),
             "sparrow_last_error": (C.c_char_p, []),
             "sparrow_set_vem_schedule": (I32, [P, C.c_double, C.c_double, I32, I32, C.c_int64]),
+            "sparrow_learner_create": (I32, [P, P, P, C.POINTER(LearnerConfig), P, C.POINTER(P)]),
+            "sparrow_learner_update": (I32, [P, I32, P, P, P, P, P, P]),
+            "sparrow_learner_q": (I32, [P, I32, I32, P, P]),
+            "sparrow_learner_export_bf16": (I32, [P, P, P]),
+            "sparrow_learner_read": (I32, [P, P, P, P, P, P, P]),
+            "sparrow_learner_steps": (C.c_int64, [P]),
+            "sparrow_learner_destroy": (None, [P]),
             "sparrow_ring_create": (I32, [I32, I32, C.c_uint64, P, C.POINTER(P)]),
             "sparrow_ring_push": (I32, [P, I32, P, P, P, P, P, P]),
             "sparrow_ring_sample": (I32, [P, I32, U32, P, P, P, P, P, P]),
@@ -409,3 +425,79 @@ class Ring:
 
     def status(self) -> int:
         return lib().sparrow_ring_status(self._h)
+
+
+class Learner:
+    """The DDQN learner on the device (sparrow_learner_*): FP32 online and
+    target networks with Adam; one update per mini-batch."""
+
+    def __init__(self, dims, w_f32, b_f32, gamma=0.98, lr=1e-4, beta1=0.9, beta2=0.999,
+                 adam_eps=1e-8, huber_k=1.0, target_every=200, max_batch=256, stream=None):
+        import torch
+        self.torch = torch
+        self.dims = tuple(int(x) for x in dims)
+        d0, h1, h2, A = self.dims
+        self.nw = h1 * d0 + h2 * h1 + A * h2
+        self.nb = h1 + h2 + A
+        self.max_batch = int(max_batch)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        w = np.ascontiguousarray(w_f32, np.float32)
+        b = np.ascontiguousarray(b_f32, np.float32)
+        if w.size != self.nw or b.size != self.nb:
+            raise ValueError(f"expected {self.nw} weights and {self.nb} biases for dims {self.dims}")
+        self._cfg = LearnerConfig(gamma, lr, beta1, beta2, adam_eps, huber_k, target_every, max_batch)
+        d = (C.c_int32 * 4)(*self.dims)
+        h = C.c_void_p()
+        _check(lib().sparrow_learner_create(d, w.ctypes.data, b.ctypes.data, C.byref(self._cfg),
+                                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sparrow_learner_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, s, a, r, s_next, done):
+        t = self.torch
+        B = int(a.numel())
+        d0 = self.dims[0]
+        for x, dt, n, name in ((s, t.float32, B * d0, "s"), (a, t.int32, B, "a"),
+                               (r, t.float32, B, "r"), (s_next, t.float32, B * d0, "s_next"),
+                               (done, t.uint8, B, "done")):
+            _buf(x, dt, n, self.device, name)
+        _check(lib().sparrow_learner_update(self._h, B, _ptr(s), _ptr(a), _ptr(r), _ptr(s_next),
+                                            _ptr(done), _ptr(self.loss)))
+        return self.loss
+
+    def q(self, x, target=False):
+        t = self.torch
+        n = x.shape[0]
+        _buf(x, t.float32, n * self.dims[0], self.device, "x")
+        q = t.zeros(n, self.dims[3], dtype=t.float32, device=self.device)
+        _check(lib().sparrow_learner_q(self._h, int(bool(target)), n, _ptr(x), _ptr(q)))
+        return q
+
+    def export_bf16(self):
+        t = self.torch
+        w = t.zeros(self.nw, dtype=t.int16, device=self.device)
+        b = t.zeros(self.nb, dtype=t.float32, device=self.device)
+        _check(lib().sparrow_learner_export_bf16(self._h, _ptr(w), _ptr(b)))
+        return w, b
+
+    def read(self):
+        """Synchronising host copies: w, b, wt, bt, and the last gradients gw, gb."""
+        out = [np.zeros(n, np.float32) for n in (self.nw, self.nb, self.nw, self.nb, self.nw, self.nb)]
+        _check(lib().sparrow_learner_read(self._h, *[o.ctypes.data for o in out]))
+        return out
+
+    @property
+    def steps(self):
+        return int(lib().sparrow_learner_steps(self._h))

@@ -157,3 +157,21 @@ def test_ring_argument_errors_without_device(lib):
 
 def test_vem_schedule_null_handle(lib):
     assert lib.sparrow_set_vem_schedule(None, 0.01, 0.8, 16, 3, 500000) == sparrow.EINVAL
+
+
+def test_learner_argument_errors_without_device(lib):
+    Cfg = lib.sparrow_learner_create.argtypes[3]._type_  # the class the loaded library uses
+    cfg = Cfg(0.98, 1e-4, 0.9, 0.999, 1e-8, 1.0, 200, 256)
+    w = np.zeros(10, np.float32)
+    h = C.c_void_p()
+    for dims in ((0, 4, 4, 2), (129, 4, 4, 2), (4, 513, 4, 2), (4, 4, 4, 17)):
+        d = (C.c_int32 * 4)(*dims)
+        assert lib.sparrow_learner_create(d, w.ctypes.data, w.ctypes.data, C.byref(cfg), None,
+                                          C.byref(h)) == sparrow.EINVAL, dims
+    bad = Cfg(0.98, 1e-4, 0.9, 0.999, 1e-8, 1.0, 200, 0)
+    d = (C.c_int32 * 4)(4, 4, 4, 2)
+    assert lib.sparrow_learner_create(d, w.ctypes.data, w.ctypes.data, C.byref(bad), None,
+                                      C.byref(h)) == sparrow.EINVAL
+    assert lib.sparrow_learner_update(None, 1, None, None, None, None, None, None) == sparrow.EINVAL
+    assert lib.sparrow_learner_steps(None) == -1
+    lib.sparrow_learner_destroy(None)

@@ -1,0 +1,123 @@
+"""GPU parity of the learner update (Alg. 2 step 2, DDQN) against the binary64
+oracle: loss, every gradient and the weights after several Adam steps, the
+target network's copy period, the Q-network forward, and the bf16 export
+for the actor."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2305_04180_amd import inputs
+from tests.parity_util import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def transitions(rng, B, d0, A):
+    """Seeded transitions shaped like the observation (ranges in [0, 1],
+    scalars around zero)."""
+    s = rng.random((B, d0)).astype(np.float32)
+    s[:, -4:] = rng.normal(0, 0.6, (B, 4)).astype(np.float32)
+    sn = rng.random((B, d0)).astype(np.float32)
+    sn[:, -4:] = rng.normal(0, 0.6, (B, 4)).astype(np.float32)
+    a = rng.integers(0, A, B).astype(np.int32)
+    r = rng.normal(0, 3, B).astype(np.float32)
+    d = (rng.random(B) < 0.1).astype(np.uint8)
+    return s, a, r, sn, d
+
+
+def layers(v, dims):
+    d0, h1, h2, A = dims
+    return v[:h1 * d0], v[h1 * d0:h1 * d0 + h2 * h1], v[h1 * d0 + h2 * h1:]
+
+
+def test_learner_updates_match_oracle(torch_gpu):
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    dims = (36, 256, 256, 7)
+    banner(f"learner {dims}, B=256, 3 updates, target every 2")
+    _, b, w = inputs.qnet_weights(dims)
+    kw = dict(gamma=0.98, lr=1e-4, target_every=2)
+    gl = sparrow.Learner(dims, w, b, max_batch=256, **kw)
+    ol = oracle.Learner(dims, w, b, **kw)
+    rng = np.random.default_rng(12)
+    for step in range(3):
+        s, a, r, sn, d = transitions(rng, 256, dims[0], dims[3])
+        g = [torch.as_tensor(x).cuda() for x in (s, a, r, sn, d)]
+        loss_g = float(gl.update(*g).item())
+        loss_o, gw_o, gb_o = ol.update(s, a, r, sn, d)
+        w_g, b_g, wt_g, bt_g, gw_g, gb_g = gl.read()
+        where = f"update {step}"
+        assert abs(loss_g - loss_o) <= 1e-5 * max(1.0, abs(loss_o)), (where, loss_g, loss_o)
+        # gradients: FP32 sums over the mini-batch against binary64
+        for name, gg, go in zip(("W1", "W2", "W3"), layers(gw_g, dims), layers(gw_o, dims)):
+            scale = np.abs(go).max()
+            err = np.abs(gg.astype(np.float64) - go)
+            assert err.max() <= 1e-4 * scale + 1e-9, (where, name, err.max(), scale)
+        assert np.abs(gb_g - gb_o).max() <= 1e-4 * np.abs(gb_o).max() + 1e-9, where
+        # weights: Adam moves each by about lr per step, its sign that of the
+        # gradient history; where a gradient is too small for its sign to be
+        # settled by FP32 the step may go the other way (at most 2 lr)
+        w_o, b_o, wt_o, bt_o = ol.params()
+        dw = np.abs(w_g.astype(np.float64) - w_o)
+        assert dw.max() <= 2 * kw["lr"] * (step + 1) + 1e-6, (where, dw.max())
+        settled = np.abs(gw_o) > 1e-3 * np.abs(gw_o).max()
+        if step == 0:
+            assert np.all(dw[settled] <= 1e-3 * kw["lr"] + 1e-7), (where, dw[settled].max())
+        # target copy every second update
+        if (step + 1) % 2 == 0:
+            assert np.array_equal(wt_g, w_g) and np.array_equal(bt_g, b_g), where
+        else:
+            assert np.array_equal(wt_g, np.asarray(w, np.float32)) or step > 1, where
+    assert gl.steps == ol.steps == 3
+    # the forward pass of both networks
+    x = transitions(rng, 200, dims[0], dims[3])[0]
+    for target in (False, True):
+        qg = to_np(gl.q(torch.as_tensor(x).cuda(), target=target)).astype(np.float64)
+        qo = ol.q(x, target=target)
+        assert np.abs(qg - qo).max() <= 1e-5 * max(1.0, np.abs(qo).max()), target
+    # the online network as the actor's bf16 weights
+    wb, bb = gl.export_bf16()
+    torch.cuda.synchronize()
+    w_now = gl.read()[0]
+    assert np.array_equal(to_np(wb).view(np.uint16), inputs._to_bf16_bits(w_now))
+    assert np.array_equal(to_np(bb), gl.read()[1])
+
+
+def test_learner_feeds_the_actor_and_rejects_bad_batches(torch_gpu):
+    """Alg. 2 step 3 / Alg. 1 step 1: the learner's exported weights install
+    as the actor; oversize and empty mini-batches are errors."""
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=32)
+    dims = (36, 256, 256, 7)
+    banner("learner -> actor weights")
+    _, b, w = inputs.qnet_weights(dims)
+    gl = sparrow.Learner(dims, w, b, max_batch=64)
+    rng = np.random.default_rng(3)
+    s, a, r, sn, d = transitions(rng, 64, dims[0], dims[3])
+    g = [torch.as_tensor(x).cuda() for x in (s, a, r, sn, d)]
+    gl.update(*g)
+    env = sparrow.Env(cfg, inputs.make_maps(cfg))
+    wb, bb = gl.export_bf16()
+    env.set_qnet(dims, to_np(wb).view(np.uint16), to_np(bb), np.full(32, 0.05, np.float32))
+    env.reset()
+    acts = env.act(env.obs)
+    torch.cuda.synchronize()
+    assert to_np(acts).min() >= 0 and to_np(acts).max() < 7
+    big = transitions(rng, 65, dims[0], dims[3])
+    with pytest.raises(sparrow.SparrowError):
+        gl.update(*[torch.as_tensor(x).cuda() for x in big])
