@@ -136,6 +136,11 @@ def lib():
         L.orc_learner_steps.restype = C.c_int64
         L.orc_learner_steps.argtypes = [P]
         L.orc_learner_q.argtypes = [P, C.c_int32, C.c_int32, P, P]
+        L.orc_tfm_init.argtypes = [P, C.c_double]
+        L.orc_tfm_actor.argtypes = [P, C.c_double]
+        L.orc_tfm_learner.argtypes = [P, C.c_double]
+        L.orc_tfm_xi.restype = C.c_double
+        L.orc_tfm_xi.argtypes = [P]
         L.orc_f16_rne.restype = C.c_uint16
         L.orc_f16_rne.argtypes = [C.c_float]
         L.orc_f16_to_f32.restype = C.c_float
@@ -468,3 +473,34 @@ class Learner:
         q = np.zeros((x.shape[0], self.dims[3]), np.float64)
         lib().orc_learner_q(self._h, int(bool(target)), x.shape[0], _p(x), _p(q))
         return q
+
+
+class Tfm:
+    """Time feedback mechanism (Sec. 3.1.2, Eq. (TB2TV)); see learner_oracle.h."""
+
+    class _S(C.Structure):
+        _fields_ = [("rho", C.c_double), ("v_sum", C.c_double), ("b_sum", C.c_double),
+                    ("v_n", C.c_int64), ("b_n", C.c_int64)]
+
+    def __init__(self, rho):
+        self._s = Tfm._S()
+        lib().orc_tfm_init(C.byref(self._s), float(rho))
+
+    def actor(self, seconds):
+        lib().orc_tfm_actor(C.byref(self._s), float(seconds))
+
+    def learner(self, seconds):
+        lib().orc_tfm_learner(C.byref(self._s), float(seconds))
+
+    @property
+    def xi(self):
+        return float(lib().orc_tfm_xi(C.byref(self._s)))
+
+    @property
+    def actor_sleep(self):
+        return max(self.xi, 0.0)
+
+    @property
+    def learner_sleep(self):
+        x = self.xi
+        return -x / self._s.rho if x <= 0 else 0.0

@@ -183,3 +183,20 @@ int32_t orc_learner_update(orc_learner *L, int32_t B, const float *s, const int3
   free(q); free(qn); free(qt); free(d1); free(d2);
   return 0;
 }
+
+void orc_tfm_init(orc_tfm *t, double rho) {
+  memset(t, 0, sizeof(*t));
+  t->rho = rho;
+}
+void orc_tfm_actor(orc_tfm *t, double seconds) {
+  t->v_sum += seconds;
+  t->v_n += 1;
+}
+void orc_tfm_learner(orc_tfm *t, double seconds) {
+  t->b_sum += seconds;
+  t->b_n += 1;
+}
+double orc_tfm_xi(const orc_tfm *t) {
+  if (t->v_n == 0 || t->b_n == 0) return 0.0;
+  return t->rho * (t->b_sum / (double)t->b_n) - t->v_sum / (double)t->v_n;
+}

@@ -57,6 +57,21 @@ int64_t orc_learner_steps(const orc_learner *L);
 /* Forward pass of the online (which = 0) or target (1) network: q [n][A]. */
 void orc_learner_q(const orc_learner *L, int32_t which, int32_t n, const float *x, double *q);
 
+/* Time feedback mechanism (Sec. 3.1.2): the sharer keeps the mean period of
+ * one vectorized step of the actor (V, sleep excluded) and of one update of
+ * the learner (B); with rho = N TPS / B_batch, Eq. (TB2TV) asks V = rho B,
+ * so xi = rho mean(B) - mean(V): the actor sleeps xi after a step when
+ * xi > 0, the learner -xi / rho after an update otherwise. Means are over
+ * every period recorded so far; xi is 0 until both have one. */
+typedef struct {
+  double rho, v_sum, b_sum;
+  int64_t v_n, b_n;
+} orc_tfm;
+void orc_tfm_init(orc_tfm *t, double rho);
+void orc_tfm_actor(orc_tfm *t, double seconds);
+void orc_tfm_learner(orc_tfm *t, double seconds);
+double orc_tfm_xi(const orc_tfm *t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -153,3 +153,40 @@ def test_target_network_copied_every_period():
     assert L.steps == 7
     with pytest.raises(ValueError):
         L.update(*batch(rng, 0, dims[0], dims[3]))
+
+
+def simulate_asl(tfm, v_period, b_period, horizon):
+    """Actor and learner running side by side in virtual time, each sleeping
+    as the mechanism says after every step / update."""
+    t_a = t_l = 0.0
+    n_v = n_b = 0
+    while min(t_a, t_l) < horizon:
+        if t_a <= t_l:
+            t_a += v_period
+            tfm.actor(v_period)
+            n_v += 1
+            t_a += tfm.actor_sleep
+        else:
+            t_l += b_period
+            tfm.learner(b_period)
+            n_b += 1
+            t_l += tfm.learner_sleep
+    return n_v, n_b
+
+
+@pytest.mark.parametrize("v,b", [(1.0, 0.05), (0.2, 0.3), (0.01, 0.001), (0.5, 0.0625)])
+def test_tfm_holds_the_update_ratio_at_rho(v, b):
+    """Eq. (TB2TV): with V = rho B the learner makes rho updates per
+    vectorized step, so TPS = B_batch B_step / T_step stays at its target,
+    whichever side is faster."""
+    hp = json.load(open(os.path.join(HERE, "golden", "paper_constants.json")))["table6_sparrow_framework"]
+    rho = hp["N"] * hp["TPS"] / hp["minibatch"]  # 16 * 256 / 256 = 16
+    tfm = oracle.Tfm(rho)
+    assert tfm.xi == 0.0  # nothing recorded yet
+    n_v, n_b = simulate_asl(tfm, v, b, horizon=2000 * max(v, rho * b))
+    assert abs(n_b / n_v - rho) / rho < 0.02, (n_v, n_b)
+    # the slower side never sleeps
+    if v > rho * b:
+        assert tfm.actor_sleep == 0.0 and tfm.learner_sleep > 0.0
+    else:
+        assert tfm.actor_sleep > 0.0 and tfm.learner_sleep == 0.0
