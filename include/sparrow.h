@@ -299,6 +299,25 @@ int sparrow_learner_read(sparrow_learner *L, float *w, float *b, float *wt, floa
 int64_t sparrow_learner_steps(const sparrow_learner *L);
 void sparrow_learner_destroy(sparrow_learner *L);
 
+/* ---- Time feedback mechanism ------------------------------------------------
+ * Sec. 3.1.2: actor and learner run side by side; to hold the transitions per
+ * step TPS = B_batch B_step / T_step at its target, Eq. (TB2TV) asks that a
+ * vectorized step of the actor take rho = N TPS / B_batch times as long as
+ * an update of the learner. The actor reports the duration of each
+ * vectorized step (sleep excluded), the learner of each update; with their
+ * means so far, xi = rho mean(learner) - mean(actor): the actor sleeps xi
+ * after a step if xi > 0, else the learner sleeps -xi / rho after an update
+ * (xi = 0 until both have reported). Host-only and thread-safe: the two
+ * sides may report from different threads. Times in seconds. */
+typedef struct sparrow_tfm sparrow_tfm;
+int sparrow_tfm_create(double rho, sparrow_tfm **out); /* EINVAL unless rho > 0 */
+void sparrow_tfm_actor_period(sparrow_tfm *t, double seconds);
+void sparrow_tfm_learner_period(sparrow_tfm *t, double seconds);
+double sparrow_tfm_xi(const sparrow_tfm *t);
+double sparrow_tfm_actor_sleep(const sparrow_tfm *t);
+double sparrow_tfm_learner_sleep(const sparrow_tfm *t);
+void sparrow_tfm_destroy(sparrow_tfm *t);
+
 #ifdef __cplusplus
 }
 #endif

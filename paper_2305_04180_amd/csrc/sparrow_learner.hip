@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -436,3 +437,56 @@ void sparrow_learner_destroy(sparrow_learner* L) {
   for (void* p : L->allocs) (void)hipFree(p);
   delete L;
 }
+
+// ---------------------------------------------------------------------------
+// Time feedback mechanism (Sec. 3.1.2): host-side pacing of actor and learner.
+// ---------------------------------------------------------------------------
+struct sparrow_tfm {
+  double rho = 0.0, v_sum = 0.0, b_sum = 0.0;
+  int64_t v_n = 0, b_n = 0;
+  mutable std::mutex mu;  // the actor and the learner report from their own threads
+};
+
+int sparrow_tfm_create(double rho, sparrow_tfm** out) {
+  if (!out) return fail(SPARROW_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!(rho > 0.0)) return fail(SPARROW_EINVAL, "rho must be positive");
+  auto* t = new sparrow_tfm();
+  t->rho = rho;
+  *out = t;
+  return SPARROW_OK;
+}
+
+void sparrow_tfm_actor_period(sparrow_tfm* t, double seconds) {
+  if (!t) return;
+  std::lock_guard<std::mutex> g(t->mu);
+  t->v_sum += seconds;
+  t->v_n += 1;
+}
+
+void sparrow_tfm_learner_period(sparrow_tfm* t, double seconds) {
+  if (!t) return;
+  std::lock_guard<std::mutex> g(t->mu);
+  t->b_sum += seconds;
+  t->b_n += 1;
+}
+
+double sparrow_tfm_xi(const sparrow_tfm* t) {
+  if (!t) return 0.0;
+  std::lock_guard<std::mutex> g(t->mu);
+  if (t->v_n == 0 || t->b_n == 0) return 0.0;
+  return t->rho * (t->b_sum / (double)t->b_n) - t->v_sum / (double)t->v_n;
+}
+
+double sparrow_tfm_actor_sleep(const sparrow_tfm* t) {
+  const double xi = sparrow_tfm_xi(t);
+  return xi > 0.0 ? xi : 0.0;
+}
+
+double sparrow_tfm_learner_sleep(const sparrow_tfm* t) {
+  if (!t) return 0.0;
+  const double xi = sparrow_tfm_xi(t);
+  return xi <= 0.0 ? -xi / t->rho : 0.0;
+}
+
+void sparrow_tfm_destroy(sparrow_tfm* t) { delete t; }

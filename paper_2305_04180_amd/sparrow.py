@@ -34,6 +34,9 @@ EXPORTS = (
     "sparrow_learner_create", "sparrow_learner_update", "sparrow_learner_q",
     "sparrow_learner_export_bf16", "sparrow_learner_read", "sparrow_learner_steps",
     "sparrow_learner_destroy",
+    "sparrow_tfm_create", "sparrow_tfm_actor_period", "sparrow_tfm_learner_period",
+    "sparrow_tfm_xi", "sparrow_tfm_actor_sleep", "sparrow_tfm_learner_sleep",
+    "sparrow_tfm_destroy",
 )
 
 
@@ -106,6 +109,13 @@ def lib(path: str = LIB_PATH):
             "sparrow_learner_read": (I32, [P, P, P, P, P, P, P]),
             "sparrow_learner_steps": (C.c_int64, [P]),
             "sparrow_learner_destroy": (None, [P]),
+            "sparrow_tfm_create": (I32, [C.c_double, C.POINTER(P)]),
+            "sparrow_tfm_actor_period": (None, [P, C.c_double]),
+            "sparrow_tfm_learner_period": (None, [P, C.c_double]),
+            "sparrow_tfm_xi": (C.c_double, [P]),
+            "sparrow_tfm_actor_sleep": (C.c_double, [P]),
+            "sparrow_tfm_learner_sleep": (C.c_double, [P]),
+            "sparrow_tfm_destroy": (None, [P]),
             "sparrow_ring_create": (I32, [I32, I32, C.c_uint64, P, C.POINTER(P)]),
             "sparrow_ring_push": (I32, [P, I32, P, P, P, P, P, P]),
             "sparrow_ring_sample": (I32, [P, I32, U32, P, P, P, P, P, P]),
@@ -501,3 +511,37 @@ class Learner:
     @property
     def steps(self):
         return int(lib().sparrow_learner_steps(self._h))
+
+
+class Tfm:
+    """Time feedback mechanism (sparrow_tfm_*): the actor reports each
+    vectorized step's duration, the learner each update's; the faster side
+    sleeps as told (Sec. 3.1.2, Eq. (TB2TV))."""
+
+    def __init__(self, rho):
+        h = C.c_void_p()
+        _check(lib().sparrow_tfm_create(float(rho), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().sparrow_tfm_destroy(self._h)
+            self._h = None
+
+    def actor(self, seconds):
+        lib().sparrow_tfm_actor_period(self._h, float(seconds))
+
+    def learner(self, seconds):
+        lib().sparrow_tfm_learner_period(self._h, float(seconds))
+
+    @property
+    def xi(self):
+        return float(lib().sparrow_tfm_xi(self._h))
+
+    @property
+    def actor_sleep(self):
+        return float(lib().sparrow_tfm_actor_sleep(self._h))
+
+    @property
+    def learner_sleep(self):
+        return float(lib().sparrow_tfm_learner_sleep(self._h))

@@ -175,3 +175,23 @@ def test_learner_argument_errors_without_device(lib):
     assert lib.sparrow_learner_update(None, 1, None, None, None, None, None, None) == sparrow.EINVAL
     assert lib.sparrow_learner_steps(None) == -1
     lib.sparrow_learner_destroy(None)
+
+
+def test_tfm_matches_the_oracle(lib):
+    """The pacing rule is host code: the library's and the oracle's sleep
+    decisions agree exactly on a random record of periods."""
+    import oracle
+    with pytest.raises(sparrow.SparrowError):
+        sparrow.Tfm(0.0)
+    rng = np.random.default_rng(5)
+    lt, ot = sparrow.Tfm(16.0), oracle.Tfm(16.0)
+    assert lt.xi == ot.xi == 0.0
+    for _ in range(500):
+        if rng.random() < 0.3:
+            v = float(rng.exponential(0.01))
+            lt.actor(v), ot.actor(v)
+        else:
+            bb = float(rng.exponential(0.001))
+            lt.learner(bb), ot.learner(bb)
+        assert lt.xi == ot.xi
+        assert lt.actor_sleep == ot.actor_sleep and lt.learner_sleep == ot.learner_sleep
