@@ -76,6 +76,8 @@ def parse():
                     help="skip the full-collection leg (32768 envs, ring buffer)")
     ap.add_argument("--c5-steps", type=int, default=2048)
     ap.add_argument("--c5-warmup", type=int, default=64)
+    ap.add_argument("--no-asl", action="store_true",
+                    help="skip the actor/learner leg paced by the time feedback mechanism")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -251,6 +253,109 @@ def collection_c5(cfg, maps, steps, warmup):
         "add_hbm": {"alg_bytes": int(add_bytes),
                     "achieved_gbs": round(add_bytes / (phase["add"] / 1e3) / 1e9, 1)},
     }
+
+
+def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
+    """Actor and learner side by side (Sec. 3.1.2, Alg. 1 and Alg. 2) on one
+    GPU, paced by the time feedback mechanism: the actor thread steps the
+    envs (actor kernel + step + add to the ring) on its stream, the learner
+    thread samples a mini-batch and runs the DDQN update on its own; each
+    reports its period and sleeps as told. Reports the TPS achieved against
+    its target."""
+    import threading
+    import torch
+    from paper_2305_04180_amd import inputs, sparrow
+    cfg = inputs.workload("c2", n_envs=n_envs)
+    maps = inputs.make_maps(cfg)
+    N, D = n_envs, cfg["n_rays"] + 4
+    dims = (D, 256, 256, 7)
+    wb, b, w32 = inputs.qnet_weights(dims)
+    s_act = torch.cuda.Stream()
+    s_learn = torch.cuda.Stream()
+    with torch.cuda.stream(s_act):
+        env = sparrow.Env(cfg, maps, stream=s_act)
+        env.set_qnet(dims, wb, b, sparrow.vem_epsilon(N, N, 0.01, 0.8))
+        ring = sparrow.Ring(1 << 20, cfg["n_rays"], seed=3, stream=s_act)
+        cur = env.reset()
+        nxt, fo = torch.zeros_like(cur), torch.zeros_like(cur)
+        act = torch.zeros(N, dtype=torch.int32, device="cuda")
+        rew = torch.zeros(N, dtype=torch.float32, device="cuda")
+        done = torch.zeros(N, dtype=torch.uint8, device="cuda")
+        sb = [torch.zeros(batch, D, device="cuda"), torch.zeros(batch, dtype=torch.int32, device="cuda"),
+              torch.zeros(batch, device="cuda"), torch.zeros(batch, D, device="cuda"),
+              torch.zeros(batch, dtype=torch.uint8, device="cuda")]
+        sidx = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    learner = sparrow.Learner(dims, w32, b, max_batch=batch, stream=s_learn)
+    rho = N * tps / batch
+    tfm = sparrow.Tfm(rho)
+    lock = threading.Lock()  # the sharer's occupancy flag (Sec. 3.1.2)
+    stop = threading.Event()
+    counts = {"v": 0, "b": 0, "v_time": 0.0, "b_time": 0.0}
+    state = {"cur": cur, "nxt": nxt}
+
+    def actor():
+        while not stop.is_set():
+            t0 = time.perf_counter()
+            with torch.cuda.stream(s_act):
+                env.act(state["cur"], act)
+                env.step(act, obs=state["nxt"], reward=rew, done=done, final_obs=fo)
+                with lock:
+                    ring.push(state["cur"], act, rew, state["nxt"], done, fo)
+            s_act.synchronize()
+            state["cur"], state["nxt"] = state["nxt"], state["cur"]
+            dt = time.perf_counter() - t0
+            tfm.actor(dt)
+            counts["v"] += 1
+            counts["v_time"] += dt
+            z = tfm.actor_sleep
+            if z > 0:
+                time.sleep(z)
+
+    def learn():
+        while not stop.is_set():
+            if ring.size < learn_start:
+                time.sleep(0.001)
+                continue
+            t0 = time.perf_counter()
+            with lock:
+                with torch.cuda.stream(s_act):  # ordered after the adds
+                    ring.sample(batch, counts["b"], outs=sb, idx=sidx)
+                    ev = torch.cuda.Event()
+                    ev.record(s_act)
+            s_learn.wait_event(ev)
+            with torch.cuda.stream(s_learn):
+                learner.update(*sb)
+            s_learn.synchronize()
+            dt = time.perf_counter() - t0
+            tfm.learner(dt)
+            counts["b"] += 1
+            counts["b_time"] += dt
+            z = tfm.learner_sleep
+            if z > 0:
+                time.sleep(z)
+
+    ta, tl = threading.Thread(target=actor), threading.Thread(target=learn)
+    ta.start()
+    tl.start()
+    # measure once the learner has started
+    while ring.size < learn_start:
+        time.sleep(0.01)
+    time.sleep(0.5)
+    v0, b0, t0 = counts["v"], counts["b"], time.perf_counter()
+    time.sleep(seconds)
+    v1, b1, t1 = counts["v"], counts["b"], time.perf_counter()
+    stop.set()
+    ta.join()
+    tl.join()
+    assert env.status() == 0 and ring.status() == 0
+    dv, db = v1 - v0, b1 - b0
+    return {"n_envs": N, "target_tps": tps, "minibatch": batch, "rho": rho,
+            "achieved_tps": round(batch * db / max(N * dv, 1), 3),
+            "vectorized_steps_per_s": round(dv / (t1 - t0), 1),
+            "updates_per_s": round(db / (t1 - t0), 1),
+            "mean_actor_period_ms": round(1e3 * counts["v_time"] / max(counts["v"], 1), 4),
+            "mean_learner_period_ms": round(1e3 * counts["b_time"] / max(counts["b"], 1), 4),
+            "window_s": round(t1 - t0, 2)}
 
 
 def kernel_source_hash():
@@ -498,6 +603,12 @@ def main():
         c5 = collection_c5(cfg5, maps5, args.c5_steps, args.c5_warmup)
         log(f"[bench] c5: {c5['value'] / 1e6:.1f} M env-steps/s, phases {c5['phase_ms_per_step']}")
 
+    asl = None
+    if not args.no_asl:
+        log("[bench] actor + learner paced by the time feedback mechanism")
+        asl = asl_tfm()
+        log(f"[bench] asl: {asl}")
+
     out = {
         "metric": "env-steps/s at N=4096, 366^2 maps, 32 rays; fused BF16 vs plain; % HBM/LDS peak",
         "value": round(fused_rate, 1),
@@ -527,6 +638,7 @@ def main():
         "cpu_baseline": cpu,
         "precision": precision,
         "collection_c5": c5,
+        "asl_tfm": asl,
     }
     print(json.dumps(out), flush=True)
 
