@@ -255,6 +255,21 @@ int64_t sparrow_ring_head(const sparrow_ring *ring);
 int sparrow_ring_status(sparrow_ring *ring);
 void sparrow_ring_destroy(sparrow_ring *ring);
 
+/* sparrow_rollout that also performs Alg. 1 step 5 inside the same kernel:
+ * step t's N transitions (s, a_hat, r, s', done) go straight into the ring,
+ * transition (t, i) at slot (head + t N + i) mod capacity, stored exactly as
+ * sparrow_ring_push stores them. s is the observation the actor saw (for
+ * t = 0 the current observation), a_hat the actor's action (before the
+ * control delay), s' the observation after the step or, for a done env, its
+ * terminal observation before the reset (the one sparrow_step returns as
+ * final_obs). Afterwards head and size advance by K N. Requirements: the
+ * ring's n_rays equals the env's and K N <= capacity (EINVAL otherwise).
+ * actions, reward, done (dev [K][N]) are nullable here; obs as in
+ * sparrow_rollout. The kernel runs on the env's stream: when the ring is
+ * bound to another stream, the caller orders the two (events). */
+int sparrow_rollout_collect(sparrow_env *env, sparrow_ring *ring, int32_t K, int32_t use_qnet,
+                            int32_t *actions, float *reward, uint8_t *done, float *obs);
+
 /* ---- Learner ---------------------------------------------------------------
  * The learner's update of Alg. 2 step 2 (train the learner's model on a
  * mini-batch with DDQN; Table 6: gamma 0.98, learning rate 1e-4, target

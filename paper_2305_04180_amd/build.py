@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "libsparrow.so")
 SOURCES = [os.path.join(CSRC, "sparrow.hip"), os.path.join(CSRC, "sparrow_ring.hip"),
            os.path.join(CSRC, "sparrow_learner.hip")]
 HEADERS = [os.path.join(CSRC, "sparrow_device.h"), os.path.join(CSRC, "sparrow_qnet.h"),
+           os.path.join(CSRC, "sparrow_mlp.h"), os.path.join(CSRC, "sparrow_ring_dev.h"),
            os.path.join(CSRC, "sparrow_host.h"),
            os.path.join(ROOT, "include", "sparrow.h")]
 ARCH = "gfx950"

@@ -4,10 +4,11 @@
 //   k_pack      uint8 grids -> bit-packed rows with an occupied ring (LDS-ready)
 //   k_step<L>   one vectorized step (or reset) per launch; each workgroup
 //               stages its group's maps into LDS, then every env runs on L lanes
-//   k_rollout<L, QNET>
+//   k_rollout<L, QNET, COLL>
 //               persistent K-step rollout: maps staged once per group and kept
 //               in LDS for all K steps; actor = uniform draws or the BF16 MFMA
-//               Q-network + VEM (Alg. 1 steps 2-4 fused)
+//               Q-network + VEM (Alg. 1 steps 2-4 fused); COLL also adds each
+//               step's transitions to the experience buffer (step 5)
 //   k_actions   uniform random actions (one thread per env)
 #include <hip/hip_runtime.h>
 
@@ -25,6 +26,7 @@
 #include "sparrow_host.h"
 #include "sparrow_mlp.h"
 #include "sparrow_qnet.h"
+#include "sparrow_ring_dev.h"
 
 using namespace sp;
 
@@ -100,6 +102,13 @@ __device__ __forceinline__ Slot make_slot(const Params& p, const int4& sl, const
   return m;
 }
 
+// Slot of transition (t, i) of a collecting rollout; head < capacity and
+// t N + i < K N <= capacity, so one subtraction wraps it.
+__device__ __forceinline__ int32_t ring_slot(const Params& p, int t, int i) {
+  const int32_t s = p.ring_head + t * p.n_envs + i;
+  return s >= p.ring.cap ? s - p.ring.cap : s;
+}
+
 // mode 0: step, mode 1: reset
 template <int L>
 __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
@@ -149,7 +158,12 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
 
 // Persistent rollout: workgroup b serves groups b, b + gridDim.x, ...
 // QC = NoQ: uniform random actions; QC = QNetCfg<...>: fused BF16 actor.
-template <int L, class QC>
+// COLL: every step also adds its N transitions (s, a_hat, r, s', done) to the
+// experience buffer (Alg. 1 step 5), transition (t, i) at slot
+// (ring_head + t N + i) mod capacity. s' of a done env is its terminal
+// observation (taken before the reset, with the step's own noise draws); the
+// observation after the step, reset or not, is also the next transition's s.
+template <int L, class QC, bool COLL>
 __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
   extern __shared__ uint32_t lds[];
   constexpr bool kQ = QC::kOn;
@@ -194,6 +208,19 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if (live)
         for (int k = ln.q; k < D; k += L) act_in[k] = bf16_rne(p.cur_obs[(size_t)i * D + k]);
     }
+    if constexpr (COLL) {
+      // s of the first transition: the current observation
+      if (live) {
+        const int32_t s0 = ring_slot(p, 0, i);
+        const float* co = p.cur_obs + (size_t)i * D;
+        for (int k = ln.q; k < D; k += L) {
+          if (k < p.n_rays)
+            p.ring.rs[(size_t)s0 * p.n_rays + k] = quant_u8(co[k]);
+          else
+            p.ring.cs[(size_t)s0 * kRingScalars + (k - p.n_rays)] = f16_bits(co[k]);
+        }
+      }
+    }
     __syncthreads();
     for (int t = 0; t < p.K_steps; ++t) {
       const uint32_t g = p.g + (uint32_t)t;
@@ -225,16 +252,45 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
         float* crow = (last || !kQ) ? p.cur_obs + (size_t)i * D : nullptr;
         int16_t* hk = last ? p.hit_k + (size_t)i * p.n_rays : nullptr;
         bool free_pose = true;  // not done: the step's collision test passed
-        if (o.done) {
-          free_pose = reset_env<L>(p, ln, m, e, i, g);
-          if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
+        if constexpr (COLL) {
+          const int32_t s0 = ring_slot(p, t, i);
+          const RingRow next_s =
+              last ? RingRow{nullptr, nullptr} : ring_row(p.ring.rs, p.ring.cs, p.n_rays, ring_slot(p, t + 1, i));
+          const RingRow this_sn = ring_row(p.ring.rsn, p.ring.csn, p.n_rays, s0);
+          // pass 0 (done envs only): the terminal observation as s'; pass 1:
+          // AutoReset, then the observation that continues the rollout
+#pragma unroll 1
+          for (int pass = 0; pass < 2; ++pass) {
+            const bool terminal = pass == 0;
+            if (terminal && !o.done) continue;
+            if (!terminal && o.done) {
+              free_pose = reset_env<L>(p, ln, m, e, i, g);
+              if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
+            }
+            observe<L>(p, ln, rd, m, e, i, g, (terminal || !o.done) ? kNoise : kNoiseReset, inv_dn,
+                       terminal ? nullptr : orow, terminal ? nullptr : crow,
+                       terminal ? nullptr : hk, terminal ? nullptr : act_in,
+                       !terminal && free_pose,
+                       (terminal || !o.done) ? this_sn : RingRow{nullptr, nullptr},
+                       terminal ? RingRow{nullptr, nullptr} : next_s);
+          }
+          if (ln.q == 0) {
+            p.ring.act[s0] = (int8_t)a_hat;
+            p.ring.rew[s0] = o.reward;
+            ring_set_done(p.ring, s0, o.done != 0);
+          }
+        } else {
+          if (o.done) {
+            free_pose = reset_env<L>(p, ln, m, e, i, g);
+            if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
+          }
+          observe<L>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
+                     act_in, free_pose);
         }
-        observe<L>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
-                   act_in, free_pose);
         if (ln.q == 0) {
           const size_t o_idx = (size_t)t * N + i;
-          p.r_reward[o_idx] = o.reward;
-          p.r_done[o_idx] = o.done;
+          if (p.r_reward) p.r_reward[o_idx] = o.reward;
+          if (p.r_done) p.r_done[o_idx] = o.done;
           if (p.r_actions) p.r_actions[o_idx] = a_hat;
         }
       }
@@ -348,7 +404,7 @@ struct sparrow_env {
   int var_epw[2] = {1, 8};
   int var_L[2] = {64, 64};
   std::map<std::pair<int, int>, Groups> groups;  // (epw, budget words)
-  std::map<std::tuple<int, int, int, int, void*, void*, void*, void*>, GraphEntry> graphs;
+  std::map<std::tuple<int, int, int, int>, GraphEntry> graphs;
   // actor
   bool has_qnet = false;
   VemSchedule vem{};  // off until sparrow_set_vem_schedule
@@ -499,19 +555,24 @@ int qnet_kind(const QParams& q) {
 }
 bool qnet_in_registers(int kind) { return kind == 1 || kind == 2; }
 
-template <int L>
+template <int L, bool COLL>
 const void* rollout_fn_L(int kind) {
-  if (kind == 1) return (const void*)k_rollout<L, Q64>;
-  if (kind == 2) return (const void*)k_rollout<L, Q96>;
-  return (const void*)k_rollout<L, NoQ>;
+  if (kind == 1) return (const void*)k_rollout<L, Q64, COLL>;
+  if (kind == 2) return (const void*)k_rollout<L, Q96, COLL>;
+  return (const void*)k_rollout<L, NoQ, COLL>;
 }
 
-const void* rollout_kernel(int L, int kind) {
+template <bool COLL>
+const void* rollout_kernel_c(int L, int kind) {
   switch (L) {
-    case 16: return rollout_fn_L<16>(kind);
-    case 32: return rollout_fn_L<32>(kind);
-    default: return rollout_fn_L<64>(kind);
+    case 16: return rollout_fn_L<16, COLL>(kind);
+    case 32: return rollout_fn_L<32, COLL>(kind);
+    default: return rollout_fn_L<64, COLL>(kind);
   }
+}
+
+const void* rollout_kernel(int L, int kind, bool collect) {
+  return collect ? rollout_kernel_c<true>(L, kind) : rollout_kernel_c<false>(L, kind);
 }
 
 const void* qnet_kernel(int kind) {
@@ -845,7 +906,8 @@ int sparrow_act(sparrow_env* e, const float* obs, int32_t* actions) {
 }
 
 static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int32_t* actions,
-                          float* reward, uint8_t* done, float* obs, bool use_graph) {
+                          float* reward, uint8_t* done, float* obs, bool use_graph,
+                          const RingDev* ring = nullptr, int32_t ring_head = 0) {
   const int reserve = q ? (int)qnet_lds_bytes(e->qp) : 0;
   const int budget_words = (e->lds_max - reserve) / 4;
   Groups* gr = nullptr;
@@ -853,7 +915,7 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   if (rc) return rc;
   const int threads = q ? kQThreads : std::max(64, epw * L);
   const size_t shmem = (size_t)reserve + (size_t)gr->max_words * 4;
-  const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0);
+  const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0, ring != nullptr);
   HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   int per_cu = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem));
@@ -869,6 +931,10 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   p.r_actions = actions;
   p.r_reward = reward;
   p.r_done = done;
+  if (ring) {
+    p.ring = *ring;
+    p.ring_head = ring_head;
+  }
   QParams qp = e->qp;
   qp.lds_base_words = gr->max_words;
   void* args[] = {&p, &qp};
@@ -877,8 +943,9 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
     e->g += (uint32_t)K;
     return SPARROW_OK;
   }
-  auto key = std::make_tuple((int)K, (int)q, L, epw, (void*)actions, (void*)reward, (void*)done,
-                             (void*)obs);
+  // the kernel's arguments are set on every launch; the key names the kernel
+  // and its launch shape
+  auto key = std::make_tuple((int)K, (int)q | (ring ? 2 : 0), L, epw);
   auto it = e->graphs.find(key);
   if (it == e->graphs.end()) {
     GraphEntry ge;
@@ -915,6 +982,29 @@ int sparrow_rollout(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* action
   if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
   return launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done,
                         obs, true);
+}
+
+int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32_t use_qnet,
+                            int32_t* actions, float* reward, uint8_t* done, float* obs) {
+  if (!e || !ring || !obs || K < 1) return fail(SPARROW_EINVAL, "bad argument");
+  if (use_qnet && !e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
+  if (use_qnet && !qnet_in_registers(qnet_kind(e->qp)))
+    return fail(SPARROW_EUNSUPPORTED,
+                "the fused rollout needs a width-256 actor; use sparrow_act with width 512");
+  if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
+  RingDev rd{};
+  int64_t head = 0;
+  int rc = ring_view(ring, &rd, &head);
+  if (rc) return rc;
+  if (rd.nr != e->cfg.n_rays)
+    return fail(SPARROW_EINVAL, "the buffer's ray count differs from the environment's");
+  if ((int64_t)K * e->cfg.n_envs > (int64_t)rd.cap)
+    return fail(SPARROW_EINVAL, "K * n_envs transitions exceed the buffer's capacity");
+  rc = launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done, obs,
+                      true, &rd, (int32_t)head);
+  if (rc) return rc;
+  ring_advance(ring, (int64_t)K * e->cfg.n_envs);
+  return SPARROW_OK;
 }
 
 int sparrow_debug_hits(sparrow_env* e, int16_t* hit_k) {

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sparrow_ring_dev.h"
+
 namespace sp {
 
 constexpr int kStop = 7;
@@ -163,7 +165,20 @@ struct Params {
   uint8_t* r_done;
   // actor
   const float* eps;         // [N]
+  // collecting rollout: the experience buffer and the slot of its next add
+  RingDev ring;
+  int32_t ring_head;
 };
+
+// Destination of one observation in the experience buffer (both NULL: none).
+struct RingRow {
+  uint8_t* r;   // [n_rays] range levels
+  uint16_t* c;  // [4] binary16 scalars
+};
+
+__device__ __forceinline__ RingRow ring_row(uint8_t* r, uint16_t* c, int nr, int32_t slot) {
+  return RingRow{r + (size_t)slot * nr, c + (size_t)slot * kRingScalars};
+}
 
 // ------------------------------------------------------------------------
 // Per-env register state (every lane of the env holds a copy).
@@ -402,7 +417,8 @@ template <int L>
 __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, const RayDirs<L>& rd, const Slot& m,
                         Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
                         float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
-                        bool disk_free) {
+                        bool disk_free, RingRow qa = RingRow{nullptr, nullptr},
+                        RingRow qb = RingRow{nullptr, nullptr}) {
   // With the robot disk known to be collision-free, every sample closer to
   // the centre than the radius lies in a cell a collision test would have
   // flagged, so none of the first k_free samples can hit.
@@ -460,6 +476,8 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       if (dst2) dst2[j] = o;
       if (dst_bf16) dst_bf16[j] = bf16_rne(o);
       if (hk) hk[j] = (int16_t)kh;
+      if (qa.r) qa.r[j] = quant_u8(o);
+      if (qb.r) qb.r[j] = quant_u8(o);
     }
   }
   if (ln.q == 0) {
@@ -477,6 +495,13 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       if (dst) dst[nr + a] = o[a];
       if (dst2) dst2[nr + a] = o[a];
       if (dst_bf16) dst_bf16[nr + a] = bf16_rne(o[a]);
+    }
+    if (qa.c || qb.c) {
+      // the four binary16 codes as one 8-byte store (rows are 8-byte aligned)
+      const uint2 h = make_uint2((uint32_t)f16_bits(o[0]) | ((uint32_t)f16_bits(o[1]) << 16),
+                                 (uint32_t)f16_bits(o[2]) | ((uint32_t)f16_bits(o[3]) << 16));
+      if (qa.c) *reinterpret_cast<uint2*>(qa.c) = h;
+      if (qb.c) *reinterpret_cast<uint2*>(qb.c) = h;
     }
   }
 }

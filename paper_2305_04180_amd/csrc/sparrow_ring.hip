@@ -2,10 +2,7 @@
 // step 5 adds each batch of transitions, Alg. 2 step 1 samples a mini-batch;
 // Table 6 sizes it at 1 M transitions and the mini-batch at 256).
 //
-// Storage, structure of arrays over the slots (every array indexed by slot):
-//   rs, rsn   uint8 [cap][n_rays]  range levels of s and s'
-//   cs, csn   uint16 [cap][4]      binary16 scalars of s and s'
-//   act       int8 [cap], rew float [cap], done one bit per slot (uint32 words)
+// Storage: sparrow_ring_dev.h (structure of arrays over the slots).
 // A push writes a contiguous run of slots (one wrap at most); a wave per
 // transition reads its FP32 rows coalesced and writes the encoded rows next
 // to each other.
@@ -23,40 +20,15 @@
 #include "../../include/sparrow.h"
 #include "sparrow_device.h"
 #include "sparrow_host.h"
+#include "sparrow_ring_dev.h"
 
 using namespace sp;
 
 namespace {
 
 constexpr uint32_t kRingSample = 8;  // Philox counter word 2 of the sampler
-constexpr int kScalars = 4;
+constexpr int kScalars = kRingScalars;
 constexpr int kRingThreads = 256;
-
-struct RingDev {
-  uint8_t* rs;
-  uint8_t* rsn;
-  uint16_t* cs;
-  uint16_t* csn;
-  int8_t* act;
-  float* rew;
-  uint32_t* done;
-  int32_t cap, nr;
-};
-
-// nearest level of 255 * clamp(o, 0, 1): the product rounds to binary32,
-// v_rndne_f32 rounds it to the nearest integer, ties to even; NaN -> 0
-__device__ __forceinline__ uint8_t quant_u8(float o) {
-  const float c = fminf(fmaxf(o, 0.0f), 1.0f);
-  return (uint8_t)__builtin_rintf(c * 255.0f);
-}
-__device__ __forceinline__ float dequant_u8(uint8_t q) { return (float)q / 255.0f; }
-// binary32 -> binary16 with v_cvt_f16_f32 (round to nearest even)
-__device__ __forceinline__ uint16_t f16_bits(float f) {
-  return __builtin_bit_cast(uint16_t, (_Float16)f);
-}
-__device__ __forceinline__ float f16_value(uint16_t h) {
-  return (float)__builtin_bit_cast(_Float16, h);
-}
 
 // One wave per transition: lanes take the row's entries, so the FP32 rows
 // are read and the encoded rows written contiguously with no division.
@@ -288,4 +260,17 @@ void sparrow_ring_destroy(sparrow_ring* R) {
   if (R->d_slots) (void)hipFree(R->d_slots);
   if (R->block) (void)hipFree(R->block);
   delete R;
+}
+
+int sp::ring_view(const sparrow_ring* R, RingDev* view, int64_t* head) {
+  if (!R || !view || !head) return fail(SPARROW_EINVAL, "NULL argument");
+  *view = R->dev;
+  *head = R->head;
+  return SPARROW_OK;
+}
+
+void sp::ring_advance(sparrow_ring* R, int64_t n) {
+  if (!R || n <= 0) return;
+  R->head = (R->head + n) % R->dev.cap;
+  R->size = std::min<int64_t>(R->size + n, R->dev.cap);
 }

@@ -28,7 +28,7 @@ EXPORTS = (
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
-    "sparrow_set_vem_schedule",
+    "sparrow_set_vem_schedule", "sparrow_rollout_collect",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
     "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
     "sparrow_learner_create", "sparrow_learner_update", "sparrow_learner_q",
@@ -90,6 +90,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_qnet_forward": (I32, [P, P, I32, P, P]),
             "sparrow_act": (I32, [P, P, P]),
             "sparrow_rollout": (I32, [P, I32, I32, P, P, P, P]),
+            "sparrow_rollout_collect": (I32, [P, P, I32, I32, P, P, P, P]),
             "sparrow_debug_hits": (I32, [P, P]),
             "sparrow_get_state": (I32, [P, P, P]),
             "sparrow_set_state": (I32, [P, P, P]),
@@ -295,6 +296,21 @@ class Env:
         self._b(obs, torch.float32, n * self.obs_dim, "obs")
         _check(lib().sparrow_rollout(self._h, K, int(bool(use_qnet)), _ptr(actions),
                                      _ptr(reward), _ptr(done), _ptr(obs)))
+        return actions, reward, done, obs
+
+    def rollout_collect(self, ring, K, use_qnet, actions=None, reward=None, done=None, obs=None):
+        """K fused steps that also add their K * N transitions to `ring`
+        (Alg. 1 steps 2-5 in one kernel); the step-major actions, rewards and
+        done flags are optional outputs here."""
+        torch = self.torch
+        n = self.n
+        obs = self.obs if obs is None else obs
+        self._b(actions, torch.int32, K * n, "actions", nullable=True)
+        self._b(reward, torch.float32, K * n, "reward", nullable=True)
+        self._b(done, torch.uint8, K * n, "done", nullable=True)
+        self._b(obs, torch.float32, n * self.obs_dim, "obs")
+        _check(lib().sparrow_rollout_collect(self._h, ring._h, K, int(bool(use_qnet)),
+                                             _ptr(actions), _ptr(reward), _ptr(done), _ptr(obs)))
         return actions, reward, done, obs
 
     # -- inspection -----------------------------------------------------------

@@ -308,3 +308,161 @@ def test_collection_loop_small(torch_gpu):
     of, oi = orc.get_state()
     compare_state(gf[live], gi[live], of[live], oi[live], "collection loop final")
     assert env.status() == 0 and ring.status() == 0
+
+
+def _oracle_collect(orc, oring, o_obs, K, actions_fn, raw):
+    """The oracle's side of a collecting rollout from observation o_obs: K
+    steps, each adding its N transitions (s' = the terminal observation
+    where done) to the oracle's ring; raw collects (s, s') per step for the
+    tie-aware comparison. Returns the per-step (a, r, done) and the last
+    observation."""
+    rows = []
+    for t in range(K):
+        a = actions_fn(t, o_obs)
+        r = orc.step(a, final_obs=True)
+        sn = np.where(r["done"][:, None].astype(bool), r["final_obs"], r["obs"])
+        oring.push(o_obs, a, r["reward"], r["obs"], r["done"], r["final_obs"])
+        raw.append((o_obs.copy(), sn.copy()))
+        rows.append((a, r["reward"], r["done"]))
+        o_obs = r["obs"]
+    return rows, o_obs
+
+
+def _compare_ring_slots(ring, oring, slots, raw_s, raw_sn, nr, where, mask=None):
+    g = ring.gather(slots)
+    o = oring.gather(slots)
+    g = [to_np(x) for x in g]
+    keep = np.ones(len(slots), bool) if mask is None else mask
+    _compare_stored_obs(g[0][keep], o[0][keep], raw_s[keep], nr, f"{where} s")
+    _compare_stored_obs(g[3][keep], o[3][keep], raw_sn[keep], nr, f"{where} s'")
+    compare_exact(g[1][keep], o[1][keep], "a", where)
+    compare_exact(g[2][keep], o[2][keep], "r", where)
+    compare_exact(g[4][keep], o[4][keep], "done", where)
+
+
+@pytest.mark.parametrize("wl,variant", [("c1", (8, 64)), ("c2", (8, 64)), ("c2", (4, 32)),
+                                        ("c2", (2, 16))])
+def test_rollout_collect_uniform_matches_oracle_ring(torch_gpu, wl, variant):
+    """Alg. 1 steps 2-5 in one kernel: two collecting rollouts (K = 24, then
+    K = 12, so the second wraps a 1500-slot ring) with uniform actions; every
+    stored slot against the oracle's ring filled by its own step-and-add
+    loop, the step-major outputs and the final state against the oracle."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload(wl, n_envs=45)
+    N, nr = 45, cfg["n_rays"]
+    banner(f"collecting rollout {wl} N={N} variant={variant}, K=24 then 12, ring 1500")
+    maps = inputs.make_maps(cfg)
+    env = sparrow.Env(cfg, maps)
+    orc = oracle.Oracle(cfg, maps)
+    env.set_variant(1, *variant)
+    env.reset()
+    o_obs, _ = orc.reset()
+    ring = sparrow.Ring(1500, nr, seed=4)
+    oring = oracle.Ring(1500, nr, seed=4)
+    raw = []
+    slot_raw = {}
+    for K in (24, 12):
+        head = ring.head
+        acts = torch.zeros(K, N, dtype=torch.int32, device=env.device)
+        rew = torch.zeros(K, N, dtype=torch.float32, device=env.device)
+        done = torch.zeros(K, N, dtype=torch.uint8, device=env.device)
+        env.rollout_collect(ring, K, False, acts, rew, done)
+        torch.cuda.synchronize()
+        first = len(raw)
+        rows, o_obs = _oracle_collect(orc, oring, o_obs, K, lambda t, o: orc.uniform_actions(),
+                                      raw)
+        for t, (a, r, d) in enumerate(rows):
+            w = f"{wl} {variant} K={K} t={t}"
+            compare_exact(to_np(acts[t]), a, "actions", w)
+            compare_exact(to_np(rew[t]), r, "reward", w)
+            compare_exact(to_np(done[t]), d, "done", w)
+            for i in range(N):
+                slot_raw[(head + t * N + i) % 1500] = (raw[first + t][0][i], raw[first + t][1][i])
+        assert (ring.size, ring.head) == (oring.size, oring.head)
+    slots = np.arange(ring.size)
+    rs = np.stack([slot_raw[s][0] for s in slots])
+    rsn = np.stack([slot_raw[s][1] for s in slots])
+    _compare_ring_slots(ring, oring, slots, rs, rsn, nr, f"{wl} {variant} ring")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, f"{wl} {variant} final")
+    compare_obs(to_np(env.obs), o_obs, nr, wl != "c1", "final obs")
+    # samples of the collected buffer
+    for draw in (0, 7):
+        *vals, idx = ring.sample(256, draw)
+        torch.cuda.synchronize()
+        *ovals, oidx = oring.sample(256, draw)
+        compare_exact(to_np(idx), oidx.astype(np.int32), "idx", f"draw {draw}")
+    assert env.status() == 0 and ring.status() == 0
+
+
+def test_rollout_collect_fused_actor_lockstep(torch_gpu):
+    """The collecting rollout with the fused BF16 actor + VEM: the oracle runs
+    its own FP64 actor; transitions of envs whose actions have equalled the
+    FP64 actor's so far are compared slot by slot."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=45)
+    N, nr, K = 45, cfg["n_rays"], 20
+    banner(f"collecting fused rollout c2 N={N} K={K}")
+    maps = inputs.make_maps(cfg)
+    env = sparrow.Env(cfg, maps)
+    orc = oracle.Oracle(cfg, maps)
+    dims = (env.obs_dim, 256, 256, 7)
+    w, b, _ = inputs.qnet_weights(dims)
+    eps = sparrow.vem_epsilon(N, N, 0.01, 0.29)
+    env.set_qnet(dims, w, b, eps)
+    env.reset()
+    o_obs, _ = orc.reset()
+    ring = sparrow.Ring(2048, nr, seed=2)
+    oring = oracle.Ring(2048, nr, seed=2)
+    acts = torch.zeros(K, N, dtype=torch.int32, device=env.device)
+    env.rollout_collect(ring, K, True, acts)
+    torch.cuda.synchronize()
+    g_acts = to_np(acts)
+    live = np.ones(N, bool)
+    live_at = []
+
+    def fp64_actor(t, o_obs):
+        nonlocal live
+        a_o, ex = orc.vem(oracle.qnet_f64(dims, w, b, o_obs), eps)
+        exb = ex.astype(bool)
+        q_ra = oracle.qnet_f64(dims, w, b, o_obs, round_act=True)
+        top, settled = settled_greedy(q_ra, qnet_rounded_bound(dims, w, b, o_obs, RANGE_TOL))
+        compare_exact(g_acts[t][live & exb], a_o[live & exb], "explored actions", f"t={t}")
+        m = live & ~exb & settled
+        compare_exact(g_acts[t][m], top[m], "settled greedy actions", f"t={t}")
+        live = live & (g_acts[t] == a_o)
+        live_at.append(live.copy())
+        return a_o
+    raw = []
+    _oracle_collect(orc, oring, o_obs, K, fp64_actor, raw)
+    print(f"{live.sum()} of {N} envs compared through {K} steps", flush=True)
+    assert live.mean() >= 0.9
+    assert (ring.size, ring.head) == (oring.size, oring.head) == (K * N, K * N)
+    slots = np.arange(K * N)
+    mask = np.concatenate(live_at)
+    rs = np.concatenate([x[0] for x in raw])
+    rsn = np.concatenate([x[1] for x in raw])
+    _compare_ring_slots(ring, oring, slots, rs, rsn, nr, "fused ring", mask)
+    assert env.status() == 0 and ring.status() == 0
+
+
+def test_rollout_collect_rejects_mismatched_ring(torch_gpu):
+    from paper_2305_04180_amd import sparrow
+    cfg = inputs.workload("c1")
+    banner("collecting rollout argument errors")
+    env = sparrow.Env(cfg, inputs.make_maps(cfg))
+    env.reset()
+    N = cfg["n_envs"]
+    with pytest.raises(sparrow.SparrowError):
+        env.rollout_collect(sparrow.Ring(4 * N, cfg["n_rays"] + 1), 2, False)  # ray count
+    small = sparrow.Ring(4 * N - 1, cfg["n_rays"])
+    with pytest.raises(sparrow.SparrowError):
+        env.rollout_collect(small, 4, False)  # 4 N > capacity
+    env.rollout_collect(small, 3, False)
+    assert small.size == 3 * N and small.head == 3 * N
+    assert env.status() == 0 and small.status() == 0
