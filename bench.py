@@ -10,6 +10,8 @@ A "step" is one vectorized step of all N envs: actor + simulator step.
           replayed from a cached HIP graph; the headline value
   plain : per step, uniform random actions + the plain step kernel
   plain+actor : per step, the separate actor kernel + the plain step kernel
+  fused+collect : the fused rollouts adding every step's transitions to a
+          device ring inside the kernel (reported beside the headline)
 The fused path is timed over --repeats runs of exactly --steps steps each
 (HIP events on the launch stream); value is the median run. Prints one JSON
 line (rank 0, N=1 only).
@@ -518,6 +520,41 @@ def main():
     samples_last = float(torch.where(hits < 0, torch.full_like(hits, M), hits).add(1).sum().item())
     log(f"[bench] fused: {fused_rate / 1e6:.1f} M env-steps/s ({fused_ms / steps_fused * 1e3:.2f} us/step)")
 
+    # ---------------- fused rollout that also fills the ring ----------------
+    # Alg. 1 steps 2-5 in one kernel: the same rollouts, each step's N
+    # transitions added to a 2^22-slot device ring inside the kernel.
+    ring = sparrow.Ring(1 << 22, cfg["n_rays"], seed=cfg["seed"])
+
+    def collect_run(terminal):
+        for _ in range(n_warm):
+            env.rollout_collect(ring, K, True, obs=obs, terminal_obs=terminal)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(n_full):
+            env.rollout_collect(ring, K, True, obs=obs, terminal_obs=terminal)
+        if rem:
+            env.rollout_collect(ring, rem, True, obs=obs, terminal_obs=terminal)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        assert env.status() == 0 and ring.status() == 0
+        return c0.elapsed_time(c1)
+    collect_ms = collect_run(True)
+    collect_pr_ms = collect_run(False)
+    fused_collect = {
+        "value": round(N * args.steps / (collect_ms / 1e3), 1), "unit": "env-steps/s",
+        "steps": args.steps, "ring_slots": 1 << 22, "ring_size": ring.size,
+        "over_fused": round(fused_ms / collect_ms, 4),
+        "post_reset_s_next_value": round(N * args.steps / (collect_pr_ms / 1e3), 1),
+        "what": "fused rollout that adds (s, a, r, s', done) of every step to the device ring "
+                "inside the kernel (uint8 ranges, binary16 scalars, int8 action, FP32 reward, "
+                "done bit); s' of a done transition is its terminal observation (value) or the "
+                "post-reset observation (post_reset_s_next_value)"}
+    del ring
+    log(f"[bench] fused+collect: {fused_collect['value'] / 1e6:.1f} M env-steps/s "
+        f"(post-reset s': {fused_collect['post_reset_s_next_value'] / 1e6:.1f} M)")
+
     # ---------------- plain step ----------------
     P = args.plain_steps
     a_buf = torch.zeros(N, dtype=torch.int32, device="cuda")
@@ -630,6 +667,7 @@ def main():
         "plain_env_steps_per_s": round(plain_rate, 1),
         "plain_actor_env_steps_per_s": round(pa_rate, 1),
         "fused_over_plain": round(fused_rate / plain_rate, 3),
+        "fused_collect": fused_collect,
         "wall_s_timed": round(wall, 4),
         "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)},
         "kernel_source_sha1": kernel_source_hash(),

@@ -260,15 +260,19 @@ void sparrow_ring_destroy(sparrow_ring *ring);
  * transition (t, i) at slot (head + t N + i) mod capacity, stored exactly as
  * sparrow_ring_push stores them. s is the observation the actor saw (for
  * t = 0 the current observation), a_hat the actor's action (before the
- * control delay), s' the observation after the step or, for a done env, its
- * terminal observation before the reset (the one sparrow_step returns as
- * final_obs). Afterwards head and size advance by K N. Requirements: the
- * ring's n_rays equals the env's and K N <= capacity (EINVAL otherwise).
- * actions, reward, done (dev [K][N]) are nullable here; obs as in
- * sparrow_rollout. The kernel runs on the env's stream: when the ring is
- * bound to another stream, the caller orders the two (events). */
+ * control delay), s' the observation after the step. For a done env, s' is
+ * its terminal observation before the reset (the one sparrow_step returns
+ * as final_obs; push with s_final) when terminal_obs != 0, else the
+ * observation after the AutoReset (what the step returns as obs; push
+ * without s_final), which skips one ray cast per done env. Afterwards head
+ * and size advance by K N. Requirements: the ring's n_rays equals the env's
+ * and K N <= capacity (EINVAL otherwise). actions, reward, done (dev [K][N])
+ * are nullable here; obs as in sparrow_rollout. Runs on the env's stream (a
+ * small kernel clearing the range's done bits, then the rollout): when the
+ * ring is bound to another stream, the caller orders the two (events). */
 int sparrow_rollout_collect(sparrow_env *env, sparrow_ring *ring, int32_t K, int32_t use_qnet,
-                            int32_t *actions, float *reward, uint8_t *done, float *obs);
+                            int32_t terminal_obs, int32_t *actions, float *reward,
+                            uint8_t *done, float *obs);
 
 /* ---- Learner ---------------------------------------------------------------
  * The learner's update of Alg. 2 step 2 (train the learner's model on a

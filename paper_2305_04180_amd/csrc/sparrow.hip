@@ -161,7 +161,8 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
 // COLL: every step also adds its N transitions (s, a_hat, r, s', done) to the
 // experience buffer (Alg. 1 step 5), transition (t, i) at slot
 // (ring_head + t N + i) mod capacity. s' of a done env is its terminal
-// observation (taken before the reset, with the step's own noise draws); the
+// observation (taken before the reset, with the step's own noise draws) when
+// ring_terminal is set, else the observation after the reset; the
 // observation after the step, reset or not, is also the next transition's s.
 template <int L, class QC, bool COLL>
 __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
@@ -257,12 +258,15 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
           const RingRow next_s =
               last ? RingRow{nullptr, nullptr} : ring_row(p.ring.rs, p.ring.cs, p.n_rays, ring_slot(p, t + 1, i));
           const RingRow this_sn = ring_row(p.ring.rsn, p.ring.csn, p.n_rays, s0);
-          // pass 0 (done envs only): the terminal observation as s'; pass 1:
-          // AutoReset, then the observation that continues the rollout
+          // pass 0 (done envs, with terminal observations requested): the
+          // terminal observation as s'; pass 1: AutoReset, then the
+          // observation that continues the rollout (also s' where pass 0
+          // did not run)
+          const bool term_pass = o.done && p.ring_terminal;
 #pragma unroll 1
           for (int pass = 0; pass < 2; ++pass) {
             const bool terminal = pass == 0;
-            if (terminal && !o.done) continue;
+            if (terminal && !term_pass) continue;
             if (!terminal && o.done) {
               free_pose = reset_env<L>(p, ln, m, e, i, g);
               if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
@@ -271,13 +275,13 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
                        terminal ? nullptr : orow, terminal ? nullptr : crow,
                        terminal ? nullptr : hk, terminal ? nullptr : act_in,
                        !terminal && free_pose,
-                       (terminal || !o.done) ? this_sn : RingRow{nullptr, nullptr},
+                       (terminal || !term_pass) ? this_sn : RingRow{nullptr, nullptr},
                        terminal ? RingRow{nullptr, nullptr} : next_s);
           }
           if (ln.q == 0) {
             p.ring.act[s0] = (int8_t)a_hat;
             p.ring.rew[s0] = o.reward;
-            ring_set_done(p.ring, s0, o.done != 0);
+            if (o.done) ring_set_done(p.ring, s0);  // the launcher cleared the range's bits
           }
         } else {
           if (o.done) {
@@ -907,7 +911,8 @@ int sparrow_act(sparrow_env* e, const float* obs, int32_t* actions) {
 
 static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int32_t* actions,
                           float* reward, uint8_t* done, float* obs, bool use_graph,
-                          const RingDev* ring = nullptr, int32_t ring_head = 0) {
+                          const RingDev* ring = nullptr, int32_t ring_head = 0,
+                          bool ring_terminal = true) {
   const int reserve = q ? (int)qnet_lds_bytes(e->qp) : 0;
   const int budget_words = (e->lds_max - reserve) / 4;
   Groups* gr = nullptr;
@@ -934,6 +939,10 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   if (ring) {
     p.ring = *ring;
     p.ring_head = ring_head;
+    p.ring_terminal = ring_terminal ? 1 : 0;
+    // the kernel sets the done bits of done transitions only
+    rc = ring_clear_done(*ring, ring_head, (int64_t)K * e->cfg.n_envs, e->stream);
+    if (rc) return rc;
   }
   QParams qp = e->qp;
   qp.lds_base_words = gr->max_words;
@@ -985,7 +994,8 @@ int sparrow_rollout(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* action
 }
 
 int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32_t use_qnet,
-                            int32_t* actions, float* reward, uint8_t* done, float* obs) {
+                            int32_t terminal_obs, int32_t* actions, float* reward, uint8_t* done,
+                            float* obs) {
   if (!e || !ring || !obs || K < 1) return fail(SPARROW_EINVAL, "bad argument");
   if (use_qnet && !e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
   if (use_qnet && !qnet_in_registers(qnet_kind(e->qp)))
@@ -1001,7 +1011,7 @@ int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32
   if ((int64_t)K * e->cfg.n_envs > (int64_t)rd.cap)
     return fail(SPARROW_EINVAL, "K * n_envs transitions exceed the buffer's capacity");
   rc = launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done, obs,
-                      true, &rd, (int32_t)head);
+                      true, &rd, (int32_t)head, terminal_obs != 0);
   if (rc) return rc;
   ring_advance(ring, (int64_t)K * e->cfg.n_envs);
   return SPARROW_OK;

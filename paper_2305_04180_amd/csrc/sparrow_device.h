@@ -168,6 +168,7 @@ struct Params {
   // collecting rollout: the experience buffer and the slot of its next add
   RingDev ring;
   int32_t ring_head;
+  int32_t ring_terminal;    // s' of a done transition: 1 terminal, 0 post-reset observation
 };
 
 // Destination of one observation in the experience buffer (both NULL: none).

@@ -85,6 +85,27 @@ k_ring_push(RingDev R, int64_t head, int32_t n, const float* __restrict__ s,
   }
 }
 
+// Clear the done bits of slots head .. head + n - 1 (mod cap) and keep the
+// others, one thread per word (the same word walk as the push): a kernel
+// that adds those n transitions afterwards only sets the bits of done slots.
+__global__ void __launch_bounds__(kRingThreads)
+k_ring_clear_done(RingDev R, int64_t head, int64_t n) {
+  const bool wraps = head + n > R.cap;
+  const int64_t w0 = wraps ? 0 : head >> 5;
+  const int64_t w1 = wraps ? ((int64_t)R.cap - 1) >> 5 : (head + n - 1) >> 5;
+  for (int64_t w = w0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w <= w1;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t keep = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int64_t slot = w * 32 + b;
+      int64_t i = slot - head;
+      if (i < 0) i += R.cap;
+      if (!(slot < R.cap && i < n)) keep |= 1u << b;
+    }
+    R.done[w] &= keep;
+  }
+}
+
 // Decode B slots. With `slots` NULL, slot b is floor(w * size / 2^32) for the
 // first word w of Philox (b, draw, 8, 0); every entry of a row recomputes it,
 // which costs less than a second launch.
@@ -266,6 +287,15 @@ int sp::ring_view(const sparrow_ring* R, RingDev* view, int64_t* head) {
   if (!R || !view || !head) return fail(SPARROW_EINVAL, "NULL argument");
   *view = R->dev;
   *head = R->head;
+  return SPARROW_OK;
+}
+
+int sp::ring_clear_done(const RingDev& R, int64_t head, int64_t n, hipStream_t stream) {
+  if (n <= 0) return SPARROW_OK;
+  const int64_t words = n / 32 + 2;
+  hipLaunchKernelGGL(k_ring_clear_done, dim3(grid_for(words)), dim3(kRingThreads), 0, stream, R,
+                     head, n);
+  HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
 

@@ -41,13 +41,10 @@ __device__ __forceinline__ float f16_value(uint16_t h) {
   return (float)__builtin_bit_cast(_Float16, h);
 }
 
-// set or clear the done bit of a slot (writers of one word may race)
-__device__ __forceinline__ void ring_set_done(const RingDev& R, int64_t slot, bool d) {
-  const uint32_t bit = 1u << (uint32_t)(slot & 31);
-  if (d)
-    atomicOr(&R.done[slot >> 5], bit);
-  else
-    atomicAnd(&R.done[slot >> 5], ~bit);
+// set the done bit of a slot whose bit was cleared beforehand (writers of
+// one word may race)
+__device__ __forceinline__ void ring_set_done(const RingDev& R, int64_t slot) {
+  atomicOr(&R.done[slot >> 5], 1u << (uint32_t)(slot & 31));
 }
 
 }  // namespace sp
@@ -57,4 +54,6 @@ namespace sp {
 // and advancing its head and size after another kernel wrote n transitions.
 int ring_view(const sparrow_ring* ring, RingDev* view, int64_t* head);
 void ring_advance(sparrow_ring* ring, int64_t n);
+// Clear the done bits of slots head .. head + n - 1 (mod capacity), on stream.
+int ring_clear_done(const RingDev& ring, int64_t head, int64_t n, hipStream_t stream);
 }  // namespace sp

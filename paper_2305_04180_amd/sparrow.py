@@ -90,7 +90,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_qnet_forward": (I32, [P, P, I32, P, P]),
             "sparrow_act": (I32, [P, P, P]),
             "sparrow_rollout": (I32, [P, I32, I32, P, P, P, P]),
-            "sparrow_rollout_collect": (I32, [P, P, I32, I32, P, P, P, P]),
+            "sparrow_rollout_collect": (I32, [P, P, I32, I32, I32, P, P, P, P]),
             "sparrow_debug_hits": (I32, [P, P]),
             "sparrow_get_state": (I32, [P, P, P]),
             "sparrow_set_state": (I32, [P, P, P]),
@@ -298,10 +298,12 @@ class Env:
                                      _ptr(reward), _ptr(done), _ptr(obs)))
         return actions, reward, done, obs
 
-    def rollout_collect(self, ring, K, use_qnet, actions=None, reward=None, done=None, obs=None):
+    def rollout_collect(self, ring, K, use_qnet, actions=None, reward=None, done=None, obs=None,
+                        terminal_obs=True):
         """K fused steps that also add their K * N transitions to `ring`
         (Alg. 1 steps 2-5 in one kernel); the step-major actions, rewards and
-        done flags are optional outputs here."""
+        done flags are optional outputs here. terminal_obs: s' of a done
+        transition is the terminal observation (else the post-reset one)."""
         torch = self.torch
         n = self.n
         obs = self.obs if obs is None else obs
@@ -310,7 +312,8 @@ class Env:
         self._b(done, torch.uint8, K * n, "done", nullable=True)
         self._b(obs, torch.float32, n * self.obs_dim, "obs")
         _check(lib().sparrow_rollout_collect(self._h, ring._h, K, int(bool(use_qnet)),
-                                             _ptr(actions), _ptr(reward), _ptr(done), _ptr(obs)))
+                                             int(bool(terminal_obs)), _ptr(actions), _ptr(reward),
+                                             _ptr(done), _ptr(obs)))
         return actions, reward, done, obs
 
     # -- inspection -----------------------------------------------------------

@@ -310,18 +310,22 @@ def test_collection_loop_small(torch_gpu):
     assert env.status() == 0 and ring.status() == 0
 
 
-def _oracle_collect(orc, oring, o_obs, K, actions_fn, raw):
+def _oracle_collect(orc, oring, o_obs, K, actions_fn, raw, terminal=True):
     """The oracle's side of a collecting rollout from observation o_obs: K
     steps, each adding its N transitions (s' = the terminal observation
-    where done) to the oracle's ring; raw collects (s, s') per step for the
-    tie-aware comparison. Returns the per-step (a, r, done) and the last
-    observation."""
+    where done, or the post-reset one with terminal=False) to the oracle's
+    ring; raw collects (s, s') per step for the tie-aware comparison.
+    Returns the per-step (a, r, done) and the last observation."""
     rows = []
     for t in range(K):
         a = actions_fn(t, o_obs)
         r = orc.step(a, final_obs=True)
-        sn = np.where(r["done"][:, None].astype(bool), r["final_obs"], r["obs"])
-        oring.push(o_obs, a, r["reward"], r["obs"], r["done"], r["final_obs"])
+        if terminal:
+            sn = np.where(r["done"][:, None].astype(bool), r["final_obs"], r["obs"])
+            oring.push(o_obs, a, r["reward"], r["obs"], r["done"], r["final_obs"])
+        else:
+            sn = r["obs"]
+            oring.push(o_obs, a, r["reward"], r["obs"], r["done"])
         raw.append((o_obs.copy(), sn.copy()))
         rows.append((a, r["reward"], r["done"]))
         o_obs = r["obs"]
@@ -340,19 +344,24 @@ def _compare_ring_slots(ring, oring, slots, raw_s, raw_sn, nr, where, mask=None)
     compare_exact(g[4][keep], o[4][keep], "done", where)
 
 
-@pytest.mark.parametrize("wl,variant", [("c1", (8, 64)), ("c2", (8, 64)), ("c2", (4, 32)),
-                                        ("c2", (2, 16))])
-def test_rollout_collect_uniform_matches_oracle_ring(torch_gpu, wl, variant):
-    """Alg. 1 steps 2-5 in one kernel: two collecting rollouts (K = 24, then
-    K = 12, so the second wraps a 1500-slot ring) with uniform actions; every
-    stored slot against the oracle's ring filled by its own step-and-add
-    loop, the step-major outputs and the final state against the oracle."""
+@pytest.mark.parametrize("wl,variant,terminal", [("c1", (8, 64), True), ("c2", (8, 64), True),
+                                                 ("c2", (4, 32), True), ("c2", (2, 16), True),
+                                                 ("c2", (8, 64), False), ("c1", (4, 16), False)])
+def test_rollout_collect_uniform_matches_oracle_ring(torch_gpu, wl, variant, terminal):
+    """Alg. 1 steps 2-5 in one kernel: after an add of 7 transitions, two
+    collecting rollouts (K = 24, then K = 12, so the second wraps a
+    1500-slot ring and overwrites slots with done bits set) with uniform
+    actions; every stored slot against the oracle's ring filled by its own
+    step-and-add loop, the step-major outputs and the final state against
+    the oracle. terminal: s' of done transitions is the terminal observation
+    (else the post-reset one)."""
     import oracle
     from paper_2305_04180_amd import sparrow
     torch = torch_gpu
     cfg = inputs.workload(wl, n_envs=45)
     N, nr = 45, cfg["n_rays"]
-    banner(f"collecting rollout {wl} N={N} variant={variant}, K=24 then 12, ring 1500")
+    banner(f"collecting rollout {wl} N={N} variant={variant} terminal={terminal}, "
+           f"7 added, K=24 then 12, ring 1500")
     maps = inputs.make_maps(cfg)
     env = sparrow.Env(cfg, maps)
     orc = oracle.Oracle(cfg, maps)
@@ -361,18 +370,24 @@ def test_rollout_collect_uniform_matches_oracle_ring(torch_gpu, wl, variant):
     o_obs, _ = orc.reset()
     ring = sparrow.Ring(1500, nr, seed=4)
     oring = oracle.Ring(1500, nr, seed=4)
+    rng = np.random.default_rng(5)
+    pre = (rng.uniform(0, 1, (7, nr + 4)).astype(np.float32), rng.integers(0, 7, 7).astype(np.int32),
+           rng.normal(size=7).astype(np.float32), rng.uniform(0, 1, (7, nr + 4)).astype(np.float32),
+           np.ones(7, np.uint8))  # every added transition done: its bits must be kept
+    ring.push(*to_gpu(torch, *pre))
+    oring.push(*pre)
     raw = []
-    slot_raw = {}
+    slot_raw = {k: (pre[0][k], pre[3][k]) for k in range(7)}
     for K in (24, 12):
         head = ring.head
         acts = torch.zeros(K, N, dtype=torch.int32, device=env.device)
         rew = torch.zeros(K, N, dtype=torch.float32, device=env.device)
         done = torch.zeros(K, N, dtype=torch.uint8, device=env.device)
-        env.rollout_collect(ring, K, False, acts, rew, done)
+        env.rollout_collect(ring, K, False, acts, rew, done, terminal_obs=terminal)
         torch.cuda.synchronize()
         first = len(raw)
         rows, o_obs = _oracle_collect(orc, oring, o_obs, K, lambda t, o: orc.uniform_actions(),
-                                      raw)
+                                      raw, terminal)
         for t, (a, r, d) in enumerate(rows):
             w = f"{wl} {variant} K={K} t={t}"
             compare_exact(to_np(acts[t]), a, "actions", w)
@@ -381,10 +396,15 @@ def test_rollout_collect_uniform_matches_oracle_ring(torch_gpu, wl, variant):
             for i in range(N):
                 slot_raw[(head + t * N + i) % 1500] = (raw[first + t][0][i], raw[first + t][1][i])
         assert (ring.size, ring.head) == (oring.size, oring.head)
-    slots = np.arange(ring.size)
-    rs = np.stack([slot_raw[s][0] for s in slots])
-    rsn = np.stack([slot_raw[s][1] for s in slots])
-    _compare_ring_slots(ring, oring, slots, rs, rsn, nr, f"{wl} {variant} ring")
+        # every stored slot, after each rollout (the first keeps the 7 added
+        # transitions and their done bits in the word it shares with them)
+        slots = np.arange(ring.size)
+        rs = np.stack([slot_raw[s][0] for s in slots])
+        rsn = np.stack([slot_raw[s][1] for s in slots])
+        _compare_ring_slots(ring, oring, slots, rs, rsn, nr, f"{wl} {variant} K={K} ring")
+    # the second rollout wrapped over the 7 added transitions and the first
+    # rollout's oldest ones
+    assert ring.size == 1500 and ring.head == (7 + 36 * N) % 1500
     gf, gi = env.get_state()
     of, oi = orc.get_state()
     compare_state(gf, gi, of, oi, f"{wl} {variant} final")
