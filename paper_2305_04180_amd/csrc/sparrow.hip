@@ -99,6 +99,8 @@ __device__ __forceinline__ Slot make_slot(const Params& p, const int4& sl, const
   m.W = mm.W;
   m.H = mm.H;
   m.wpr = mm.wpr;
+  m.wlo = -1 - mm.wpr;
+  m.whi = (mm.H + 1) * mm.wpr - 1;
   return m;
 }
 
@@ -109,13 +111,14 @@ __device__ __forceinline__ int32_t ring_slot(const Params& p, int t, int i) {
   return s >= p.ring.cap ? s - p.ring.cap : s;
 }
 
-// mode 0: step, mode 1: reset
+// mode 0: step, mode 1: reset. Each env stages only the rows of its map
+// within range of the robot (after the motion, or after the AutoReset), into
+// its own part of LDS with its own lanes: no workgroup barrier. The
+// AutoReset tests its candidates against the packed map in global memory.
 template <int L>
 __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   extern __shared__ uint32_t lds[];
   const int grp = blockIdx.x;
-  stage_maps(p, grp, lds);
-  __syncthreads();
   const int slot = threadIdx.x / L;
   if (slot >= p.epw) return;
   const int4 sl = p.slots[grp * p.epw + slot];
@@ -123,7 +126,8 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   const int i = sl.x;
   const Lanes<L> ln(threadIdx.x);
   const RayDirs<L> rd = load_rays<L>(p.rays, p.n_rays, ln.q);
-  const Slot m = make_slot(p, sl, lds);
+  const MapMeta mm = p.meta[sl.y];
+  uint32_t* buf = lds + sl.z;
   const float inv_dn = p.inv_dn[sl.y];
   const int D = p.obs_dim;
   Env e = load_env(p.s, i);
@@ -131,9 +135,12 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   float* crow = p.cur_obs + (size_t)i * D;
   int16_t* hk = p.hit_k + (size_t)i * p.n_rays;
   StepOut o{};
+  Slot m{};
   bool reset_now = mode == 1;
   if (mode == 0) {
-    o = step_env<L>(p, ln, m, e, p.actions[i]);
+    step_motion(p, e, p.actions[i]);
+    m = stage_window<L>(p, ln, mm, buf, e.y);
+    o = step_outcome<L>(p, ln, m, e);
     reset_now = o.done != 0;
     if (reset_now && p.final_obs)
       observe<L>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D, nullptr,
@@ -141,8 +148,9 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   }
   bool free_pose = true;  // not done: the step's collision test passed
   if (reset_now) {
-    free_pose = reset_env<L>(p, ln, m, e, i, p.g);
+    free_pose = reset_env<L>(p, ln, global_slot(p, mm), e, i, p.g);
     if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
+    m = stage_window<L>(p, ln, mm, buf, e.y);
   }
   observe<L>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
              nullptr, free_pose);
@@ -407,7 +415,7 @@ struct sparrow_env {
   // for 4096 envs on 366^2 maps with 32 rays)
   int var_epw[2] = {1, 8};
   int var_L[2] = {64, 64};
-  std::map<std::pair<int, int>, Groups> groups;  // (epw, budget words)
+  std::map<std::tuple<int, int, bool>, Groups> groups;  // (epw, budget words, windowed)
   std::map<std::tuple<int, int, int, int>, GraphEntry> graphs;
   // actor
   bool has_qnet = false;
@@ -423,10 +431,28 @@ int obs_dim(const sparrow_env* e) { return e->cfg.n_rays + 4; }
 
 int words_of(const MapMeta& m) { return (1 + m.wpr * (m.H + 2) + 3) & ~3; }
 
-// Envs sorted by packed size (largest first), packed greedily into groups of at
-// most epw envs whose maps fit the LDS budget together.
-int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out) {
-  auto key = std::make_pair(epw, budget_words);
+// Rows staged on each side of the robot's row by the windowed step: every
+// sample of a ray (distance <= range, |u| <= 1 up to rounding) and every
+// cell of the collision disk lies within ceil(max(range, r)) + 1 rows.
+int window_rows(const sparrow_config& c) {
+  return (int)std::ceil(std::max((double)c.range_cells, (double)c.robot_radius)) + 2;
+}
+
+// LDS words of a windowed slot: at most 2 win + 1 rows (and at most the map's
+// H + 2), the word in front, up to three words of 16-byte alignment in front
+// of that, rounded up to 16 bytes; never more than the whole padded map.
+int window_words_of(const MapMeta& m, int win) {
+  const int rows = std::min(m.H + 2, 2 * win + 1);
+  return std::min(words_of(m), (rows * m.wpr + 4 + 3) & ~3);
+}
+
+// Envs sorted by slot size (largest first), packed greedily into groups of
+// at most epw envs whose slots fit the LDS budget together. A slot holds the
+// whole packed map, or (windowed) the rows within range of the robot.
+int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out, bool windowed = false) {
+  const int win = window_rows(e->cfg);
+  auto slot_words = [&](const MapMeta& m) { return windowed ? window_words_of(m, win) : words_of(m); };
+  auto key = std::make_tuple(epw, budget_words, windowed);
   auto it = e->groups.find(key);
   if (it != e->groups.end()) {
     *out = &it->second;
@@ -436,7 +462,7 @@ int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out) {
   std::vector<int> order(N);
   for (int i = 0; i < N; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return words_of(e->h_meta[e->h_env_map[a]]) > words_of(e->h_meta[e->h_env_map[b]]);
+    return slot_words(e->h_meta[e->h_env_map[a]]) > slot_words(e->h_meta[e->h_env_map[b]]);
   });
   std::vector<int4> slots;
   Groups gr;
@@ -455,7 +481,7 @@ int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out) {
   };
   for (int i : order) {
     const int m = e->h_env_map[i];
-    const int w = words_of(e->h_meta[m]);
+    const int w = slot_words(e->h_meta[m]);
     if (w > budget_words)
       return fail(SPARROW_EUNSUPPORTED, "a map does not fit the LDS budget of a workgroup");
     if (cur == epw || used + w > budget_words) flush();
@@ -490,6 +516,7 @@ Params base_params(sparrow_env* e) {
   while (p.k_free <= p.M &&
          (double)p.k_free * c.march_step * (1.0 + 1e-6) + 1e-3 <= (double)c.robot_radius)
     ++p.k_free;
+  p.win_rows = window_rows(c);
   p.t_max = c.timeout_steps;
   p.delay_lo = c.delay_lo;
   p.delay_hi = c.delay_hi;
@@ -535,7 +562,7 @@ int launch_step_L(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
 
 int launch_step(sparrow_env* e, Params p, int mode, int epw, int L) {
   Groups* gr = nullptr;
-  int rc = get_groups(e, epw, e->lds_max / 4, &gr);
+  int rc = get_groups(e, epw, e->lds_max / 4, &gr, true);
   if (rc) return rc;
   p.slots = gr->d_slots;
   p.n_groups = gr->G;

@@ -143,6 +143,7 @@ struct Params {
   int32_t n_groups, epw;
   int32_t n_envs, n_rays, obs_dim, M, t_max, delay_lo, delay_hi;
   int32_t k_free;           // samples with t_k (1 + 1e-6) + 1e-3 <= robot radius
+  int32_t win_rows;         // rows staged on each side of the robot's row (windowed step)
   float ds, range, inv_R, robot_r, arrive_r, omega_max;
   float dt_lo, dt_span, K_lo, K_span, mu_lo, mu_span, vmax_lo, vmax_span, sigma_lo,
       sigma_span;
@@ -240,29 +241,35 @@ __device__ __forceinline__ int med3i(int x, int lo, int hi) {
   return r;
 }
 
-// A map slot in LDS. Row y (y = -1..H) is n = ceil((W + 2) / 32) words; cell
+// A map slot. Row y (y = -1..H) is n = ceil((W + 2) / 32) words; cell
 // x >= 0 is bit x & 31 of word x >> 5 of its row, and columns -1 and -2 are
 // bits 31 and 30 of the previous row's last word (columns >= W, so set), with
 // one set word in front of row -1. Every bit outside [0, W) x [0, H) is set,
 // so a coordinate clamped to [-1, W] x [-1, H] reads as occupied: outside the
 // map counts as an obstacle. w1 points at word 0 of row 0; the word of (x, y)
 // is w1[y * n + (x >> 5)] with an arithmetic shift, its bit x & 31.
+// A slot holds the whole map, or a window of rows y_lo..y_hi together with
+// the word in front of row y_lo (the last word of row y_lo - 1, or the set
+// word): [wlo, whi] = [y_lo n - 1, (y_hi + 1) n - 1] are the word indices
+// it holds, relative to w1.
 struct Slot {
   const uint32_t* w1;
   int32_t W, H, wpr;
+  int32_t wlo, whi;
   // The march's address: no per-axis clamp, only the word index clamped to
-  // the slot, [-1 - n, (H + 1) n - 1] (the set word in front .. the last word
-  // of row H). Exact for a ray that starts inside the map: consecutive
-  // samples move at most ds |u| <= 1 (+ rounding, < 2 cells) per axis, so the
-  // first sample outside [0, W) x [0, H) lies within two cells of the map and
-  // its word and bit are set ones (rows -1 and H; the two padding columns,
-  // which are also columns -1 and -2 of the next row; the set word or the
-  // clamp for row -2 and row H + 1). Later samples of the same block may
-  // read any word of the slot; they are past the first hit and never count.
+  // the slot's words. Exact for a ray that starts inside the map:
+  // consecutive samples move at most ds |u| <= 1 (+ rounding, < 2 cells) per
+  // axis, so the first sample outside [0, W) x [0, H) lies within two cells
+  // of the map and its word and bit are set ones (rows -1 and H; the two
+  // padding columns, which are also columns -1 and -2 of the next row; the
+  // set word or the clamp for row -2 and row H + 1). A window covers every
+  // row within the range of the robot, so no sample up to the first hit
+  // leaves it. Later samples of the same block may read any word of the
+  // slot; they are past the first hit and never count.
   __device__ __forceinline__ const uint32_t* word_of_march(int ix, int iy, int& bit) const {
     bit = ix;  // the bit-field extract uses its low five bits
     int w = __mul24(iy, wpr) + (ix >> 5);
-    w = med3i(w, -1 - wpr, (H + 1) * wpr - 1);
+    w = med3i(w, wlo, whi);
     asm("" : "+v"(w));
     return w1 + w;
   }
@@ -578,9 +585,9 @@ struct StepOut {
   uint8_t done, flags;
 };
 
-template <int L>
-__device__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m, Env& e,
-                            int a_hat) {
+// Control delay, command, Eq. (5) and Eq. (6): the part of the step that
+// does not read the map.
+__device__ __forceinline__ void step_motion(const Params& p, Env& e, int a_hat) {
   if (a_hat < 0 || a_hat >= kNumActions) a_hat = kStop;
   int a;
   if (e.delay == 0) {
@@ -614,7 +621,12 @@ __device__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m, 
   e.vl = vl;
   e.va = va;
   e.t += 1;
-  // collision, arrival, reward (Sec. 4.3.1)
+}
+
+// Collision, arrival, reward and truncation at the new pose (Sec. 4.3.1).
+template <int L>
+__device__ __forceinline__ StepOut step_outcome(const Params& p, const Lanes<L>& ln,
+                                                const Slot& m, Env& e) {
   const bool coll = collides_env<L>(ln, m, e.x, e.y, p.robot_r);
   const float dx = e.tx - e.x, dy = e.ty - e.y;
   const float d2 = dx * dx + dy * dy;
@@ -639,6 +651,66 @@ __device__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m, 
   o.flags = (uint8_t)((term ? 1 : 0) | (trunc ? 2 : 0) | (coll ? 4 : 0) |
                       (arrived && !coll ? 8 : 0));
   return o;
+}
+
+template <int L>
+__device__ __forceinline__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m,
+                                            Env& e, int a_hat) {
+  step_motion(p, e, a_hat);
+  return step_outcome<L>(p, ln, m, e);
+}
+
+// The whole packed map m in global memory as a slot (the AutoReset of the
+// windowed step tests candidates anywhere on the map).
+__device__ __forceinline__ Slot global_slot(const Params& p, const MapMeta& mm) {
+  Slot s;
+  s.w1 = p.words + mm.off + 1 + mm.wpr;
+  s.W = mm.W;
+  s.H = mm.H;
+  s.wpr = mm.wpr;
+  s.wlo = -1 - mm.wpr;
+  s.whi = (mm.H + 1) * mm.wpr - 1;
+  return s;
+}
+
+// Copy the rows of map mm within p.win_rows of the robot's row (clamped to
+// the map's rows -1..H), with the word in front of the first, into the env's
+// LDS buffer `buf`, by the env's own L lanes (one wave, so no workgroup
+// barrier: the wave's LDS writes are done before its later LDS reads). The
+// copy starts at the 16-byte boundary at or below that word; packed maps are
+// 16-byte padded, so it never reads past the map.
+template <int L>
+__device__ __forceinline__ Slot stage_window(const Params& p, const Lanes<L>& ln,
+                                             const MapMeta& mm, uint32_t* buf, float y) {
+  const int n = mm.wpr;
+  const int cy = med3i(cvt_flr(y), -1, mm.H);
+  const int y_lo = max(-1, cy - p.win_rows), y_hi = min(mm.H, cy + p.win_rows);
+  const uint32_t ws = mm.off + (uint32_t)((y_lo + 1) * n);  // the word in front of row y_lo
+  const uint32_t we = mm.off + 1u + (uint32_t)((y_hi + 2) * n);
+  const uint32_t ws4 = ws & ~3u;
+  const int n4 = (int)((we - ws4 + 3u) >> 2);
+  const uint4* src = reinterpret_cast<const uint4*>(p.words + ws4);
+  uint4* dst = reinterpret_cast<uint4*>(buf);
+  int k = ln.q;
+  for (; k + 3 * L < n4; k += 4 * L) {
+    uint4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[k + u * L];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) dst[k + u * L] = v[u];
+  }
+  for (; k < n4; k += L) dst[k] = src[k];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  Slot s;
+  s.w1 = buf + (int)(ws - ws4) + 1 - y_lo * n;
+  s.W = mm.W;
+  s.H = mm.H;
+  s.wpr = n;
+  s.wlo = y_lo * n - 1;
+  s.whi = (y_hi + 1) * n - 1;
+  return s;
 }
 
 }  // namespace sp

@@ -167,3 +167,60 @@ def test_set_state_roundtrip_and_errors(torch_gpu):
         env.set_qnet((36, 256, 256, 7), np.zeros(100, np.uint16), np.zeros(519, np.float32),
                      np.zeros(5, np.float32))
     assert env.status() == 0
+
+
+def test_windowed_step_extreme_poses(torch_gpu):
+    """The plain step stages only the map rows within range of the robot.
+    Poses at the map's edges, far outside it (the staged rows are clamped to
+    the map's) and with the range reaching past both ends, on 512-row maps
+    with range 128 and on maps shorter than the window; terminal
+    observations at those poses and the steps after the AutoReset against
+    the oracle."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    rng = np.random.default_rng(17)
+    grids = []
+    for H, W in ((512, 512), (300, 40), (200, 512)):
+        g = (rng.random((H, W)) < 0.02).astype(np.uint8)
+        grids.append(g)
+    maps = inputs.single_maps(grids, env_to_map=[0, 0, 0, 0, 0, 0, 1, 1, 2, 2, 0, 2])
+    cfg = inputs.workload("c3", n_envs=12, label="window")
+    banner("windowed step: edge and outside poses, 512 rows, range 128")
+    for variant in ((1, 64), (4, 32), (8, 16)):
+        env = sparrow.Env(cfg, maps)
+        env.set_variant(0, *variant)
+        orc = oracle.Oracle(cfg, maps)
+        env.reset()
+        orc.reset()
+        f, iv = orc.get_state()
+        # x, y: inside near each edge, far outside, and mid-map
+        poses = [(256.5, 0.2), (256.5, 511.9), (3.5, 140.0), (508.5, 300.0), (256.5, -40.0),
+                 (256.5, 700.0), (-25.0, 256.0), (20.5, 300.3), (100.0, 100.0), (300.0, 199.5),
+                 (256.0, 256.0), (-1e4, -1e4)]
+        for k, (x, y) in enumerate(poses):
+            f[k, 0], f[k, 1] = x, y
+        env.set_state(f, iv)
+        orc.set_state(f, iv)
+        fo = torch.zeros(env.n, env.obs_dim, dtype=torch.float32, device=env.device)
+        flags = torch.zeros(env.n, dtype=torch.uint8, device=env.device)
+        for s in range(6):
+            a = env.random_actions()
+            fo.zero_()
+            env.step(a, flags=flags, final_obs=fo)
+            r = orc.step(orc.uniform_actions(), final_obs=True, hit_k=True)
+            w = f"window {variant} step {s}"
+            compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", w)
+            compare_exact(to_np(env.done), r["done"], "done", w)
+            compare_exact(to_np(flags), r["flags"], "flags", w)
+            compare_exact(to_np(env.reward), r["reward"], "reward", w)
+            compare_obs(to_np(env.obs), r["obs"], cfg["n_rays"], True, w)
+            dn = r["done"].astype(bool)
+            if dn.any():
+                compare_obs(to_np(fo)[dn], r["final_obs"][dn], cfg["n_rays"], True, w + " final")
+            if s == 0:  # the outside poses collide at once
+                assert dn[[4, 5, 6, 11]].all(), w
+        gf, gi = env.get_state()
+        of, oi = orc.get_state()
+        compare_state(gf, gi, of, oi, f"window {variant} final")
+        assert env.status() == orc.status
