@@ -52,8 +52,9 @@ MI355X_BF16_TFLOPS = 2500.0
 ALG_OPS_PER_SAMPLE = 13
 ALG_OPS_PER_RAY = 110
 ALG_OPS_PER_ENV = 707
-# HBM bytes of one plain step of one env: its packed map (staged into LDS
-# every step) + SoA state read and written (15 x 4 B x 2) + action (4) +
+# HBM bytes of one plain step of one env: the rows of its packed map within
+# range of the robot (staged into LDS every step) + SoA state read and
+# written (15 x 4 B x 2) + action (4) +
 # obs and the library's copy (2 x 4 x obs_dim) + reward (4) + done (1) +
 # per-ray hit indices (2 x n_rays)
 
@@ -232,7 +233,9 @@ def collection_c5(cfg, maps, steps, warmup):
     phase = {k: float(np.mean([m[i].elapsed_time(m[i + 1]) for m in evs])) for i, k in
              enumerate(names)}
     mlp_flops = 2.0 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3])
-    map_bytes = env_map_bytes(maps)
+    # the plain step stages the rows within range of each robot (taken at
+    # the loop's final state)
+    map_bytes = env_window_bytes(maps, cfg, env.get_state()[0][:, 1])
     step_bytes = map_bytes + N * (15 * 4 * 2 + 4 + 4 * D * 2 + 4 + 1 + 2 * nr)
     add_bytes = N * (3 * 4 * D + 4 + 4 + 1) + N * (2 * nr + 2 * 8 + 1 + 4)
     return {
@@ -400,6 +403,21 @@ def env_map_bytes(maps):
         H, W = g.shape
         words = 1 + ((W + 2 + 31) // 32) * (H + 2)
         tot += ((words + 3) // 4) * 16
+    return tot
+
+
+def env_window_bytes(maps, cfg, y):
+    """Bytes the windowed step stages for envs whose robots are at rows y
+    (float array [N]): the rows within ceil(max(range, r)) + 2 of the
+    robot's row, clipped to the map's rows -1..H, plus the word in front."""
+    win = math.ceil(max(cfg["range"], cfg["robot_r"])) + 2
+    tot = 0
+    for e, m in enumerate(maps.env_to_map):
+        H, W = maps.grids[m].shape
+        wpr = (W + 2 + 31) // 32
+        cy = min(max(math.floor(float(y[e])), -1), H)
+        rows = min(H, cy + win) - max(-1, cy - win) + 1
+        tot += 4 * (rows * wpr + 1)
     return tot
 
 
@@ -614,13 +632,17 @@ def main():
                 "lds_frac": round(lds_gbs / MI355X_LDS_GBS, 5),
                 "hbm_frac": round(hbm_gbs / MI355X_HBM_GBS, 5),
                 "mfma_frac": round(mlp_flops * N * K / avg_launch_s / 1e12 / MI355X_BF16_TFLOPS, 5)}
-    step_bytes = env_map_bytes(maps) + N * (15 * 4 * 2 + 4 + 4 * D * 2 + 4 + 1 + 2 * nr)
+    win_bytes = env_window_bytes(maps, cfg, env.get_state()[0][:, 1])
+    step_bytes = win_bytes + N * (15 * 4 * 2 + 4 + 4 * D * 2 + 4 + 1 + 2 * nr)
     plain_hbm = step_bytes * P / (plain_ms / 1e3) / 1e9
     plain_roofline = {"bound": "hbm", "achieved": round(plain_hbm, 1), "peak": MI355X_HBM_GBS,
                       "unit": "GB/s", "frac": round(plain_hbm / MI355X_HBM_GBS, 4),
                       "traffic": counter_traffic("traffic_bytes_per_launch_k_step"),
                       "traffic_alg_bytes": int(step_bytes),
-                      "kernel": "k_step (one launch per step) + k_actions"}
+                      "kernel": "k_step (one launch per step, map rows within range "
+                                "staged) + k_actions",
+                      "staged_map_bytes_per_step": int(win_bytes),
+                      "whole_map_bytes": int(env_map_bytes(maps))}
 
     cpu = None
     precision = None
