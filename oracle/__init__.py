@@ -62,6 +62,18 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class _Task(C.Structure):
+    _fields_ = [("n_actions", C.c_int32), ("reward", C.c_int32), ("state", C.c_int32),
+                ("arrive_reward", C.c_float), ("collide_reward", C.c_float),
+                ("plan_dist", C.c_float), ("near_dist", C.c_float), ("w_d1", C.c_float),
+                ("w_d2", C.c_float), ("w_v", C.c_float), ("w_alpha", C.c_float),
+                ("w_d", C.c_float)]
+
+
+REWARD_PROGRESS, REWARD_EQ11 = 0, 1
+STATE_TARGET, STATE_RELATIVE = 0, 1
+
+
 class LearnerConfig(C.Structure):
     _fields_ = [("gamma", C.c_double), ("lr", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("adam_eps", C.c_double), ("huber_k", C.c_double),
@@ -103,6 +115,10 @@ def lib():
         L.orc_philox_batch.argtypes = [C.c_int32, P, P, P]
         L.orc_collides.argtypes = [P, C.c_int32, C.c_float, C.c_float]
         L.orc_collides.restype = C.c_int32
+        L.orc_near.argtypes = [P, C.c_int32, C.c_float, C.c_float]
+        L.orc_near.restype = C.c_int32
+        L.orc_set_task.argtypes = [P, C.POINTER(_Task)]
+        L.orc_set_task.restype = C.c_int32
         L.orc_march.argtypes = [P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]
         L.orc_march.restype = C.c_int32
         L.orc_ray_table.argtypes = [P, P, P]
@@ -244,6 +260,7 @@ class Oracle:
             raise ValueError("oracle rejected the configuration")
         self.n = c.n_envs
         self.obs_dim = c.n_rays + 4
+        self.n_actions = N_ACTIONS
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -318,6 +335,21 @@ class Oracle:
 
     def collides(self, m, px, py):
         return bool(lib().orc_collides(self._h, m, C.c_float(px), C.c_float(py)))
+
+    def near(self, m, px, py):
+        return bool(lib().orc_near(self._h, m, C.c_float(px), C.c_float(py)))
+
+    def set_task(self, n_actions=7, reward=REWARD_PROGRESS, state=STATE_TARGET,
+                 arrive_reward=10.0, collide_reward=-10.0, plan_dist=1.0, near_dist=0.0,
+                 weights=(0.3, 0.1, 0.3, 0.3, 0.1)):
+        """Task variant (Sec. 4.3.1): 5 or 7 actions, progress or Eq. (11)
+        reward, target or relative-pose state (see the C header)."""
+        t = _Task(n_actions, reward, state, arrive_reward, collide_reward, plan_dist, near_dist,
+                  *weights)
+        if lib().orc_set_task(self._h, C.byref(t)) != 0:
+            raise ValueError("oracle rejected the task")
+        self.n_actions = n_actions
+        self.obs_dim = lib().orc_obs_dim(self._h)
 
     def march(self, m, x, y, ux, uy):
         return int(lib().orc_march(self._h, m, C.c_float(x), C.c_float(y), C.c_float(ux),

@@ -25,6 +25,10 @@ static const float TWO_M24 = 5.9604644775390625e-08f; /* 2^-24 */
  * 2 and 4 add half turns). Entries: (A_v, A_w). */
 static const float ACT_V[7] = {0.02f, 1.0f, 1.0f, 1.0f, 1.0f, 1.0f, 0.02f};
 static const float ACT_W[7] = {1.0f, 1.0f, 0.5f, 0.0f, -0.5f, -1.0f, -1.0f};
+/* The five actions of Sec. 4.3.1 in the order listed there (turn left, go
+ * straight and turn left, go straight, go straight and turn right, turn
+ * right) as rows of the table above. */
+static const int32_t FIVE_ACTIONS[5] = {0, 1, 3, 5, 6};
 
 struct orc_env {
   orc_config cfg;
@@ -37,6 +41,9 @@ struct orc_env {
   float *ray_c, *ray_s; /* cos / sin of each ray's offset from forward */
   int32_t M;            /* samples k = 0..M */
   float inv_R;
+  orc_task task;
+  float inv_D;          /* 1 / plan_dist, rounded once */
+  float near_r;         /* robot_r + near_dist (binary32 sum) */
   uint32_t g;           /* global step counter */
   int32_t status;
   /* state */
@@ -145,8 +152,7 @@ static int occupied(const orc_env *e, int32_t m, int32_t ix, int32_t iy) {
  * cell square [i, i+1] x [j, j+1] that meets the disk's bounding box
  * [x - r, x + r] (closed: i from ceil(x - r) - 1 to floor(x + r)); touching
  * (distance <= r) collides. */
-int32_t orc_collides(const orc_env *e, int32_t m, float px, float py) {
-  const float r = e->cfg.robot_r;
+static int32_t disk_hits(const orc_env *e, int32_t m, float px, float py, float r) {
   const float r2 = r * r;
   int32_t i0 = (int32_t)ceilf(px - r) - 1, i1 = (int32_t)floorf(px + r);
   int32_t j0 = (int32_t)ceilf(py - r) - 1, j1 = (int32_t)floorf(py + r);
@@ -161,6 +167,14 @@ int32_t orc_collides(const orc_env *e, int32_t m, float px, float py) {
     }
   }
   return 0;
+}
+
+int32_t orc_collides(const orc_env *e, int32_t m, float px, float py) {
+  return disk_hits(e, m, px, py, e->cfg.robot_r);
+}
+
+int32_t orc_near(const orc_env *e, int32_t m, float px, float py) {
+  return disk_hits(e, m, px, py, e->near_r);
 }
 
 /* LiDAR ray (Sec. 3.2 ray casting on the grid): samples at t_k = k * ds for
@@ -238,7 +252,21 @@ orc_env *orc_create(const orc_config *cfg, int32_t n_maps, const uint8_t *cells,
   int32_t **is[] = {&e->t, &e->delay, &e->q0, &e->q1};
   for (size_t f = 0; f < sizeof(is) / sizeof(is[0]); ++f)
     *is[f] = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+  orc_task t = {ORC_NACT, ORC_REWARD_PROGRESS, ORC_STATE_TARGET, 10.0f, -10.0f, 1.0f, 0.0f,
+                0.3f, 0.1f, 0.3f, 0.3f, 0.1f};
+  orc_set_task(e, &t);
   return e;
+}
+
+int32_t orc_set_task(orc_env *e, const orc_task *t) {
+  if (!e || !t) return ORC_EINVAL;
+  if ((t->n_actions != 5 && t->n_actions != 7) || t->reward < 0 || t->reward > 1 ||
+      t->state < 0 || t->state > 1 || !(t->plan_dist > 0.0f) || !(t->near_dist >= 0.0f))
+    return ORC_EINVAL;
+  e->task = *t;
+  e->inv_D = (float)(1.0 / (double)t->plan_dist);
+  e->near_r = e->cfg.robot_r + t->near_dist;
+  return ORC_OK;
 }
 
 void orc_destroy(orc_env *e) {
@@ -255,7 +283,7 @@ void orc_destroy(orc_env *e) {
 int32_t orc_status(const orc_env *e) { return e->status; }
 uint32_t orc_global_step(const orc_env *e) { return e->g; }
 void orc_set_global_step(orc_env *e, uint32_t g) { e->g = g; }
-int32_t orc_obs_dim(const orc_env *e) { return e->cfg.n_rays + 4; }
+int32_t orc_obs_dim(const orc_env *e) { return e->cfg.n_rays + 4 + e->task.state; }
 void orc_advance(orc_env *e) { e->g += 1u; }
 
 void orc_get_state(const orc_env *e, float *f, int32_t *iv) {
@@ -382,14 +410,26 @@ static void observe(const orc_env *e, int32_t i, uint32_t noise_purpose, float *
     dn = fminf(fmaxf(dn, 0.0f), c->range);
     o[j] = dn * e->inv_R;
   }
-  o[nr] = e->vl[i] / e->vmax[i];
-  o[nr + 1] = e->va[i] / c->omega_max;
   float dx = e->tx[i] - e->x[i], dy = e->ty[i] - e->y[i];
-  float d2 = dx * dx + dy * dy;
-  o[nr + 2] = sqrtf(d2) * e->inv_dn[m];
   float bx = dx * fx + dy * fy; /* target in the robot frame */
   float by = dy * fx - dx * fy;
-  o[nr + 3] = (float)(atan2((double)by, (double)bx) / PI_D);
+  float bearing = (float)(atan2((double)by, (double)bx) / PI_D);
+  if (e->task.state == ORC_STATE_TARGET) {
+    o[nr] = e->vl[i] / e->vmax[i];
+    o[nr + 1] = e->va[i] / c->omega_max;
+    float d2 = dx * dx + dy * dy;
+    o[nr + 2] = sqrtf(d2) * e->inv_dn[m];
+    o[nr + 3] = bearing;
+  } else {
+    /* Sec. 4.3.1 relative pose: the robot's position relative to the target
+     * over the planning distance D, its orientation relative to the
+     * direction of the target (alpha / pi), then the two velocities */
+    o[nr] = (e->x[i] - e->tx[i]) * e->inv_D;
+    o[nr + 1] = (e->y[i] - e->ty[i]) * e->inv_D;
+    o[nr + 2] = bearing;
+    o[nr + 3] = e->vl[i] / e->vmax[i];
+    o[nr + 4] = e->va[i] / c->omega_max;
+  }
 }
 
 int32_t orc_reset(orc_env *e, float *obs, int16_t *hit_k) {
@@ -411,6 +451,41 @@ static double rel_err(double a, double b, double scale) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Eq. (11) of Sec. 4.3.1 for a step that did not end the episode, at the    */
+/* post-step pose:                                                           */
+/*   r = w_d1 r_d1 + w_d2 r_d2 + w_v r_v + w_alpha r_alpha + w_d r_d         */
+/* r_d1 = max(1 - d1 / D, 0), r_d2 = max(1 - d2 / D, 0) with d1 = |x - tx|,  */
+/* d2 = |y - ty| (largest value 1, falling with the distance);               */
+/* r_v = 1 if v_l > v_max / 2, else 0; r_alpha = 1 - |alpha| / pi, alpha the */
+/* orientation relative to the direction of the target; r_d = -1 if an       */
+/* occupied cell lies within near_dist of the robot's edge (within           */
+/* robot_r + near_dist of its centre, touching included), else 0. Binary32   */
+/* in this order; alpha / pi as in the observation (FP64, rounded once).     */
+/* ------------------------------------------------------------------------ */
+static float eq11_reward(const orc_env *e, int32_t i, int32_t m) {
+  const orc_task *t = &e->task;
+  const float x = e->x[i], y = e->y[i];
+  const float d1 = fabsf(x - e->tx[i]), d2 = fabsf(y - e->ty[i]);
+  const float rd1 = fmaxf(1.0f - d1 * e->inv_D, 0.0f);
+  const float rd2 = fmaxf(1.0f - d2 * e->inv_D, 0.0f);
+  const float rv = e->vl[i] > 0.5f * e->vmax[i] ? 1.0f : 0.0f;
+  float s, co;
+  orc_sincos_f32(e->phi[i], &s, &co);
+  const float fx = -co, fy = -s;
+  const float dx = e->tx[i] - x, dy = e->ty[i] - y;
+  const float bx = dx * fx + dy * fy, by = dy * fx - dx * fy;
+  const float alpha = (float)(atan2((double)by, (double)bx) / PI_D);
+  const float ra = 1.0f - fabsf(alpha);
+  const float rd = orc_near(e, m, x, y) ? -1.0f : 0.0f;
+  float r = t->w_d1 * rd1;
+  r = r + t->w_d2 * rd2;
+  r = r + t->w_v * rv;
+  r = r + t->w_alpha * ra;
+  r = r + t->w_d * rd;
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One step of env i (Alg. 1 step 4: s', r, done = envs.step(a_hat)).        */
 /* ------------------------------------------------------------------------ */
 static int32_t step_env(orc_env *e, int32_t i, int32_t a_hat, float *o, float *reward,
@@ -418,7 +493,8 @@ static int32_t step_env(orc_env *e, int32_t i, int32_t a_hat, float *o, float *r
                         orc_stats *st) {
   const orc_config *c = &e->cfg;
   const int32_t m = e->env_map[i];
-  if (a_hat < 0 || a_hat >= ORC_NACT) a_hat = ORC_STOP;
+  if (a_hat < 0 || a_hat >= e->task.n_actions) a_hat = ORC_STOP;
+  else if (e->task.n_actions == 5) a_hat = FIVE_ACTIONS[a_hat];
   /* control delay: a FIFO of depth 0..2 holding not-yet-applied actions */
   int32_t a;
   if (e->delay[i] == 0) {
@@ -502,15 +578,18 @@ static int32_t step_env(orc_env *e, int32_t i, int32_t a_hat, float *o, float *r
   int32_t term = 0;
   float r;
   if (coll) {
-    r = -10.0f;
+    r = e->task.collide_reward;
     term = 1;
   } else if (arrived) {
-    r = 10.0f;
+    r = e->task.arrive_reward;
     term = 1;
-  } else {
+  } else if (e->task.reward == ORC_REWARD_PROGRESS) {
     float dist = sqrtf(d2);
     r = (e->dprev[i] - dist) - 0.01f;
     e->dprev[i] = dist;
+  } else {
+    r = eq11_reward(e, i, m);
+    e->dprev[i] = sqrtf(d2);
   }
   int32_t trunc = !term && e->t[i] >= c->t_max;
   int32_t dn = term || trunc;
@@ -627,7 +706,7 @@ void orc_uniform_actions(const orc_env *e, int32_t *actions) {
   for (int32_t i = 0; i < e->cfg.n_envs; ++i) {
     uint32_t w[4];
     draw(e, (uint32_t)i, ORC_P_ACTION_UNIFORM, 0, w);
-    actions[i] = scale_u32(w[0], ORC_NACT);
+    actions[i] = scale_u32(w[0], (uint32_t)e->task.n_actions);
   }
 }
 

@@ -80,6 +80,34 @@ uint32_t orc_global_step(const orc_env *e);
 void orc_set_global_step(orc_env *e, uint32_t g);
 int32_t orc_obs_dim(const orc_env *e);
 
+/* Task variant (Sec. 4.3.1). The default task is the workloads': 7 actions,
+ * the progress reward (previous minus current distance to the target, minus
+ * 0.01) with terminal -10 / +10, and the target state [ranges | v_l/v_max,
+ * v_a/omega_max, distance/(sqrt 2 max(W, H)), bearing/pi]. The paper's own
+ * formulation changes three things, selectable apart:
+ *   n_actions = 5: the five actions it lists, rows {0,1,3,5,6} of the table;
+ *   reward = ORC_REWARD_EQ11: Eq. (11) on steps that do not end the episode
+ *     (see eq11_reward in the source for the reading of its terms), with
+ *     the terminal rewards arrive_reward (+75 there) / collide_reward (-10);
+ *   state = ORC_STATE_RELATIVE: [ranges | (x - tx)/D, (y - ty)/D, alpha/pi,
+ *     v_l/v_max, v_a/omega_max], n_rays + 5 entries (27 + 5 = 32 there).
+ * D = plan_dist (cells); near_dist (cells) is the r_d margin around the
+ * robot's edge; w_* the Eq. (11) weights (0.3 0.1 0.3 0.3 0.1). Parity
+ * against the paper is unpinned for this variant: the shapes of r_d1, r_d2
+ * and r_alpha and the cell size are not stated. Returns ORC_EINVAL for
+ * n_actions other than 5 or 7, unknown modes, plan_dist <= 0 or
+ * near_dist < 0. orc_obs_dim follows the state. */
+enum { ORC_REWARD_PROGRESS = 0, ORC_REWARD_EQ11 = 1 };
+enum { ORC_STATE_TARGET = 0, ORC_STATE_RELATIVE = 1 };
+typedef struct {
+  int32_t n_actions, reward, state;
+  float arrive_reward, collide_reward, plan_dist, near_dist;
+  float w_d1, w_d2, w_v, w_alpha, w_d;
+} orc_task;
+int32_t orc_set_task(orc_env *e, const orc_task *t);
+/* Disk test with radius robot_r + near_dist (the r_d term of Eq. (11)). */
+int32_t orc_near(const orc_env *e, int32_t map, float px, float py);
+
 /* Reset every env (draws use the current global step), write obs, advance. */
 int32_t orc_reset(orc_env *e, float *obs, int16_t *hit_k);
 

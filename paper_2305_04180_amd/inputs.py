@@ -56,8 +56,17 @@ WORKLOADS = {
     # the headline workload: c2 physics driven by c4's actor
     "m": dict(_COMMON, **_DR_FULL, n_envs=4096, sides=(366,), style="mixed", n_rays=32,
               range=100.0, steps=10000, qnet=(36, 256, 256, 7), eps=(0.01, 0.3)),
+    # the paper's own task (Sec. 4.3.1/4.3.2) on c2's maps and physics: 27 rays,
+    # 5 actions, Eq. (11) reward with +75 / -10, the 32-entry relative-pose
+    # state and the 32-256-128-5 network. Cell size read as 2 cm: the 30 cm
+    # margin of r_d is 15 cells; the planning distance D is 100 cells.
+    "p": dict(_COMMON, **_DR_FULL, n_envs=4096, sides=(366,), style="mixed", n_rays=27,
+              range=100.0, steps=2048, qnet=(32, 256, 128, 5), eps=(0.01, 0.3),
+              task=dict(n_actions=5, reward=1, state=1, arrive_reward=75.0,
+                        collide_reward=-10.0, plan_dist=100.0, near_dist=15.0,
+                        weights=(0.3, 0.1, 0.3, 0.3, 0.1))),
 }
-WORKLOAD_IDS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "m": 2}
+WORKLOAD_IDS = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "m": 2, "p": 2}
 
 
 def workload(name: str, **overrides) -> dict:
