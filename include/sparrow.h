@@ -116,12 +116,13 @@ int sparrow_create(const sparrow_config *cfg, const sparrow_maps *maps, void *hi
 int sparrow_reset(sparrow_env *env, float *obs);
 
 /* One vectorized step (Alg. 1 step 4: s', r, done = envs.step(a_hat)).
- * actions: dev [N] (values outside [0, 7) act as "stop"). Writes obs, reward,
- * done, and optionally flags (dev [N]) and final_obs (dev [N][n_rays+4], the
- * observation at the terminal pose of envs that are done; rows of other envs
- * are left untouched). Envs that are done are reset inside the step and obs
- * holds their first observation of the next episode (AutoReset, Sec. 3.2.5).
- * Advances the global step by one. */
+ * actions: dev [N] (values outside [0, n_actions) act as "stop"). Writes obs
+ * (dev [N][obs_dim]), reward, done, and optionally flags (dev [N]) and
+ * final_obs (dev [N][obs_dim], the observation at the terminal pose of envs
+ * that are done; rows of other envs are left untouched). Envs that are done
+ * are reset inside the step and obs holds their first observation of the
+ * next episode (AutoReset, Sec. 3.2.5). EINVAL before the first reset (or
+ * set_state) and after a task change. Advances the global step by one. */
 int sparrow_step(sparrow_env *env, const int32_t *actions, float *obs, float *reward,
                  uint8_t *done, uint8_t *flags, float *final_obs);
 
@@ -129,16 +130,64 @@ int sparrow_step(sparrow_env *env, const int32_t *actions, float *obs, float *re
  * draws a rollout with use_qnet = 0 makes. Does not advance the step. */
 int sparrow_random_actions(sparrow_env *env, int32_t *actions);
 
-/* Install the actor: Q-network dims[4] = {obs_dim, h1, h2, 7} (host), with
- * obs_dim = n_rays + 4 <= 96 and h1 = h2 in {256, 512}. Width 256 keeps the
- * weights resident in registers and drives the fused rollout; width 512
- * streams them from L2 and serves sparrow_act and sparrow_qnet_forward only
- * (a rollout with use_qnet = 1 returns EUNSUPPORTED). Other shapes return
- * EUNSUPPORTED. w_bf16: dev, bf16 bit patterns, [W1 (h1 x obs_dim) |
- * W2 (h2 x h1) | W3 (7 x h2)], each row-major [out][in] (Sec. 4.3.2 fully
- * connected layers with ReLU). b_f32: dev [h1 + h2 + 7]. eps: dev [N]
- * per-env exploration probability of VEM (Sec. 3.1.1). All three are
- * copied. */
+/* ---- Task (Sec. 4.3.1) -------------------------------------------------------
+ * The default task is the workloads': 7 actions (the table in the design
+ * notes), the progress reward (previous minus current distance to the
+ * target, minus 0.01) with terminal -10 on collision / +10 on arrival, and
+ * the target state [ranges | v_l/v_max, v_a/omega_max, distance/(sqrt 2
+ * max(W, H)), bearing/pi] of n_rays + 4 entries. The paper's own task
+ * differs in three places, each selectable:
+ *   n_actions = 5: the five actions Sec. 4.3.1 lists (turn left, straight
+ *     and left, straight, straight and right, turn right), rows 0, 1, 3, 5,
+ *     6 of the 7-row table; ids >= n_actions act as stop.
+ *   reward = SPARROW_REWARD_EQ11: terminal collide_reward / arrive_reward
+ *     (-10 / +75 there); otherwise Eq. (11), r = w_d1 r_d1 + w_d2 r_d2 +
+ *     w_v r_v + w_alpha r_alpha + w_d r_d in binary32 in this order, with
+ *     r_d1 = max(1 - |x - tx| / D, 0), r_d2 = max(1 - |y - ty| / D, 0),
+ *     r_v = 1 if v_l > v_max / 2 else 0, r_alpha = 1 - |alpha| / pi (alpha:
+ *     heading relative to the direction of the target), r_d = -1 if an
+ *     occupied cell lies within near_dist of the robot's edge (touching
+ *     included) else 0; D = plan_dist. The paper leaves the shapes of r_d1,
+ *     r_d2 and r_alpha open: these are readings.
+ *   state = SPARROW_STATE_RELATIVE: [ranges | (x - tx)/D, (y - ty)/D,
+ *     alpha/pi, v_l/v_max, v_a/omega_max], n_rays + 5 entries (32 with the
+ *     paper's 27 rays).
+ * Setting a task synchronises the stream, drops the installed Q-network
+ * (its sizes follow the task) and requires a reset before the next step.
+ * EINVAL for n_actions other than 5 or 7, unknown modes, plan_dist <= 0 or
+ * near_dist outside [0, 64]. The collecting rollout runs the default task
+ * only (EUNSUPPORTED otherwise). */
+#define SPARROW_REWARD_PROGRESS 0
+#define SPARROW_REWARD_EQ11 1
+#define SPARROW_STATE_TARGET 0
+#define SPARROW_STATE_RELATIVE 1
+typedef struct {
+  int32_t n_actions;   /* 7 or 5 */
+  int32_t reward;      /* SPARROW_REWARD_* */
+  int32_t state;       /* SPARROW_STATE_* */
+  float arrive_reward; /* terminal reward on arrival */
+  float collide_reward;/* terminal reward on collision */
+  float plan_dist;     /* D, cells */
+  float near_dist;     /* r_d margin around the robot's edge, cells */
+  float w_d1, w_d2, w_v, w_alpha, w_d; /* Eq. (11) weights (0.3 0.1 0.3 0.3 0.1) */
+} sparrow_task;
+int sparrow_set_task(sparrow_env *env, const sparrow_task *task);
+/* Entries of one observation row under the current task (n_rays + 4 or
+ * n_rays + 5); -1 for NULL. */
+int32_t sparrow_obs_dim(const sparrow_env *env);
+
+/* Install the actor: Q-network dims[4] = {obs_dim, h1, h2, A} (host), with
+ * obs_dim = sparrow_obs_dim(env) and A the task's n_actions (EINVAL
+ * otherwise). Shapes: h1 = h2 = 256 with obs_dim <= 96, or h1 = 256, h2 =
+ * 128 with obs_dim <= 64 (the [32, 256, 128, 5] network of Sec. 4.3.2):
+ * weights resident in registers, drives the fused rollout; h1 = h2 = 512
+ * with obs_dim <= 96: weights streamed from L2, serves sparrow_act and
+ * sparrow_qnet_forward only (a rollout with use_qnet = 1 returns
+ * EUNSUPPORTED). Other shapes return EUNSUPPORTED. w_bf16: dev, bf16 bit
+ * patterns, [W1 (h1 x obs_dim) | W2 (h2 x h1) | W3 (A x h2)], each row-major
+ * [out][in] (Sec. 4.3.2 fully connected layers with ReLU). b_f32: dev
+ * [h1 + h2 + A]. eps: dev [N] per-env exploration probability of VEM
+ * (Sec. 3.1.1). All three are copied. */
 int sparrow_set_qnet(sparrow_env *env, const int32_t *dims, const uint16_t *w_bf16,
                      const float *b_f32, const float *eps);
 
@@ -157,7 +206,7 @@ int sparrow_set_vem_schedule(sparrow_env *env, double e_min, double e_max, int32
                              int32_t or_final, int64_t decay_transitions);
 
 /* Q-network forward on given observations (dev obs [n][obs_dim] -> dev q
- * [n][7] FP32, dev greedy [n] int32 = lowest argmax). Same MFMA code as the
+ * [n][A] FP32, dev greedy [n] int32 = lowest argmax). Same MFMA code as the
  * fused actor: the observation is rounded to bf16 (RNE), layers accumulate in
  * FP32, hidden activations are stored as bf16. Either output may be NULL. */
 int sparrow_qnet_forward(sparrow_env *env, const float *obs, int32_t n, float *q,

@@ -2,9 +2,9 @@
 //
 // Kernels:
 //   k_pack      uint8 grids -> bit-packed rows with an occupied ring (LDS-ready)
-//   k_step<L>   one vectorized step (or reset) per launch; each workgroup
+//   k_step<L, TK> one vectorized step (or reset) per launch; each workgroup
 //               stages its group's maps into LDS, then every env runs on L lanes
-//   k_rollout<L, QNET, COLL>
+//   k_rollout<L, QNET, COLL, TK>
 //               persistent K-step rollout: maps staged once per group and kept
 //               in LDS for all K steps; actor = uniform draws or the BF16 MFMA
 //               Q-network + VEM (Alg. 1 steps 2-4 fused); COLL also adds each
@@ -64,11 +64,11 @@ __global__ void k_pack(const uint8_t* __restrict__ cells, const int64_t* __restr
 }
 
 __global__ void k_actions(int32_t n, uint32_t g, uint32_t key0, uint32_t key1,
-                          int32_t* __restrict__ actions) {
+                          int32_t n_actions, int32_t* __restrict__ actions) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const U4 w = philox((uint32_t)i, g, kActionUniform, 0u, key0, key1);
-  actions[i] = scale_u32(w.x, kNumActions);
+  actions[i] = scale_u32(w.x, (uint32_t)n_actions);
 }
 
 // Copy the group's maps into LDS (16-byte words; offsets are multiples of 4).
@@ -115,7 +115,7 @@ __device__ __forceinline__ int32_t ring_slot(const Params& p, int t, int i) {
 // within range of the robot (after the motion, or after the AutoReset), into
 // its own part of LDS with its own lanes: no workgroup barrier. The
 // AutoReset tests its candidates against the packed map in global memory.
-template <int L>
+template <int L, bool TK>
 __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   extern __shared__ uint32_t lds[];
   const int grp = blockIdx.x;
@@ -138,13 +138,13 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   Slot m{};
   bool reset_now = mode == 1;
   if (mode == 0) {
-    step_motion(p, e, p.actions[i]);
+    step_motion<TK>(p, e, p.actions[i]);
     m = stage_window<L>(p, ln, mm, buf, e.y);
-    o = step_outcome<L>(p, ln, m, e);
+    o = step_outcome<L, TK>(p, ln, m, e);
     reset_now = o.done != 0;
     if (reset_now && p.final_obs)
-      observe<L>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D, nullptr,
-                 nullptr, nullptr, false);
+      observe<L, TK>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D,
+                     nullptr, nullptr, nullptr, false);
   }
   bool free_pose = true;  // not done: the step's collision test passed
   if (reset_now) {
@@ -152,8 +152,8 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
     if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
     m = stage_window<L>(p, ln, mm, buf, e.y);
   }
-  observe<L>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
-             nullptr, free_pose);
+  observe<L, TK>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow, crow,
+                 hk, nullptr, free_pose);
   if (ln.q == 0) {
     store_env(p.s, i, e);
     if (mode == 0) {
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
 // observation (taken before the reset, with the step's own noise draws) when
 // ring_terminal is set, else the observation after the reset; the
 // observation after the step, reset or not, is also the next transition's s.
-template <int L, class QC, bool COLL>
+template <int L, class QC, bool COLL, bool TK>
 __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
   extern __shared__ uint32_t lds[];
   constexpr bool kQ = QC::kOn;
@@ -236,10 +236,11 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if (t % L == 0 && live) {
         const uint32_t gq = g + (uint32_t)ln.q;
         if constexpr (kQ) {
-          draws = vem_draw(i, gq, qp.vem.on ? vem_eps(qp.vem, i, gq) : eps, p.key0, p.key1);
+          draws = vem_draw(i, gq, qp.vem.on ? vem_eps(qp.vem, i, gq) : eps, p.key0, p.key1,
+                           TaskOf<TK>::n_actions(p));
         } else {
           const U4 w = philox((uint32_t)i, gq, kActionUniform, 0u, p.key0, p.key1);
-          draws = scale_u32(w.x, kNumActions);
+          draws = scale_u32(w.x, (uint32_t)TaskOf<TK>::n_actions(p));
         }
       }
       const int draw = __shfl(draws, (threadIdx.x & 63 & ~(L - 1)) + t % L);
@@ -249,13 +250,13 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
         // LDS reads run ahead of the MFMAs where the registers allow it
         const f32x4 tile = qnet_forward_group<QC, (L >= 32 ? 4 : 1)>(qp, qw, w3, lds, threadIdx.x);
         float qa[kNumActions];
-        const int greedy = qnet_q_values(qp, tile, slot & 15, qa);
+        const int greedy = qnet_q_values(qp, tile, slot & 15, qa, TaskOf<TK>::n_actions(p));
         if (live) a_hat = draw >= 0 ? draw : greedy;
       } else {
         a_hat = draw;
       }
       if (live) {
-        const StepOut o = step_env<L>(p, ln, m, e, a_hat);
+        const StepOut o = step_env<L, TK>(p, ln, m, e, a_hat);
         const bool last = t == p.K_steps - 1;
         float* orow = last ? p.obs + (size_t)i * D : nullptr;
         float* crow = (last || !kQ) ? p.cur_obs + (size_t)i * D : nullptr;
@@ -279,7 +280,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
               free_pose = reset_env<L>(p, ln, m, e, i, g);
               if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
             }
-            observe<L>(p, ln, rd, m, e, i, g, (terminal || !o.done) ? kNoise : kNoiseReset, inv_dn,
+            observe<L, TK>(p, ln, rd, m, e, i, g, (terminal || !o.done) ? kNoise : kNoiseReset,
+                           inv_dn,
                        terminal ? nullptr : orow, terminal ? nullptr : crow,
                        terminal ? nullptr : hk, terminal ? nullptr : act_in,
                        !terminal && free_pose,
@@ -296,8 +298,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
             free_pose = reset_env<L>(p, ln, m, e, i, g);
             if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
           }
-          observe<L>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise, inv_dn, orow, crow, hk,
-                     act_in, free_pose);
+          observe<L, TK>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise, inv_dn, orow, crow,
+                         hk, act_in, free_pose);
         }
         if (ln.q == 0) {
           const size_t o_idx = (size_t)t * N + i;
@@ -345,19 +347,21 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
     // wave 0 reports the 16 rows; lane r < 16 takes row r
     const int r = threadIdx.x & 15;
     float qa[kNumActions];
-    const int gi = qnet_q_values(qp, tile, r, qa);
+    const int gi = qnet_q_values(qp, tile, r, qa, qp.n_actions);
     if (threadIdx.x < kQRows && r0 + r < n) {
       const int row = r0 + r;
       if (q)
-        for (int a = 0; a < kNumActions; ++a) q[(size_t)row * kNumActions + a] = qa[a];
+        for (int a = 0; a < qp.n_actions; ++a) q[(size_t)row * qp.n_actions + a] = qa[a];
       if (greedy) greedy[row] = gi;
-      if (actions) actions[row] = vem_select(gi, row, g, actor_eps(qp, eps, row, g), key0, key1);
+      if (actions)
+        actions[row] = vem_select(gi, row, g, actor_eps(qp, eps, row, g), key0, key1, qp.n_actions);
     }
   }
 }
 
 using Q64 = QNetCfg<64, 256, 256>;
 using Q96 = QNetCfg<96, 256, 256>;
+using Q64N = QNetCfg<64, 256, 128>;  // the 32-256-128-5 network of Sec. 4.3.2
 
 // ===========================================================================
 // Host side
@@ -417,6 +421,9 @@ struct sparrow_env {
   int var_L[2] = {64, 64};
   std::map<std::tuple<int, int, bool>, Groups> groups;  // (epw, budget words, windowed)
   std::map<std::tuple<int, int, int, int>, GraphEntry> graphs;
+  // task (Sec. 4.3.1); the default is the workloads' task
+  sparrow_task task{SPARROW_N_ACTIONS, SPARROW_REWARD_PROGRESS, SPARROW_STATE_TARGET, 10.0f,
+                    -10.0f, 1.0f, 0.0f, 0.3f, 0.1f, 0.3f, 0.3f, 0.1f};
   // actor
   bool has_qnet = false;
   VemSchedule vem{};  // off until sparrow_set_vem_schedule
@@ -427,15 +434,18 @@ struct sparrow_env {
 
 namespace {
 
-int obs_dim(const sparrow_env* e) { return e->cfg.n_rays + 4; }
+int obs_dim(const sparrow_env* e) { return e->cfg.n_rays + 4 + e->task.state; }
 
 int words_of(const MapMeta& m) { return (1 + m.wpr * (m.H + 2) + 3) & ~3; }
 
 // Rows staged on each side of the robot's row by the windowed step: every
 // sample of a ray (distance <= range, |u| <= 1 up to rounding) and every
-// cell of the collision disk lies within ceil(max(range, r)) + 1 rows.
-int window_rows(const sparrow_config& c) {
-  return (int)std::ceil(std::max((double)c.range_cells, (double)c.robot_radius)) + 2;
+// cell of the collision disk (and of the Eq. (11) margin disk) lies within
+// ceil(max(range, disk radius)) + 1 rows.
+int window_rows(const sparrow_config& c, const sparrow_task& t) {
+  const double disk = (double)c.robot_radius +
+                      (t.reward == SPARROW_REWARD_EQ11 ? (double)t.near_dist : 0.0);
+  return (int)std::ceil(std::max((double)c.range_cells, disk)) + 2;
 }
 
 // LDS words of a windowed slot: at most 2 win + 1 rows (and at most the map's
@@ -450,7 +460,7 @@ int window_words_of(const MapMeta& m, int win) {
 // at most epw envs whose slots fit the LDS budget together. A slot holds the
 // whole packed map, or (windowed) the rows within range of the robot.
 int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out, bool windowed = false) {
-  const int win = window_rows(e->cfg);
+  const int win = window_rows(e->cfg, e->task);
   auto slot_words = [&](const MapMeta& m) { return windowed ? window_words_of(m, win) : words_of(m); };
   auto key = std::make_tuple(epw, budget_words, windowed);
   auto it = e->groups.find(key);
@@ -516,7 +526,20 @@ Params base_params(sparrow_env* e) {
   while (p.k_free <= p.M &&
          (double)p.k_free * c.march_step * (1.0 + 1e-6) + 1e-3 <= (double)c.robot_radius)
     ++p.k_free;
-  p.win_rows = window_rows(c);
+  p.win_rows = window_rows(c, e->task);
+  const sparrow_task& tk = e->task;
+  p.n_actions = tk.n_actions;
+  p.reward_mode = tk.reward;
+  p.state_mode = tk.state;
+  p.r_arrive = tk.arrive_reward;
+  p.r_collide = tk.collide_reward;
+  p.inv_D = (float)(1.0 / (double)tk.plan_dist);
+  p.near_r = c.robot_radius + tk.near_dist;
+  p.w_d1 = tk.w_d1;
+  p.w_d2 = tk.w_d2;
+  p.w_v = tk.w_v;
+  p.w_a = tk.w_alpha;
+  p.w_d = tk.w_d;
   p.t_max = c.timeout_steps;
   p.delay_lo = c.delay_lo;
   p.delay_hi = c.delay_hi;
@@ -549,15 +572,28 @@ Params base_params(sparrow_env* e) {
 
 int check_L(int L) { return L == 16 || L == 32 || L == 64; }
 
-template <int L>
-int launch_step_L(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
+// The default task runs kernels compiled for it (TK = false); any other task
+// runs the instantiations that read the task from the parameters.
+bool task_is_default(const sparrow_task& t) {
+  return t.n_actions == SPARROW_N_ACTIONS && t.reward == SPARROW_REWARD_PROGRESS &&
+         t.state == SPARROW_STATE_TARGET && t.arrive_reward == 10.0f && t.collide_reward == -10.0f;
+}
+
+template <int L, bool TK>
+int launch_step_LT(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
   const int threads = std::max(64, gr.epw * L);
   const size_t shmem = (size_t)gr.max_words * 4;
-  HIP_TRY(hipFuncSetAttribute((const void*)k_step<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shmem));
-  hipLaunchKernelGGL(k_step<L>, dim3(gr.G), dim3(threads), shmem, e->stream, p, mode);
+  HIP_TRY(hipFuncSetAttribute((const void*)k_step<L, TK>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  hipLaunchKernelGGL((k_step<L, TK>), dim3(gr.G), dim3(threads), shmem, e->stream, p, mode);
   HIP_TRY(hipGetLastError());
   return SPARROW_OK;
+}
+
+template <int L>
+int launch_step_L(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
+  return task_is_default(e->task) ? launch_step_LT<L, false>(e, p, gr, mode)
+                                  : launch_step_LT<L, true>(e, p, gr, mode);
 }
 
 int launch_step(sparrow_env* e, Params p, int mode, int epw, int L) {
@@ -577,33 +613,38 @@ int launch_step(sparrow_env* e, Params p, int mode, int epw, int L) {
 
 // 0: no actor network; 1, 2: width 256 (weights in registers), obs padded
 // to 64 or 96; 3, 4: width 512 (weights streamed from L2), obs padded to 64
-// or 96
+// or 96; 5: 256 then 128 (in registers), obs padded to 64
 int qnet_kind(const QParams& q) {
+  if (q.h1 == 256 && q.h2 == 128) return q.d0p == 64 ? 5 : -1;
   if (q.h1 != q.h2) return -1;
   if (q.h1 == 256) return q.d0p == 64 ? 1 : q.d0p == 96 ? 2 : -1;
   if (q.h1 == 512) return q.d0p == 64 ? 3 : q.d0p == 96 ? 4 : -1;
   return -1;
 }
-bool qnet_in_registers(int kind) { return kind == 1 || kind == 2; }
+bool qnet_in_registers(int kind) { return kind == 1 || kind == 2 || kind == 5; }
 
-template <int L, bool COLL>
+template <int L, bool COLL, bool TK>
 const void* rollout_fn_L(int kind) {
-  if (kind == 1) return (const void*)k_rollout<L, Q64, COLL>;
-  if (kind == 2) return (const void*)k_rollout<L, Q96, COLL>;
-  return (const void*)k_rollout<L, NoQ, COLL>;
+  if (kind == 1) return (const void*)k_rollout<L, Q64, COLL, TK>;
+  if (kind == 2) return (const void*)k_rollout<L, Q96, COLL, TK>;
+  if (kind == 5) return (const void*)k_rollout<L, Q64N, COLL, TK>;
+  return (const void*)k_rollout<L, NoQ, COLL, TK>;
 }
 
-template <bool COLL>
+template <bool COLL, bool TK>
 const void* rollout_kernel_c(int L, int kind) {
   switch (L) {
-    case 16: return rollout_fn_L<16, COLL>(kind);
-    case 32: return rollout_fn_L<32, COLL>(kind);
-    default: return rollout_fn_L<64, COLL>(kind);
+    case 16: return rollout_fn_L<16, COLL, TK>(kind);
+    case 32: return rollout_fn_L<32, COLL, TK>(kind);
+    default: return rollout_fn_L<64, COLL, TK>(kind);
   }
 }
 
-const void* rollout_kernel(int L, int kind, bool collect) {
-  return collect ? rollout_kernel_c<true>(L, kind) : rollout_kernel_c<false>(L, kind);
+// Collecting rollouts exist for the default task only (the launcher checks).
+const void* rollout_kernel(int L, int kind, bool collect, bool default_task) {
+  if (collect) return rollout_kernel_c<true, false>(L, kind);
+  return default_task ? rollout_kernel_c<false, false>(L, kind)
+                      : rollout_kernel_c<false, true>(L, kind);
 }
 
 const void* qnet_kernel(int kind) {
@@ -611,6 +652,7 @@ const void* qnet_kernel(int kind) {
     case 2: return (const void*)k_qnet<Q96>;
     case 3: return (const void*)k_mlp<64, 512>;
     case 4: return (const void*)k_mlp<96, 512>;
+    case 5: return (const void*)k_qnet<Q64N>;
     default: return (const void*)k_qnet<Q64>;
   }
 }
@@ -710,7 +752,8 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
   alloc((void**)&e->inv_dn, sizeof(float) * maps->n_maps);
   alloc((void**)&e->env_map, sizeof(int32_t) * N);
   alloc((void**)&e->rays, sizeof(float2) * c.n_rays);
-  alloc((void**)&e->cur_obs, sizeof(float) * (size_t)N * obs_dim(e));
+  // room for the larger of the two state layouts (n_rays + 5)
+  alloc((void**)&e->cur_obs, sizeof(float) * (size_t)N * (c.n_rays + 5));
   alloc((void**)&e->hit_k, sizeof(int16_t) * (size_t)N * c.n_rays);
   alloc((void**)&e->err, sizeof(int32_t));
   const size_t fbytes = sizeof(float) * (size_t)N;
@@ -751,7 +794,7 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
   CREATE_TRY(hipMemcpy(e->rays, rays.data(), sizeof(float2) * c.n_rays, hipMemcpyHostToDevice));
   CREATE_TRY(hipMemset(e->err, 0, sizeof(int32_t)));
   CREATE_TRY(hipMemset(e->state_block, 0, fbytes * 15));
-  CREATE_TRY(hipMemset(e->cur_obs, 0, sizeof(float) * (size_t)N * obs_dim(e)));
+  CREATE_TRY(hipMemset(e->cur_obs, 0, sizeof(float) * (size_t)N * (c.n_rays + 5)));
   CREATE_TRY(hipMemset(e->hit_k, 0, sizeof(int16_t) * (size_t)N * c.n_rays));
   {
     int max_words = 0;
@@ -800,6 +843,7 @@ int sparrow_reset(sparrow_env* e, float* obs) {
 int sparrow_step(sparrow_env* e, const int32_t* actions, float* obs, float* reward, uint8_t* done,
                  uint8_t* flags, float* final_obs) {
   if (!e || !actions || !obs || !reward || !done) return fail(SPARROW_EINVAL, "NULL argument");
+  if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before step");
   Params p = base_params(e);
   p.actions = actions;
   p.obs = obs;
@@ -817,7 +861,8 @@ int sparrow_random_actions(sparrow_env* e, int32_t* actions) {
   if (!e || !actions) return fail(SPARROW_EINVAL, "NULL argument");
   const int N = e->cfg.n_envs;
   hipLaunchKernelGGL(k_actions, dim3((N + 255) / 256), dim3(256), 0, e->stream, N, e->g,
-                     (uint32_t)e->cfg.seed, (uint32_t)(e->cfg.seed >> 32), actions);
+                     (uint32_t)e->cfg.seed, (uint32_t)(e->cfg.seed >> 32),
+                     (int32_t)e->task.n_actions, actions);
   HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
@@ -826,9 +871,14 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
                      const float* eps) {
   if (!e || !dims || !w_bf16 || !b_f32 || !eps) return fail(SPARROW_EINVAL, "NULL argument");
   const int d0 = dims[0], h1 = dims[1], h2 = dims[2], A = dims[3];
-  if (d0 != obs_dim(e) || A != SPARROW_N_ACTIONS) return fail(SPARROW_EINVAL, "qnet dims must be {n_rays + 4, h1, h2, 7}");
-  if (h1 != h2 || (h1 != 256 && h1 != 512) || d0 > 96)
-    return fail(SPARROW_EUNSUPPORTED, "the actor supports h1 = h2 in {256, 512} and obs_dim <= 96");
+  if (d0 != obs_dim(e) || A != e->task.n_actions)
+    return fail(SPARROW_EINVAL, "qnet dims must be {obs_dim, h1, h2, n_actions} of the task");
+  const bool wide_ok = h1 == h2 && (h1 == 256 || h1 == 512) && d0 <= 96;
+  const bool narrow_ok = h1 == 256 && h2 == 128 && d0 <= 64;
+  if (!wide_ok && !narrow_ok)
+    return fail(SPARROW_EUNSUPPORTED,
+                "the actor supports (h1, h2) = (256, 256) or (512, 512) with obs_dim <= 96, "
+                "and (256, 128) with obs_dim <= 64");
   if (e->q_block) {
     (void)hipFree(e->q_block);
     e->q_block = nullptr;
@@ -841,6 +891,7 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
   qp.d0 = d0;
   qp.h1 = h1;
   qp.h2 = h2;
+  qp.n_actions = A;
   qp.d0p = d0 <= 64 ? 64 : 96;
   const size_t w_elems = (size_t)h1 * d0 + (size_t)h2 * h1 + (size_t)A * h2;
   const size_t b_elems = (size_t)h1 + h2 + A;
@@ -947,7 +998,8 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   if (rc) return rc;
   const int threads = q ? kQThreads : std::max(64, epw * L);
   const size_t shmem = (size_t)reserve + (size_t)gr->max_words * 4;
-  const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0, ring != nullptr);
+  const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0, ring != nullptr,
+                                  task_is_default(e->task));
   HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   int per_cu = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem));
@@ -981,7 +1033,9 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   }
   // the kernel's arguments are set on every launch; the key names the kernel
   // and its launch shape
-  auto key = std::make_tuple((int)K, (int)q | (ring ? 2 : 0), L, epw);
+  const int kind = q ? qnet_kind(e->qp) : 0;
+  auto key = std::make_tuple((int)K, kind | (ring ? 8 : 0) | (task_is_default(e->task) ? 0 : 16),
+                             L, epw);
   auto it = e->graphs.find(key);
   if (it == e->graphs.end()) {
     GraphEntry ge;
@@ -1029,6 +1083,8 @@ int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32
     return fail(SPARROW_EUNSUPPORTED,
                 "the fused rollout needs a width-256 actor; use sparrow_act with width 512");
   if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
+  if (!task_is_default(e->task))
+    return fail(SPARROW_EUNSUPPORTED, "the collecting rollout runs the default task only");
   RingDev rd{};
   int64_t head = 0;
   int rc = ring_view(ring, &rd, &head);
@@ -1043,6 +1099,23 @@ int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32
   ring_advance(ring, (int64_t)K * e->cfg.n_envs);
   return SPARROW_OK;
 }
+
+int sparrow_set_task(sparrow_env* e, const sparrow_task* t) {
+  if (!e || !t) return fail(SPARROW_EINVAL, "NULL argument");
+  if ((t->n_actions != 5 && t->n_actions != 7) ||
+      (t->reward != SPARROW_REWARD_PROGRESS && t->reward != SPARROW_REWARD_EQ11) ||
+      (t->state != SPARROW_STATE_TARGET && t->state != SPARROW_STATE_RELATIVE) ||
+      !(t->plan_dist > 0.0f) || !(t->near_dist >= 0.0f) || !(t->near_dist <= 64.0f))
+    return fail(SPARROW_EINVAL,
+                "task: n_actions 5 or 7, known reward and state, plan_dist > 0, 0 <= near_dist <= 64");
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  e->task = *t;
+  e->has_qnet = false;   // the network's input and output sizes follow the task
+  e->was_reset = false;  // the observation layout changes: reset before stepping
+  return SPARROW_OK;
+}
+
+int32_t sparrow_obs_dim(const sparrow_env* e) { return e ? obs_dim(e) : -1; }
 
 int sparrow_debug_hits(sparrow_env* e, int16_t* hit_k) {
   if (!e || !hit_k) return fail(SPARROW_EINVAL, "NULL argument");

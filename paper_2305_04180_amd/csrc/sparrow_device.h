@@ -25,7 +25,7 @@
 namespace sp {
 
 constexpr int kStop = 7;
-constexpr int kNumActions = 7;
+constexpr int kNumActions = 7;  // the largest action set (the 7-row table)
 
 // Philox counter word 2 ("purpose") of each random draw.
 enum : uint32_t {
@@ -143,6 +143,14 @@ struct Params {
   int32_t n_groups, epw;
   int32_t n_envs, n_rays, obs_dim, M, t_max, delay_lo, delay_hi;
   int32_t k_free;           // samples with t_k (1 + 1e-6) + 1e-3 <= robot radius
+  // task (Sec. 4.3.1): actions 7 (the table) or 5 (its rows 0, 1, 3, 5, 6);
+  // reward 0 progress, 1 Eq. (11); state 0 target distance/bearing, 1
+  // relative pose
+  int32_t n_actions, reward_mode, state_mode;
+  float r_arrive, r_collide;  // terminal rewards
+  float inv_D;              // 1 / planning distance
+  float near_r;             // robot radius + the r_d margin
+  float w_d1, w_d2, w_v, w_a, w_d;  // Eq. (11) weights
   int32_t win_rows;         // rows staged on each side of the robot's row (windowed step)
   float ds, range, inv_R, robot_r, arrive_r, omega_max;
   float dt_lo, dt_span, K_lo, K_span, mu_lo, mu_span, vmax_lo, vmax_span, sigma_lo,
@@ -170,6 +178,23 @@ struct Params {
   RingDev ring;
   int32_t ring_head;
   int32_t ring_terminal;    // s' of a done transition: 1 terminal, 0 post-reset observation
+};
+
+// The task seen by a kernel instantiation: TK = false is the default task
+// (7 actions, progress reward with -10 / +10, target state) fixed at compile
+// time, so its kernels carry none of the other tasks' code; TK = true reads
+// the task from the parameters.
+template <bool TK>
+struct TaskOf {
+  static __device__ __forceinline__ int n_actions(const Params& p) {
+    return TK ? p.n_actions : kNumActions;
+  }
+  static __device__ __forceinline__ int reward(const Params& p) { return TK ? p.reward_mode : 0; }
+  static __device__ __forceinline__ int state(const Params& p) { return TK ? p.state_mode : 0; }
+  static __device__ __forceinline__ float arrive(const Params& p) { return TK ? p.r_arrive : 10.0f; }
+  static __device__ __forceinline__ float collide(const Params& p) {
+    return TK ? p.r_collide : -10.0f;
+  }
 };
 
 // Destination of one observation in the experience buffer (both NULL: none).
@@ -421,7 +446,7 @@ __device__ __forceinline__ RayDirs<L> load_rays(const float2* rays, int nr, int 
 // ------------------------------------------------------------------------
 // Observation of one env: rays (march + noise), velocities, target.
 // ------------------------------------------------------------------------
-template <int L>
+template <int L, bool TK = false>
 __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, const RayDirs<L>& rd, const Slot& m,
                         Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
                         float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
@@ -490,16 +515,32 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
   }
   if (ln.q == 0) {
     const float dx = e.tx - e.x, dy = e.ty - e.y;
-    const float d2 = dx * dx + dy * dy;
     const float bx = dx * fx + dy * fy;
     const float by = dy * fx - dx * fy;
-    float o[4];
-    o[0] = e.vl / e.vmax;
-    o[1] = e.va / p.omega_max;
-    o[2] = sqrtf(d2) * inv_dn;
-    o[3] = atan2f(by, bx) * kInvPiF;
+    const float bearing = atan2f(by, bx) * kInvPiF;
+    float o[5];
+    const int smode = TaskOf<TK>::state(p);
+    if (smode == 0) {
+      const float d2 = dx * dx + dy * dy;
+      o[0] = e.vl / e.vmax;
+      o[1] = e.va / p.omega_max;
+      o[2] = sqrtf(d2) * inv_dn;
+      o[3] = bearing;
+      o[4] = 0.0f;
+    } else {
+      // relative pose (Sec. 4.3.1): position relative to the target over
+      // the planning distance, orientation relative to the target, then the
+      // velocities
+      o[0] = (e.x - e.tx) * p.inv_D;
+      o[1] = (e.y - e.ty) * p.inv_D;
+      o[2] = bearing;
+      o[3] = e.vl / e.vmax;
+      o[4] = e.va / p.omega_max;
+    }
+    const int ns = 4 + smode;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < 5; ++a) {
+      if (a >= ns) break;
       if (dst) dst[nr + a] = o[a];
       if (dst2) dst2[nr + a] = o[a];
       if (dst_bf16) dst_bf16[nr + a] = bf16_rne(o[a]);
@@ -586,9 +627,13 @@ struct StepOut {
 };
 
 // Control delay, command, Eq. (5) and Eq. (6): the part of the step that
-// does not read the map.
+// does not read the map. With five actions, action a is row a + (a >= 2) +
+// (a >= 3) of the table: rows 0, 1, 3, 5, 6, the five actions of Sec. 4.3.1.
+template <bool TK = false>
 __device__ __forceinline__ void step_motion(const Params& p, Env& e, int a_hat) {
-  if (a_hat < 0 || a_hat >= kNumActions) a_hat = kStop;
+  const int n_actions = TaskOf<TK>::n_actions(p);
+  if (a_hat < 0 || a_hat >= n_actions) a_hat = kStop;
+  else if (n_actions == 5) a_hat += (a_hat >= 2 ? 1 : 0) + (a_hat >= 3 ? 1 : 0);
   int a;
   if (e.delay == 0) {
     a = a_hat;
@@ -623,8 +668,35 @@ __device__ __forceinline__ void step_motion(const Params& p, Env& e, int a_hat) 
   e.t += 1;
 }
 
-// Collision, arrival, reward and truncation at the new pose (Sec. 4.3.1).
+// Eq. (11) of Sec. 4.3.1 on a step that did not end the episode, at the new
+// pose: r = w_d1 r_d1 + w_d2 r_d2 + w_v r_v + w_alpha r_alpha + w_d r_d,
+// r_d1 = max(1 - |x - tx| / D, 0), r_d2 = max(1 - |y - ty| / D, 0),
+// r_v = [v_l > v_max / 2], r_alpha = 1 - |alpha| / pi (alpha: heading
+// relative to the direction of the target), r_d = -1 when an occupied cell
+// lies within the margin of the robot's edge (a disk test of radius
+// robot_r + margin, touching included), else 0. (dx, dy) = target - pose.
 template <int L>
+__device__ __forceinline__ float eq11_reward(const Params& p, const Lanes<L>& ln, const Slot& m,
+                                             const Env& e, float dx, float dy) {
+  const float rd1 = fmaxf(1.0f - fabsf(dx) * p.inv_D, 0.0f);
+  const float rd2 = fmaxf(1.0f - fabsf(dy) * p.inv_D, 0.0f);
+  const float rv = e.vl > 0.5f * e.vmax ? 1.0f : 0.0f;
+  float sn, cs;
+  sincos_f32(e.phi, sn, cs);
+  const float fx = -cs, fy = -sn;
+  const float bx = dx * fx + dy * fy, by = dy * fx - dx * fy;
+  const float ra = 1.0f - fabsf(atan2f(by, bx) * kInvPiF);
+  const float rd = collides_env<L>(ln, m, e.x, e.y, p.near_r) ? -1.0f : 0.0f;
+  float r = p.w_d1 * rd1;
+  r = r + p.w_d2 * rd2;
+  r = r + p.w_v * rv;
+  r = r + p.w_a * ra;
+  r = r + p.w_d * rd;
+  return r;
+}
+
+// Collision, arrival, reward and truncation at the new pose (Sec. 4.3.1).
+template <int L, bool TK = false>
 __device__ __forceinline__ StepOut step_outcome(const Params& p, const Lanes<L>& ln,
                                                 const Slot& m, Env& e) {
   const bool coll = collides_env<L>(ln, m, e.x, e.y, p.robot_r);
@@ -634,15 +706,18 @@ __device__ __forceinline__ StepOut step_outcome(const Params& p, const Lanes<L>&
   bool term = false;
   float r;
   if (coll) {
-    r = -10.0f;
+    r = TaskOf<TK>::collide(p);
     term = true;
   } else if (arrived) {
-    r = 10.0f;
+    r = TaskOf<TK>::arrive(p);
     term = true;
-  } else {
+  } else if (TaskOf<TK>::reward(p) == 0) {
     const float dist = sqrtf(d2);
     r = (e.dprev - dist) - 0.01f;
     e.dprev = dist;
+  } else {
+    r = eq11_reward<L>(p, ln, m, e, dx, dy);
+    e.dprev = sqrtf(d2);
   }
   const bool trunc = !term && e.t >= p.t_max;
   StepOut o;
@@ -653,11 +728,11 @@ __device__ __forceinline__ StepOut step_outcome(const Params& p, const Lanes<L>&
   return o;
 }
 
-template <int L>
+template <int L, bool TK = false>
 __device__ __forceinline__ StepOut step_env(const Params& p, const Lanes<L>& ln, const Slot& m,
                                             Env& e, int a_hat) {
-  step_motion(p, e, a_hat);
-  return step_outcome<L>(p, ln, m, e);
+  step_motion<TK>(p, e, a_hat);
+  return step_outcome<L, TK>(p, ln, m, e);
 }
 
 // The whole packed map m in global memory as a slot (the AutoReset of the

@@ -187,12 +187,14 @@ k_mlp(QParams qp, const float* __restrict__ obs, int32_t n, float* __restrict__ 
 #pragma unroll
         for (int ww = 1; ww < kMWaves; ++ww) s += QP[(ww * 16 + a) * kMRows + tid];
         qa[a] = qp.b3[a] + s;
-        if (qa[a] > qa[best]) best = a;
+        if (a < qp.n_actions && qa[a] > qa[best]) best = a;
       }
       if (q)
-        for (int a = 0; a < kNumActions; ++a) q[(size_t)row * kNumActions + a] = qa[a];
+        for (int a = 0; a < qp.n_actions; ++a) q[(size_t)row * qp.n_actions + a] = qa[a];
       if (greedy) greedy[row] = best;
-      if (actions) actions[row] = vem_select(best, row, g, actor_eps(qp, eps, row, g), key0, key1);
+      if (actions)
+        actions[row] =
+            vem_select(best, row, g, actor_eps(qp, eps, row, g), key0, key1, qp.n_actions);
     }
   }
 }

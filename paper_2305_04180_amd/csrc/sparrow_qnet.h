@@ -51,6 +51,7 @@ struct QParams {
   const float* b2;     // [h2]
   const float* b3;     // [16], entries >= 7 zero
   int32_t d0, d0p, h1, h2;
+  int32_t n_actions;       // outputs in use (5 or 7; rows of w3 past them are zero)
   int32_t lds_base_words;  // first LDS word of the actor's buffers
   VemSchedule vem;
 };
@@ -277,15 +278,15 @@ __device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
 
 // Q values of env column `row` of a wave's layer-3 tile (plus bias), gathered
 // from the lanes that hold them; every calling lane gets all of them and the
-// lowest index of the maximum.
+// lowest index of the maximum over the q.n_actions actions in use.
 __device__ __forceinline__ int qnet_q_values(const QParams& q, const f32x4& tile, int row,
-                                             float (&qa)[kNumActions]) {
+                                             float (&qa)[kNumActions], int n_actions) {
   int best = 0;
 #pragma unroll
   for (int a = 0; a < kNumActions; ++a) {
     const float v = __shfl(tile[a & 3], row + 16 * (a >> 2));
     qa[a] = q.b3[a] + v;
-    if (qa[a] > qa[best]) best = a;
+    if (a < n_actions && qa[a] > qa[best]) best = a;
   }
   return best;
 }
@@ -295,14 +296,14 @@ __device__ __forceinline__ int qnet_q_values(const QParams& q, const f32x4& tile
 // depend on Q, so the rollout draws it ahead of the forward pass. Returns the random
 // action, or -1 to keep the greedy one.
 __device__ __forceinline__ int vem_draw(int env, uint32_t g, float eps, uint32_t key0,
-                                        uint32_t key1) {
+                                        uint32_t key1, int n_actions) {
   const U4 w = philox((uint32_t)env, g, kExplore, 0u, key0, key1);
-  return unit24(w.x) < eps ? scale_u32(w.y, kNumActions) : -1;
+  return unit24(w.x) < eps ? scale_u32(w.y, (uint32_t)n_actions) : -1;
 }
 
 __device__ __forceinline__ int vem_select(int greedy, int env, uint32_t g, float eps,
-                                          uint32_t key0, uint32_t key1) {
-  const int d = vem_draw(env, g, eps, key0, key1);
+                                          uint32_t key0, uint32_t key1, int n_actions) {
+  const int d = vem_draw(env, g, eps, key0, key1, n_actions);
   return d >= 0 ? d : greedy;
 }
 

@@ -28,7 +28,8 @@ EXPORTS = (
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
-    "sparrow_set_vem_schedule", "sparrow_rollout_collect",
+    "sparrow_set_vem_schedule", "sparrow_rollout_collect", "sparrow_set_task",
+    "sparrow_obs_dim",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
     "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
     "sparrow_learner_create", "sparrow_learner_update", "sparrow_learner_q",
@@ -65,6 +66,18 @@ class LearnerConfig(C.Structure):
                 ("target_every", C.c_int32), ("max_batch", C.c_int32)]
 
 
+class TaskStruct(C.Structure):
+    _fields_ = [("n_actions", C.c_int32), ("reward", C.c_int32), ("state", C.c_int32),
+                ("arrive_reward", C.c_float), ("collide_reward", C.c_float),
+                ("plan_dist", C.c_float), ("near_dist", C.c_float), ("w_d1", C.c_float),
+                ("w_d2", C.c_float), ("w_v", C.c_float), ("w_alpha", C.c_float),
+                ("w_d", C.c_float)]
+
+
+REWARD_PROGRESS, REWARD_EQ11 = 0, 1
+STATE_TARGET, STATE_RELATIVE = 0, 1
+
+
 class MapsStruct(C.Structure):
     _fields_ = [("n_maps", C.c_int32), ("cells", C.c_void_p), ("offsets", C.c_void_p),
                 ("width", C.c_void_p), ("height", C.c_void_p), ("env_to_map", C.c_void_p)]
@@ -91,6 +104,8 @@ def lib(path: str = LIB_PATH):
             "sparrow_act": (I32, [P, P, P]),
             "sparrow_rollout": (I32, [P, I32, I32, P, P, P, P]),
             "sparrow_rollout_collect": (I32, [P, P, I32, I32, I32, P, P, P, P]),
+            "sparrow_set_task": (I32, [P, C.POINTER(TaskStruct)]),
+            "sparrow_obs_dim": (I32, [P]),
             "sparrow_debug_hits": (I32, [P, P]),
             "sparrow_get_state": (I32, [P, P, P]),
             "sparrow_set_state": (I32, [P, P, P]),
@@ -185,6 +200,7 @@ class Env:
         self.n = cfg["n_envs"]
         self.n_rays = cfg["n_rays"]
         self.obs_dim = self.n_rays + 4
+        self.n_actions = N_ACTIONS
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cells, offsets, width, height, env_to_map = maps.flat()
@@ -203,6 +219,23 @@ class Env:
         self.done = torch.zeros(self.n, dtype=u8, device=dev)
         self.flags = torch.zeros(self.n, dtype=u8, device=dev)
         self.actions = torch.zeros(self.n, dtype=i32, device=dev)
+        if cfg.get("task"):
+            self.set_task(**cfg["task"])
+
+    def set_task(self, n_actions=7, reward=REWARD_PROGRESS, state=STATE_TARGET,
+                 arrive_reward=10.0, collide_reward=-10.0, plan_dist=1.0, near_dist=0.0,
+                 weights=(0.3, 0.1, 0.3, 0.3, 0.1)):
+        """Task variant (Sec. 4.3.1): 5 or 7 actions, progress or Eq. (11)
+        reward, target or relative-pose state. Drops the Q-network; reset
+        before stepping."""
+        t = TaskStruct(int(n_actions), int(reward), int(state), float(arrive_reward),
+                       float(collide_reward), float(plan_dist), float(near_dist),
+                       *[float(x) for x in weights])
+        _check(lib().sparrow_set_task(self._h, C.byref(t)))
+        self.n_actions = int(n_actions)
+        self.obs_dim = int(lib().sparrow_obs_dim(self._h))
+        self.obs = self.torch.zeros(self.n, self.obs_dim, dtype=self.torch.float32,
+                                    device=self.device)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -268,9 +301,9 @@ class Env:
         self._b(obs, torch.float32, n * self.obs_dim, "obs")
         if obs.dim() != 2 or obs.shape[1] != self.obs_dim:
             raise ValueError(f"obs: expected shape [n, {self.obs_dim}], got {tuple(obs.shape)}")
-        q = torch.zeros(n, N_ACTIONS, dtype=torch.float32, device=self.device) if q is None else q
+        q = torch.zeros(n, self.n_actions, dtype=torch.float32, device=self.device) if q is None else q
         greedy = torch.zeros(n, dtype=torch.int32, device=self.device) if greedy is None else greedy
-        self._b(q, torch.float32, n * N_ACTIONS, "q")
+        self._b(q, torch.float32, n * self.n_actions, "q")
         self._b(greedy, torch.int32, n, "greedy")
         _check(lib().sparrow_qnet_forward(self._h, _ptr(obs), n, _ptr(q), _ptr(greedy)))
         return q, greedy

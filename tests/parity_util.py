@@ -150,7 +150,39 @@ def settled_greedy(q64, bound):
     return top, gap > bound[rows, top] + bound[rows, second]
 
 
-def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where):
+def compare_reward(g, o, tol, where=""):
+    """Rewards: bit-exact (tol = 0), or within tol where the reward has an
+    atan2 term (Eq. (11)'s r_alpha; FP32 atan2 within a few ulp of FP64)."""
+    if tol == 0:
+        compare_exact(g, o, "reward", where)
+        return
+    d = np.abs(np.asarray(g, np.float64) - np.asarray(o, np.float64))
+    assert d.size == 0 or d.max() <= tol, f"{where}: reward differs by {d.max()}"
+
+
+def compare_obs_relative(g, o, n_rays, noisy=True, where=""):
+    """Relative-pose observations [ranges | (x-tx)/D, (y-ty)/D, alpha/pi,
+    v_l/v_max, v_a/omega_max]: ranges as compare_obs, the pose and velocity
+    entries bit-exact, alpha/pi within BEARING_TOL (wrapping at +-1)."""
+    g = np.asarray(g, np.float32)
+    o = np.asarray(o, np.float32)
+    assert g.shape == o.shape, where
+    rg, ro = g[:, :n_rays], o[:, :n_rays]
+    if noisy:
+        d = np.abs(rg.astype(np.float64) - ro)
+        assert d.size == 0 or d.max() <= RANGE_TOL, f"{where}: range obs differ by {d.max()}"
+    else:
+        assert np.array_equal(rg.view(np.uint32), ro.view(np.uint32)), f"{where}: range obs"
+    for k in (0, 1, 3, 4):
+        col = n_rays + k
+        bad = np.argwhere(g[:, col].view(np.uint32) != o[:, col].view(np.uint32))
+        assert bad.size == 0, f"{where}: state entry {k} differs at rows {bad[:5].ravel()}"
+    b = np.abs(g[:, n_rays + 2].astype(np.float64) - o[:, n_rays + 2])
+    b = np.minimum(b, np.abs(b - 2.0))
+    assert b.size == 0 or b.max() <= BEARING_TOL, f"{where}: alpha differs by {b.max()}"
+
+
+def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where, reward_tol=0.0):
     """Step the oracle with its own FP64 actor + VEM next to a GPU rollout
     (acts, rew, done: [K][N]) and compare; eps is the per-env VEM array, or
     a function of the step index giving it. Explored actions equal the
@@ -178,7 +210,7 @@ def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where):
         n_agree += int((live & ~exb & (acts[t] == a_o)).sum())
         live &= acts[t] == a_o
         r = orc.step(a_o)
-        compare_exact(rew[t][live], r["reward"][live], "reward", w_)
+        compare_reward(rew[t][live], r["reward"][live], reward_tol, w_)
         compare_exact(done[t][live], r["done"][live], "done", w_)
         o_obs = r["obs"]
     print(f"{where}: {live.sum()} of {N} envs compared over {K} steps; {n_settled} of "

@@ -1,0 +1,180 @@
+"""GPU parity of the paper's own task (Sec. 4.3.1/4.3.2) against the oracle:
+27 rays, the five listed actions, the Eq. (11) reward with +75 / -10, the
+32-entry relative-pose state, and the 32-256-128-5 actor. Hit cells, done
+flags, flags, the whole state and the pose/velocity entries of the
+observation are bit-exact; the reward and alpha/pi carry an atan2 and are
+compared within a few FP32 ulp."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2305_04180_amd import inputs
+from tests.parity_util import (RANGE_TOL, actor_lockstep, compare_exact, compare_obs_relative,
+                               compare_reward, compare_state, qnet_bound, qnet_rounded_bound,
+                               settled_greedy, to_np)
+
+pytestmark = pytest.mark.gpu
+REWARD_TOL = 1e-6  # 0.3 * |d alpha/pi| (a few ulp of atan2) plus the sum's rounding
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def make(cfg, maps):
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    env = sparrow.Env(cfg, maps)  # the preset's task is set at creation
+    orc = oracle.Oracle(cfg, maps)
+    orc.set_task(**cfg["task"])
+    assert env.obs_dim == orc.obs_dim == cfg["n_rays"] + 5 == 32
+    return env, orc
+
+
+@pytest.mark.parametrize("variant", [(1, 64), (8, 32), (4, 16)])
+def test_task_step_parity(torch_gpu, variant):
+    torch = torch_gpu
+    cfg = inputs.workload("p", n_envs=37)
+    banner(f"paper task step N=37 variant={variant} 120 steps")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps)
+    env.set_variant(0, *variant)
+    env.reset()
+    o_obs, rc = orc.reset()
+    compare_obs_relative(to_np(env.obs), o_obs, cfg["n_rays"], True, "reset")
+    fo = torch.zeros(env.n, env.obs_dim, dtype=torch.float32, device=env.device)
+    flags = torch.zeros(env.n, dtype=torch.uint8, device=env.device)
+    n_done = 0
+    for s in range(120):
+        a = env.random_actions()
+        a_o = orc.uniform_actions()
+        compare_exact(to_np(a), a_o, "uniform actions", f"step {s}")
+        assert a_o.max() < 5
+        fo.zero_()
+        env.step(a, flags=flags, final_obs=fo)
+        r = orc.step(a_o, final_obs=True, hit_k=True)
+        w = f"task {variant} step {s}"
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", w)
+        compare_exact(to_np(env.done), r["done"], "done", w)
+        compare_exact(to_np(flags), r["flags"], "flags", w)
+        compare_reward(to_np(env.reward), r["reward"], REWARD_TOL, w)
+        compare_obs_relative(to_np(env.obs), r["obs"], cfg["n_rays"], True, w)
+        dn = r["done"].astype(bool)
+        if dn.any():
+            compare_obs_relative(to_np(fo)[dn], r["final_obs"][dn], cfg["n_rays"], True,
+                                 w + " final")
+            # terminal rewards are the constants themselves
+            term = (r["flags"][dn] & 1).astype(bool)
+            assert set(np.unique(r["reward"][dn][term])) <= {np.float32(75.0), np.float32(-10.0)}
+        n_done += int(dn.sum())
+        if s % 10 == 9:
+            gf, gi = env.get_state()
+            of, oi = orc.get_state()
+            compare_state(gf, gi, of, oi, w)
+    assert n_done > 5
+    assert env.status() == 0
+
+
+def test_task_rollout_uniform_parity(torch_gpu):
+    torch = torch_gpu
+    cfg = inputs.workload("p", n_envs=45)
+    K = 24
+    banner(f"paper task rollout uniform N=45 K={K}")
+    maps = inputs.make_maps(cfg)
+    for variant in [(8, 64), (4, 32), (2, 16)]:
+        env, orc = make(cfg, maps)
+        env.set_variant(1, *variant)
+        env.reset()
+        orc.reset()
+        acts, rew, done, obs = env.rollout(K, use_qnet=False)
+        torch.cuda.synchronize()
+        for t in range(K):
+            a = orc.uniform_actions()
+            r = orc.step(a, hit_k=True)
+            w = f"task rollout {variant} t={t}"
+            compare_exact(to_np(acts[t]), a, "actions", w)
+            compare_reward(to_np(rew[t]), r["reward"], REWARD_TOL, w)
+            compare_exact(to_np(done[t]), r["done"], "done", w)
+        compare_obs_relative(to_np(obs), r["obs"], cfg["n_rays"], True, "rollout final obs")
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", "rollout final")
+        gf, gi = env.get_state()
+        of, oi = orc.get_state()
+        compare_state(gf, gi, of, oi, f"task rollout {variant} final")
+
+
+def test_task_actor_forward_and_fused_rollout(torch_gpu):
+    """The 32-256-128-5 network (Sec. 4.3.2) in BF16 on MFMA against the FP64
+    oracle, then the fused rollout with it and VEM, the oracle running its
+    own FP64 actor."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload("p", n_envs=45)
+    dims = cfg["qnet"]
+    assert tuple(dims) == (32, 256, 128, 5)
+    banner("paper task actor 32-256-128-5: forward and fused rollout K=20")
+    maps = inputs.make_maps(cfg)
+    env, orc = make(cfg, maps)
+    w, b, _ = inputs.qnet_weights(dims)
+    eps = sparrow.vem_epsilon(env.n, env.n, 0.01, 0.29)
+    env.set_qnet(dims, w, b, eps)
+    env.reset()
+    o_obs, _ = orc.reset()
+    rows = [o_obs]
+    rng = np.random.default_rng(3)
+    rows.append(rng.uniform(-1.2, 1.2, size=(301, 32)).astype(np.float32))
+    x = np.concatenate(rows)
+    q, greedy = env.qnet_forward(torch.as_tensor(x).cuda())
+    torch.cuda.synchronize()
+    q = to_np(q).astype(np.float64)
+    assert q.shape == (x.shape[0], 5)
+    q64 = oracle.qnet_f64(dims, w, b, x)
+    bound = qnet_bound(dims, w, b, x)
+    assert np.all(np.abs(q - q64) <= bound), (np.abs(q - q64) / bound).max()
+    q_ra = oracle.qnet_f64(dims, w, b, x, round_act=True)
+    top, settled = settled_greedy(q_ra, qnet_rounded_bound(dims, w, b, x))
+    assert np.array_equal(to_np(greedy)[settled], top[settled]) and settled.mean() > 0.9
+    K = 20
+    acts, rew, done, obs = env.rollout(K, use_qnet=True)
+    torch.cuda.synchronize()
+    live, o_last = actor_lockstep(orc, dims, w, b, eps, o_obs, to_np(acts), to_np(rew),
+                                  to_np(done), "task fused", reward_tol=REWARD_TOL)
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf[live], gi[live], of[live], oi[live], "task fused final")
+    assert env.status() == 0
+    # the ring stores the four scalars of the target state only
+    ring = sparrow.Ring(4096, cfg["n_rays"])
+    with pytest.raises(sparrow.SparrowError):
+        env.rollout_collect(ring, 2, True)
+
+
+def test_task_errors(torch_gpu):
+    from paper_2305_04180_amd import sparrow
+    cfg = inputs.workload("c1", n_envs=4)
+    banner("task argument errors")
+    env = sparrow.Env(cfg, inputs.make_maps(cfg))
+    for bad in (dict(n_actions=6), dict(reward=2), dict(state=2), dict(plan_dist=0.0),
+                dict(near_dist=-1.0), dict(near_dist=100.0)):
+        with pytest.raises(sparrow.SparrowError):
+            env.set_task(**bad)
+    env.set_task(n_actions=5, state=1, plan_dist=50.0)
+    assert env.obs_dim == cfg["n_rays"] + 5
+    with pytest.raises(sparrow.SparrowError):
+        env.step(env.random_actions())  # a task change requires a reset
+    env.reset()
+    env.step(env.random_actions())
+    dims = (env.obs_dim, 256, 256, 7)  # 7 outputs for a 5-action task
+    w, b, _ = inputs.qnet_weights(dims)
+    with pytest.raises(sparrow.SparrowError):
+        env.set_qnet(dims, w, b, np.zeros(4, np.float32))
+    assert env.status() == 0
