@@ -79,6 +79,8 @@ def parse():
                     help="skip the full-collection leg (32768 envs, ring buffer)")
     ap.add_argument("--c5-steps", type=int, default=2048)
     ap.add_argument("--c5-warmup", type=int, default=64)
+    ap.add_argument("--no-task", action="store_true",
+                    help="skip the paper's own task (27 rays, 5 actions, Eq. (11), 32-256-128-5)")
     ap.add_argument("--no-asl", action="store_true",
                     help="skip the actor/learner leg paced by the time feedback mechanism")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -258,6 +260,57 @@ def collection_c5(cfg, maps, steps, warmup):
         "add_hbm": {"alg_bytes": int(add_bytes),
                     "achieved_gbs": round(add_bytes / (phase["add"] / 1e3) / 1e9, 1)},
     }
+
+
+def paper_task(steps=2048, K=64):
+    """The paper's own task (Sec. 4.3.1/4.3.2) at 4096 envs on 366^2 maps:
+    27 rays, five actions, Eq. (11) reward, 32-entry relative-pose state,
+    the 32-256-128-5 actor with VEM; fused rollouts and the plain step."""
+    import torch
+    from paper_2305_04180_amd import inputs, sparrow
+    cfg = inputs.workload("p")
+    N = cfg["n_envs"]
+    maps = inputs.make_maps(cfg)
+    dims = cfg["qnet"]
+    w, b, _ = inputs.qnet_weights(dims)
+    env = sparrow.Env(cfg, maps)
+    env.set_qnet(dims, w, b, sparrow.vem_epsilon(N, N, cfg["eps"][0],
+                                                 cfg["eps"][1] - cfg["eps"][0]))
+    env.reset()
+    env.autotune(steps=8)
+    acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
+    rew = torch.zeros(K, N, dtype=torch.float32, device="cuda")
+    done = torch.zeros(K, N, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        env.rollout(K, True, acts, rew, done)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps // K):
+        env.rollout(K, True, acts, rew, done)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fused = N * (steps // K) * K / (e0.elapsed_time(e1) / 1e3)
+    a = torch.zeros(N, dtype=torch.int32, device="cuda")
+    for _ in range(16):
+        env.random_actions(a)
+        env.step(a)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(256):
+        env.random_actions(a)
+        env.step(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain = N * 256 / (e0.elapsed_time(e1) / 1e3)
+    assert env.status() == 0
+    return {"workload": "4096 envs, own 366x366 map each, 27 rays/270 deg/range 100, full DR, "
+                        "5 actions, Eq. (11) reward (+75/-10, margin 15 cells, D 100 cells), "
+                        "32-entry relative-pose state, Q-MLP 32-256-128-5 bf16",
+            "fused_env_steps_per_s": round(fused, 1), "plain_env_steps_per_s": round(plain, 1),
+            "fused_steps": (steps // K) * K, "plain_steps": 256,
+            "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)}}
 
 
 def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
@@ -662,6 +715,12 @@ def main():
         c5 = collection_c5(cfg5, maps5, args.c5_steps, args.c5_warmup)
         log(f"[bench] c5: {c5['value'] / 1e6:.1f} M env-steps/s, phases {c5['phase_ms_per_step']}")
 
+    ptask = None
+    if not args.no_task:
+        log("[bench] the paper's own task (Sec. 4.3.1/4.3.2)")
+        ptask = paper_task()
+        log(f"[bench] paper task: {ptask}")
+
     asl = None
     if not args.no_asl:
         log("[bench] actor + learner paced by the time feedback mechanism")
@@ -698,6 +757,7 @@ def main():
         "cpu_baseline": cpu,
         "precision": precision,
         "collection_c5": c5,
+        "paper_task": ptask,
         "asl_tfm": asl,
     }
     print(json.dumps(out), flush=True)
