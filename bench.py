@@ -758,6 +758,12 @@ def main():
         "precision": precision,
         "collection_c5": c5,
         "paper_task": ptask,
+        "paper_context": {"value": 8155.0, "unit": "env-steps/s", "kind": "context",
+                          "hardware": "NVIDIA RTX 3090 + AMD 3990X (the paper's platform)",
+                          "derived_from": "Table 4: maximal real-time factor 815.5 at N = 64, "
+                                          "divided by the 0.1 s control interval of Table 7",
+                          "note": "a different workload (map size and ray count not stated); "
+                                  "not the target, so vs_baseline stays null"},
         "asl_tfm": asl,
     }
     print(json.dumps(out), flush=True)
