@@ -668,6 +668,54 @@ __device__ __forceinline__ void step_motion(const Params& p, Env& e, int a_hat) 
   e.t += 1;
 }
 
+// Whether any occupied cell square lies within distance r of (px, py): the
+// decision of collides_env's per-cell test over the same box, one row of
+// the box per lane. In a row the cells that pass form one run around the
+// cell under px (dx grows monotonically away from it, and so does the FP32
+// sum dx^2 + dy^2); the run's ends are estimated with a square root and
+// settled by the exact per-cell test of their neighbours, then its bits are
+// read word by word. Cells outside the map count as occupied.
+template <int L>
+__device__ __forceinline__ bool disk_any(const Lanes<L>& ln, const Slot& m, float px, float py,
+                                         float r) {
+  const float r2 = r * r;
+  const int i0 = (int)ceilf(px - r) - 1, i1 = (int)floorf(px + r);
+  const int j0 = (int)ceilf(py - r) - 1, j1 = (int)floorf(py + r);
+  const int ic = cvt_flr(px);
+  bool hit = false;
+  for (int j = j0 + ln.q; j <= j1; j += L) {
+    const float fj = (float)j;
+    const float dy = fmaxf(fmaxf(fj - py, 0.0f), py - (fj + 1.0f));
+    const float dy2 = dy * dy;
+    if (!(dy2 <= r2)) continue;  // no cell of the row is close enough (or NaN)
+    auto pass = [&](int i) {
+      const float fi = (float)i;
+      const float dx = fmaxf(fmaxf(fi - px, 0.0f), px - (fi + 1.0f));
+      return dx * dx + dy2 <= r2;
+    };
+    const float t = sqrtf(r2 - dy2);
+    int hi = min(max(cvt_flr(px + t), ic), i1);
+    while (hi < i1 && pass(hi + 1)) ++hi;
+    while (hi > ic && !pass(hi)) --hi;
+    int lo = max(min((int)ceilf(px - t) - 1, ic), i0);
+    while (lo > i0 && pass(lo - 1)) --lo;
+    while (lo < ic && !pass(lo)) ++lo;
+    // the cell under px always passes, so lo <= ic <= hi
+    if (j < 0 || j >= m.H || lo < 0 || hi >= m.W) {
+      hit = true;
+      continue;
+    }
+    const uint32_t* row = m.w1 + j * m.wpr;
+    for (int c = lo >> 5; c <= (hi >> 5); ++c) {
+      uint32_t mask = ~0u;
+      if (c == (lo >> 5)) mask &= ~0u << (lo & 31);
+      if (c == (hi >> 5)) mask &= ~0u >> (31 - (hi & 31));
+      hit = hit || (row[c] & mask) != 0u;
+    }
+  }
+  return ln.ballot(hit) != 0ull;
+}
+
 // Eq. (11) of Sec. 4.3.1 on a step that did not end the episode, at the new
 // pose: r = w_d1 r_d1 + w_d2 r_d2 + w_v r_v + w_alpha r_alpha + w_d r_d,
 // r_d1 = max(1 - |x - tx| / D, 0), r_d2 = max(1 - |y - ty| / D, 0),
@@ -686,7 +734,7 @@ __device__ __forceinline__ float eq11_reward(const Params& p, const Lanes<L>& ln
   const float fx = -cs, fy = -sn;
   const float bx = dx * fx + dy * fy, by = dy * fx - dx * fy;
   const float ra = 1.0f - fabsf(atan2f(by, bx) * kInvPiF);
-  const float rd = collides_env<L>(ln, m, e.x, e.y, p.near_r) ? -1.0f : 0.0f;
+  const float rd = disk_any<L>(ln, m, e.x, e.y, p.near_r) ? -1.0f : 0.0f;
   float r = p.w_d1 * rd1;
   r = r + p.w_d2 * rd2;
   r = r + p.w_v * rv;

@@ -178,3 +178,46 @@ def test_task_errors(torch_gpu):
     with pytest.raises(sparrow.SparrowError):
         env.set_qnet(dims, w, b, np.zeros(4, np.float32))
     assert env.status() == 0
+
+
+def test_task_margin_disk_many_poses(torch_gpu):
+    """r_d of Eq. (11) (any occupied cell within robot radius + margin) at
+    many random poses held in place (dt = 0), on sparse random maps with the
+    disk reaching past the map's edges; a wrong r_d shows as a 0.1 reward
+    error. Also the 32-lane and 16-lane variants (several rows per lane)."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    rng = np.random.default_rng(21)
+    grids = [(rng.random((200, 200)) < 0.002).astype(np.uint8),
+             (rng.random((120, 300)) < 0.004).astype(np.uint8)]
+    N = 64
+    maps = inputs.single_maps(grids, env_to_map=np.arange(N) % 2)
+    cfg = inputs.workload("p", n_envs=N, label="margin")
+    banner("paper task: r_d at 64 x 8 random held poses, three variants")
+    for variant in ((1, 64), (4, 32), (8, 16)):
+        env, orc = make(cfg, maps)
+        env.set_variant(0, *variant)
+        env.reset()
+        orc.reset()
+        for rnd in range(8):
+            f, iv = orc.get_state()
+            H = np.array([grids[k % 2].shape[0] for k in range(N)], np.float32)
+            W = np.array([grids[k % 2].shape[1] for k in range(N)], np.float32)
+            f[:, 0] = rng.uniform(-3, W + 3).astype(np.float32)
+            f[:, 1] = rng.uniform(-3, H + 3).astype(np.float32)
+            f[:, 2] = rng.uniform(-3.1, 3.1, N).astype(np.float32)
+            f[:, 3] = rng.uniform(0, 10, N).astype(np.float32)   # v_l
+            f[:, 8] = 0.0                                       # dt: pose held
+            f[:, 9] = 1.0                                       # K: velocities held
+            f[:, 11] = 10.0                                     # v_max
+            iv[:, 1] = 0
+            env.set_state(f, iv)
+            orc.set_state(f, iv)
+            a = env.random_actions()
+            env.step(a)
+            r = orc.step(orc.uniform_actions())
+            w = f"margin {variant} round {rnd}"
+            compare_exact(to_np(env.done), r["done"], "done", w)
+            compare_reward(to_np(env.reward), r["reward"], REWARD_TOL, w)
+        assert env.status() == 0
