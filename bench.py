@@ -160,11 +160,12 @@ def cpu_baseline(cfg, maps, w, b, eps, seconds, cores=None):
                       f"FP64 Q-network + VEM + FP32 step, {dt:.1f} s"}
 
 
-def collection_c5(cfg, maps, steps, warmup):
+def collection_c5(cfg, maps, steps, warmup, fused_add=False):
     """The full collection loop (Alg. 1 steps 2-5 with Alg. 2 step 1's
     sampling): per step the 68-512-512-7 actor + VEM (separate kernel), the
     step with AutoReset, and an add of the N transitions to the 2^22-slot
-    device ring; every 8 steps a uniform mini-batch of 256."""
+    device ring (fused_add: by the step kernel itself; else a separate add
+    kernel); every 8 steps a uniform mini-batch of 256."""
     import torch
     from paper_2305_04180_amd import inputs, sparrow
     N, nr = cfg["n_envs"], cfg["n_rays"]
@@ -203,9 +204,14 @@ def collection_c5(cfg, maps, steps, warmup):
         mark()
         env.act(c, act)
         mark()
-        env.step(act, obs=n_, reward=rew, done=done, final_obs=fo)
-        mark()
-        ring.push(c, act, rew, n_, done, fo)
+        if fused_add:
+            # the step adds the transitions itself (s = c, the step's own copy)
+            env.step_collect(ring, act, obs=n_, reward=rew, done=done)
+            mark()
+        else:
+            env.step(act, obs=n_, reward=rew, done=done, final_obs=fo)
+            mark()
+            ring.push(c, act, rew, n_, done, fo)
         mark()
         if t % 8 == 7:
             ring.sample(B, t // 8, outs=sb, idx=sidx)
@@ -245,6 +251,7 @@ def collection_c5(cfg, maps, steps, warmup):
                   "add to a 2^22-slot device ring, 256-draw sample every 8 steps",
         "value": round(N * steps / (ms / 1e3), 1), "unit": "env-steps/s",
         "n_envs": N, "steps": steps, "warmup": warmup, "ms_per_step": round(ms / steps, 5),
+        "add": "inside the step kernel" if fused_add else "separate add kernel",
         "config": {"workload": "32768 envs, own map each, sides {256,366,512}, 64 rays/270 deg/"
                                "range 128, full DR, Q-MLP 68-512-512-7 bf16, eps linspace(0.01,0.3)",
                    "ring_slots": 1 << 22, "bytes_per_transition": 2 * nr + 2 * 8 + 1 + 4 + 0.125,
@@ -713,6 +720,11 @@ def main():
     if maps5 is not None:
         log("[bench] c5 full collection loop")
         c5 = collection_c5(cfg5, maps5, args.c5_steps, args.c5_warmup)
+        # the same loop with the add done by the step kernel (sparrow_step_collect)
+        ins = collection_c5(cfg5, maps5, max(256, args.c5_steps // 4), args.c5_warmup,
+                            fused_add=True)
+        c5["add_in_step"] = {"value": ins["value"], "steps": ins["steps"],
+                             "phase_ms_per_step": ins["phase_ms_per_step"]}
         log(f"[bench] c5: {c5['value'] / 1e6:.1f} M env-steps/s, phases {c5['phase_ms_per_step']}")
 
     ptask = None

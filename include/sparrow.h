@@ -323,6 +323,21 @@ int sparrow_rollout_collect(sparrow_env *env, sparrow_ring *ring, int32_t K, int
                             int32_t terminal_obs, int32_t *actions, float *reward,
                             uint8_t *done, float *obs);
 
+/* sparrow_step (no final_obs) that also adds the step's N transitions to the
+ * ring in the same kernel (Alg. 1 step 5 with a separate actor, as in the
+ * full collection loop): transition i at slot (head + i) mod capacity, s =
+ * the env's current observation (the one the actions were chosen on), a =
+ * actions[i] as given (stored as int8), r, done, and s' as in
+ * sparrow_rollout_collect (terminal observation for done envs when
+ * terminal_obs != 0, else the post-reset one); stored exactly as
+ * sparrow_ring_push stores them. Head and size advance by N. Needs the
+ * target state (EUNSUPPORTED otherwise), the ring's n_rays equal to the
+ * env's and N <= capacity (EINVAL). Runs on the env's stream (the done-bit
+ * clear, then the step). */
+int sparrow_step_collect(sparrow_env *env, sparrow_ring *ring, const int32_t *actions,
+                         float *obs, float *reward, uint8_t *done, uint8_t *flags,
+                         int32_t terminal_obs);
+
 /* ---- Learner ---------------------------------------------------------------
  * The learner's update of Alg. 2 step 2 (train the learner's model on a
  * mini-batch with DDQN; Table 6: gamma 0.98, learning rate 1e-4, target

@@ -115,6 +115,11 @@ __device__ __forceinline__ int32_t ring_slot(const Params& p, int t, int i) {
 // within range of the robot (after the motion, or after the AutoReset), into
 // its own part of LDS with its own lanes: no workgroup barrier. The
 // AutoReset tests its candidates against the packed map in global memory.
+// With a ring in the parameters (p.ring.cap > 0, mode 0) the step also adds
+// its N transitions to it, transition i at slot (ring_head + i) mod
+// capacity: s from the library's copy of the current observation, the
+// action as given, s' the observation after the step (for a done env the
+// terminal one when p.ring_terminal is set).
 template <int L, bool TK>
 __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   extern __shared__ uint32_t lds[];
@@ -137,14 +142,30 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   StepOut o{};
   Slot m{};
   bool reset_now = mode == 1;
+  const bool coll = mode == 0 && p.ring.cap > 0;
+  const int32_t s0 = coll ? ring_slot(p, 0, i) : 0;
+  RingRow sn_row{nullptr, nullptr};
+  if (coll) {
+    // s: the observation the action was chosen on
+    for (int k = ln.q; k < D; k += L) {
+      if (k < p.n_rays)
+        p.ring.rs[(size_t)s0 * p.n_rays + k] = quant_u8(crow[k]);
+      else
+        p.ring.cs[(size_t)s0 * kRingScalars + (k - p.n_rays)] = f16_bits(crow[k]);
+    }
+    sn_row = ring_row(p.ring.rsn, p.ring.csn, p.n_rays, s0);
+  }
   if (mode == 0) {
     step_motion<TK>(p, e, p.actions[i]);
     m = stage_window<L>(p, ln, mm, buf, e.y);
     o = step_outcome<L, TK>(p, ln, m, e);
     reset_now = o.done != 0;
-    if (reset_now && p.final_obs)
-      observe<L, TK>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn, p.final_obs + (size_t)i * D,
-                     nullptr, nullptr, nullptr, false);
+    const bool term_row = coll && p.ring_terminal;
+    if (reset_now && (p.final_obs || term_row))
+      observe<L, TK>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn,
+                     p.final_obs ? p.final_obs + (size_t)i * D : nullptr, nullptr, nullptr,
+                     nullptr, false, term_row ? sn_row : RingRow{nullptr, nullptr});
+    if (reset_now && term_row) sn_row = RingRow{nullptr, nullptr};  // s' written
   }
   bool free_pose = true;  // not done: the step's collision test passed
   if (reset_now) {
@@ -153,13 +174,18 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
     m = stage_window<L>(p, ln, mm, buf, e.y);
   }
   observe<L, TK>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow, crow,
-                 hk, nullptr, free_pose);
+                 hk, nullptr, free_pose, sn_row);
   if (ln.q == 0) {
     store_env(p.s, i, e);
     if (mode == 0) {
       p.reward[i] = o.reward;
       p.done[i] = o.done;
       if (p.flags) p.flags[i] = o.flags;
+    }
+    if (coll) {
+      p.ring.act[s0] = (int8_t)p.actions[i];
+      p.ring.rew[s0] = o.reward;
+      if (o.done) ring_set_done(p.ring, s0);  // the launcher cleared the range's bits
     }
   }
 }
@@ -854,6 +880,39 @@ int sparrow_step(sparrow_env* e, const int32_t* actions, float* obs, float* rewa
   const int rc = launch_step(e, p, 0, e->var_epw[0], e->var_L[0]);
   if (rc) return rc;
   e->g += 1;
+  return SPARROW_OK;
+}
+
+int sparrow_step_collect(sparrow_env* e, sparrow_ring* ring, const int32_t* actions, float* obs,
+                         float* reward, uint8_t* done, uint8_t* flags, int32_t terminal_obs) {
+  if (!e || !ring || !actions || !obs || !reward || !done) return fail(SPARROW_EINVAL, "NULL argument");
+  if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before step");
+  if (e->task.state != SPARROW_STATE_TARGET)
+    return fail(SPARROW_EUNSUPPORTED, "the ring stores the four scalars of the target state");
+  RingDev rd{};
+  int64_t head = 0;
+  int rc = ring_view(ring, &rd, &head);
+  if (rc) return rc;
+  if (rd.nr != e->cfg.n_rays)
+    return fail(SPARROW_EINVAL, "the buffer's ray count differs from the environment's");
+  if ((int64_t)e->cfg.n_envs > (int64_t)rd.cap)
+    return fail(SPARROW_EINVAL, "n_envs transitions exceed the buffer's capacity");
+  rc = ring_clear_done(rd, head, e->cfg.n_envs, e->stream);
+  if (rc) return rc;
+  Params p = base_params(e);
+  p.actions = actions;
+  p.obs = obs;
+  p.reward = reward;
+  p.done = done;
+  p.flags = flags;
+  p.final_obs = nullptr;
+  p.ring = rd;
+  p.ring_head = (int32_t)head;
+  p.ring_terminal = terminal_obs ? 1 : 0;
+  rc = launch_step(e, p, 0, e->var_epw[0], e->var_L[0]);
+  if (rc) return rc;
+  e->g += 1;
+  ring_advance(ring, e->cfg.n_envs);
   return SPARROW_OK;
 }
 

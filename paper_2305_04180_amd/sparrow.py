@@ -28,7 +28,8 @@ EXPORTS = (
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
-    "sparrow_set_vem_schedule", "sparrow_rollout_collect", "sparrow_set_task",
+    "sparrow_set_vem_schedule", "sparrow_rollout_collect", "sparrow_step_collect",
+    "sparrow_set_task",
     "sparrow_obs_dim",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
     "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
@@ -105,6 +106,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_rollout": (I32, [P, I32, I32, P, P, P, P]),
             "sparrow_rollout_collect": (I32, [P, P, I32, I32, I32, P, P, P, P]),
             "sparrow_set_task": (I32, [P, C.POINTER(TaskStruct)]),
+            "sparrow_step_collect": (I32, [P, P, P, P, P, P, P, I32]),
             "sparrow_obs_dim": (I32, [P]),
             "sparrow_debug_hits": (I32, [P, P]),
             "sparrow_get_state": (I32, [P, P, P]),
@@ -268,6 +270,21 @@ class Env:
         final_obs = self._b(final_obs, t.float32, n * D, "final_obs", nullable=True)
         _check(lib().sparrow_step(self._h, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done),
                                   _ptr(flags), _ptr(final_obs)))
+        return obs, reward, done
+
+    def step_collect(self, ring, actions, obs=None, reward=None, done=None, flags=None,
+                     terminal_obs=True):
+        """One step that also adds its N transitions (s = the current
+        observation, the given actions, r, s', done) to `ring`."""
+        t, n, D = self.torch, self.n, self.obs_dim
+        actions = self._b(actions, t.int32, n, "actions")
+        obs = self._b(self.obs if obs is None else obs, t.float32, n * D, "obs")
+        reward = self._b(self.reward if reward is None else reward, t.float32, n, "reward")
+        done = self._b(self.done if done is None else done, t.uint8, n, "done")
+        flags = self._b(flags, t.uint8, n, "flags", nullable=True)
+        _check(lib().sparrow_step_collect(self._h, ring._h, _ptr(actions), _ptr(obs),
+                                          _ptr(reward), _ptr(done), _ptr(flags),
+                                          int(bool(terminal_obs))))
         return obs, reward, done
 
     def random_actions(self, out=None):

@@ -486,3 +486,52 @@ def test_rollout_collect_rejects_mismatched_ring(torch_gpu):
     env.rollout_collect(small, 3, False)
     assert small.size == 3 * N and small.head == 3 * N
     assert env.status() == 0 and small.status() == 0
+
+
+@pytest.mark.parametrize("wl,variant,terminal", [("c2", (1, 64), True), ("c3", (8, 32), True),
+                                                 ("c2", (4, 16), False)])
+def test_step_collect_matches_oracle_ring(torch_gpu, wl, variant, terminal):
+    """The plain step that adds its transitions to the ring itself, with the
+    actions given from outside (here the uniform draws, which the oracle
+    makes on its own): 30 steps of 45 envs into a 1000-slot ring (it wraps),
+    every stored slot against the oracle's step-and-add loop."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    cfg = inputs.workload(wl, n_envs=45)
+    N, nr = 45, cfg["n_rays"]
+    banner(f"collecting step {wl} N={N} variant={variant} terminal={terminal}, 30 steps, ring 1000")
+    maps = inputs.make_maps(cfg)
+    env = sparrow.Env(cfg, maps)
+    orc = oracle.Oracle(cfg, maps)
+    env.set_variant(0, *variant)
+    env.reset()
+    o_obs, _ = orc.reset()
+    ring = sparrow.Ring(1000, nr, seed=6)
+    oring = oracle.Ring(1000, nr, seed=6)
+    raw, slot_raw = [], {}
+    flags = torch.zeros(N, dtype=torch.uint8, device=env.device)
+    for t in range(30):
+        head = ring.head
+        a = env.random_actions()
+        env.step_collect(ring, a, flags=flags, terminal_obs=terminal)
+        torch.cuda.synchronize()
+        rows, o_obs = _oracle_collect(orc, oring, o_obs, 1, lambda t_, o: orc.uniform_actions(),
+                                      raw, terminal)
+        a_o, r_o, d_o = rows[0]
+        w = f"{wl} {variant} step {t}"
+        compare_exact(to_np(a), a_o, "actions", w)
+        compare_exact(to_np(env.reward), r_o, "reward", w)
+        compare_exact(to_np(env.done), d_o, "done", w)
+        compare_obs(to_np(env.obs), o_obs, nr, True, w)
+        for i in range(N):
+            slot_raw[(head + i) % 1000] = (raw[-1][0][i], raw[-1][1][i])
+        assert (ring.size, ring.head) == (oring.size, oring.head)
+    slots = np.arange(ring.size)
+    rs = np.stack([slot_raw[s][0] for s in slots])
+    rsn = np.stack([slot_raw[s][1] for s in slots])
+    _compare_ring_slots(ring, oring, slots, rs, rsn, nr, f"{wl} {variant} ring")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, f"{wl} {variant} final")
+    assert env.status() == 0 and ring.status() == 0
