@@ -721,7 +721,8 @@ def main():
         log("[bench] c5 full collection loop")
         c5 = collection_c5(cfg5, maps5, args.c5_steps, args.c5_warmup)
         # the same loop with the add done by the step kernel (sparrow_step_collect)
-        ins = collection_c5(cfg5, maps5, max(256, args.c5_steps // 4), args.c5_warmup,
+        log("[bench] c5 loop with the add inside the step")
+        ins = collection_c5(cfg5, maps5, max(16, args.c5_steps // 4), args.c5_warmup,
                             fused_add=True)
         c5["add_in_step"] = {"value": ins["value"], "steps": ins["steps"],
                              "phase_ms_per_step": ins["phase_ms_per_step"]}
