@@ -13,7 +13,11 @@
  *     normalisation and no host round trip (Sec. 3.2.1, Alg. 1 step 4),
  *   - an optional fused actor: a Q-network (Sec. 4.3.2) in BF16 on MFMA with
  *     FP32 accumulation, followed by vectorized epsilon-greedy exploration
- *     (VEM, Sec. 3.1.1), feeding K-step rollouts (Alg. 1 steps 2-4).
+ *     (VEM, Sec. 3.1.1), feeding K-step rollouts (Alg. 1 steps 2-4),
+ *   - the sharer's experience buffer (Alg. 1 step 5, Alg. 2 step 1), filled
+ *     by separate adds or by the step and rollout kernels themselves, the
+ *     DDQN learner update (Alg. 2 step 2) and the time feedback mechanism
+ *     (Sec. 3.1.2), and the paper's own task variant (Sec. 4.3.1).
  *
  * Conventions shared by every entry point:
  *   - Return value: SPARROW_OK (0) or a negative SPARROW_E* code; the message
@@ -28,11 +32,13 @@
  *     and sparrow_autotune.
  *   - A handle belongs to one stream and is not thread-safe; distinct handles
  *     are independent. Calls on one handle must not overlap.
- *   - Layouts: obs is FP32 row-major [N][n_rays + 4]; reward FP32 [N];
- *     done uint8 0/1 [N]; flags uint8 [N]; actions int32 [N] in [0, 7).
- *     Rollout outputs are step-major [K][N].
+ *   - Layouts: obs is FP32 row-major [N][obs_dim] (obs_dim = n_rays + 4 for
+ *     the default task; see sparrow_set_task); reward FP32 [N]; done uint8
+ *     0/1 [N]; flags uint8 [N]; actions int32 [N] in [0, n_actions) (7 by
+ *     default). Rollout outputs are step-major [K][N].
  *
- * Observation row (Sec. 4.3.1 state, normalised, relative to the robot):
+ * Observation row of the default task (Sec. 4.3.1 state, normalised,
+ * relative to the robot; sparrow_set_task documents the other layout):
  *   [0, n_rays)   range_j / range (after noise, clipped to [0, range])
  *   n_rays        linear velocity / v_max of the env
  *   n_rays + 1    angular velocity / omega_max
@@ -111,7 +117,7 @@ int sparrow_create(const sparrow_config *cfg, const sparrow_maps *maps, void *hi
                    sparrow_env **out);
 
 /* Reset every env (Alg. 1 initial s = envs.reset()): draws physics, start and
- * target, writes obs (dev [N][n_rays+4]). Advances the global step by one.
+ * target, writes obs (dev [N][obs_dim]). Advances the global step by one.
  * A map with no free start/target makes the error sticky (see status). */
 int sparrow_reset(sparrow_env *env, float *obs);
 
@@ -222,7 +228,7 @@ int sparrow_act(sparrow_env *env, const float *obs, int32_t *actions);
  * installed Q-network + VEM on the current observation; 0: uniform random
  * actions), then the step with AutoReset. Outputs, step-major: actions
  * (dev [K][N], nullable), reward (dev [K][N]), done (dev [K][N]), and obs
- * (dev [N][n_rays+4]) after the last step. Needs a prior reset (the current
+ * (dev [N][obs_dim]) after the last step. Needs a prior reset (the current
  * observation is kept on the device). Advances the global step by K. */
 int sparrow_rollout(sparrow_env *env, int32_t K, int32_t use_qnet, int32_t *actions,
                     float *reward, uint8_t *done, float *obs);
