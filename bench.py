@@ -424,16 +424,15 @@ def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
 
 
 def kernel_source_hash():
-    """sha1 of the HIP sources and the C-ABI header: identifies the kernel
-    build that a counter summary in profiles/ was taken from."""
+    """sha1 of the HIP sources (kernels and the host side that launches
+    them): identifies the kernel build that a counter summary in profiles/
+    was taken from."""
     import hashlib
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_2305_04180_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
-    with open(os.path.join(ROOT, "include", "sparrow.h"), "rb") as f:
-        h.update(f.read())
     return h.hexdigest()
 
 
