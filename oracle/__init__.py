@@ -305,21 +305,22 @@ class Oracle:
     def advance(self):
         lib().orc_advance(self._h)
 
-    def step_envs(self, ids, actions):
+    def step_envs(self, ids, actions, final_obs=False):
         """Step only the envs in `ids` (the others keep their state), then
-        advance the global step. Returns full-size reward/done/obs arrays
-        whose rows outside `ids` are zero."""
+        advance the global step. Returns full-size reward/done/obs (and
+        final_obs) arrays whose rows outside `ids` are zero."""
         a = np.ascontiguousarray(actions, dtype=np.int32)
         obs = np.zeros((self.n, self.obs_dim), np.float32)
         rew = np.zeros(self.n, np.float32)
         done = np.zeros(self.n, np.uint8)
+        fo = np.zeros((self.n, self.obs_dim), np.float32) if final_obs else None
         L = lib()
         for i in ids:
             i = int(i)
-            L.orc_step_range(self._h, i, i + 1, _p(a), _p(obs), _p(rew), _p(done), None, None,
+            L.orc_step_range(self._h, i, i + 1, _p(a), _p(obs), _p(rew), _p(done), None, _p(fo),
                              None, None)
         lib().orc_advance(self._h)
-        return dict(obs=obs, reward=rew, done=done)
+        return dict(obs=obs, reward=rew, done=done, final_obs=fo)
 
     def get_state(self):
         f = np.zeros((self.n, len(STATE_F)), np.float32)

@@ -119,3 +119,92 @@ def test_c3_uneven_sides_rollout_sampled(torch_gpu):
     gf, gi = env.get_state()
     of, oi = orc.get_state()
     compare_state(gf[ids], gi[ids], of[ids], oi[ids], "c3 final state")
+
+
+def test_c5_full_collection_loop_sampled(torch_gpu):
+    """C5 at its full size: 32768 envs on sides {256, 366, 512} (512
+    distinct maps, each shared by 64 envs), 64 rays, range 128, the
+    68-512-512-7 actor + VEM as a separate kernel, the step with terminal
+    observations and the add of all 32768 transitions to a 2^22-slot ring,
+    as the benchmark runs them. The oracle runs every 64th env with its own
+    FP64 actor; while an env's actions equal the FP64 actor's, its steps
+    and its stored transitions are compared."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    from tests.parity_util import RANGE_TOL, qnet_rounded_bound, settled_greedy
+    from tests.test_gpu_collect import _compare_stored_obs
+    torch = torch_gpu
+    cfg = inputs.workload("c5")
+    N, nr, T = cfg["n_envs"], cfg["n_rays"], 6
+    banner(f"c5 full collection N={N}, {T} steps, every 64th env against the oracle")
+    maps = inputs.make_maps(cfg, n_maps=512)
+    maps.env_to_map = (np.arange(N) % 512).astype(np.int32)
+    dims = cfg["qnet"]
+    w, b, _ = inputs.qnet_weights(dims)
+    eps = sparrow.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
+    env = sparrow.Env(cfg, maps)
+    env.set_qnet(dims, w, b, eps)
+    cur = env.reset()
+    env.autotune(steps=2)
+    ring = sparrow.Ring(1 << 22, nr, seed=5)
+    orc = oracle.Oracle(cfg, maps)
+    o_obs, _ = orc.reset()
+    ids = np.arange(0, N, 64)
+    oring = oracle.Ring(T * len(ids), nr, seed=5)
+    nxt, fo = torch.zeros_like(cur), torch.zeros_like(cur)
+    act = torch.zeros(N, dtype=torch.int32, device=env.device)
+    rew = torch.zeros(N, dtype=torch.float32, device=env.device)
+    done = torch.zeros(N, dtype=torch.uint8, device=env.device)
+    live = np.ones(len(ids), bool)
+    live_at, raw = [], []
+    for t in range(T):
+        env.act(cur, act)
+        fo.zero_()
+        env.step(act, obs=nxt, reward=rew, done=done, final_obs=fo)
+        ring.push(cur, act, rew, nxt, done, fo)
+        # the oracle's own actor on the sampled envs
+        q_full = np.zeros((N, dims[3]), np.float64)
+        q_full[ids] = oracle.qnet_f64(dims, w, b, o_obs[ids])
+        a_o, ex = orc.vem(q_full, eps)
+        q_ra = oracle.qnet_f64(dims, w, b, o_obs[ids], round_act=True)
+        top, settled = settled_greedy(q_ra, qnet_rounded_bound(dims, w, b, o_obs[ids], RANGE_TOL))
+        r = orc.step_envs(ids, a_o, final_obs=True)
+        torch.cuda.synchronize()
+        g_a = to_np(act)[ids]
+        exb = ex[ids].astype(bool)
+        w_ = f"c5 t={t}"
+        compare_exact(g_a[live & exb], a_o[ids][live & exb], "explored actions", w_)
+        m = live & ~exb & settled
+        compare_exact(g_a[m], top[m], "settled greedy actions", w_)
+        live &= g_a == a_o[ids]
+        compare_exact(to_np(rew)[ids][live], r["reward"][ids][live], "reward", w_)
+        compare_exact(to_np(done)[ids][live], r["done"][ids][live], "done", w_)
+        compare_obs(to_np(nxt)[ids][live], r["obs"][ids][live], nr, True, w_)
+        d = r["done"][ids].astype(bool)
+        sn = np.where(d[:, None], r["final_obs"][ids], r["obs"][ids])
+        oring.push(o_obs[ids], a_o[ids], r["reward"][ids], r["obs"][ids], r["done"][ids],
+                   r["final_obs"][ids])
+        raw.append((o_obs[ids].copy(), sn))
+        live_at.append(live.copy())
+        o_obs = o_obs.copy()
+        o_obs[ids] = r["obs"][ids]
+        cur, nxt = nxt, cur
+    print(f"{live.sum()} of {len(ids)} sampled envs compared through {T} steps", flush=True)
+    assert live.mean() >= 0.9
+    assert ring.size == T * N
+    slots = np.concatenate([t * N + ids for t in range(T)])
+    g = [to_np(x) for x in ring.gather(slots)]
+    o = oring.gather(np.arange(T * len(ids)))
+    mask = np.concatenate(live_at)
+    rs = np.concatenate([x[0] for x in raw])
+    rsn = np.concatenate([x[1] for x in raw])
+    _compare_stored_obs(g[0][mask], o[0][mask], rs[mask], nr, "c5 ring s")
+    _compare_stored_obs(g[3][mask], o[3][mask], rsn[mask], nr, "c5 ring s'")
+    compare_exact(g[1][mask], o[1][mask], "ring a", "c5")
+    compare_exact(g[2][mask], o[2][mask], "ring r", "c5")
+    compare_exact(g[4][mask], o[4][mask], "ring done", "c5")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    lid = ids[live]
+    compare_state(gf[lid], gi[lid], of[lid], oi[lid], "c5 final state")
+    assert env.status() == 0 and ring.status() == 0
