@@ -298,7 +298,13 @@ def paper_task(steps=2048, K=64):
         env.rollout(K, True, acts, rew, done)
     e1.record(stream)
     torch.cuda.synchronize()
-    fused = N * (steps // K) * K / (e0.elapsed_time(e1) / 1e3)
+    fused_ms = e0.elapsed_time(e1)
+    fused = N * (steps // K) * K / (fused_ms / 1e3)
+    hits = env.debug_hits().to(torch.int32)
+    M = int(cfg["range"] / cfg["ds"])
+    samples = float(torch.where(hits < 0, torch.full_like(hits, M), hits).add(1).sum().item()) / N
+    ops = ALG_OPS_PER_SAMPLE * samples + ALG_OPS_PER_RAY * cfg["n_rays"] + ALG_OPS_PER_ENV
+    alu = ops * fused / 1e12
     a = torch.zeros(N, dtype=torch.int32, device="cuda")
     for _ in range(16):
         env.random_actions(a)
@@ -317,7 +323,52 @@ def paper_task(steps=2048, K=64):
                         "32-entry relative-pose state, Q-MLP 32-256-128-5 bf16",
             "fused_env_steps_per_s": round(fused, 1), "plain_env_steps_per_s": round(plain, 1),
             "fused_steps": (steps // K) * K, "plain_steps": 256,
+            "roofline": {"bound": "alu", "achieved": round(alu, 3), "peak": MI355X_VALU_TOPS,
+                         "unit": "TFLOP/s", "frac": round(alu / MI355X_VALU_TOPS, 4),
+                         "samples_per_env_step": round(samples, 2),
+                         "units": "the default task's lane-op counts (13/sample, 110/ray, "
+                                  "707/env); Eq. (11)'s terms are not counted"},
             "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)}}
+
+
+def learner_leg(updates=200, batch=256):
+    """The DDQN update (Alg. 2 step 2) on its own: back-to-back updates on
+    resident 256-row mini-batches of the 36-256-256-7 network, HIP events
+    around them. Algorithmic FLOP per update: three forward passes (online
+    s, online s', target s') and the backward pass of one (about two
+    forwards), FP32 on the vector units."""
+    import torch
+    from paper_2305_04180_amd import inputs, sparrow
+    dims = (36, 256, 256, 7)
+    _, b, w32 = inputs.qnet_weights(dims)
+    L = sparrow.Learner(dims, w32, b, max_batch=batch)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    s = torch.rand(batch, dims[0], device="cuda", generator=g)
+    sn = torch.rand(batch, dims[0], device="cuda", generator=g)
+    a = torch.randint(0, dims[3], (batch,), device="cuda", dtype=torch.int32, generator=g)
+    r = torch.randn(batch, device="cuda", generator=g)
+    d = (torch.rand(batch, device="cuda", generator=g) < 0.1).to(torch.uint8)
+    for _ in range(10):
+        L.update(s, a, r, sn, d)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(updates):
+        L.update(s, a, r, sn, d)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / updates
+    fwd = 2.0 * batch * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3])
+    flop = 5.0 * fwd
+    tf = flop / (ms / 1e3) / 1e12
+    return {"updates": updates, "minibatch": batch, "network": list(dims),
+            "ms_per_update": round(ms, 4), "updates_per_s": round(1e3 / ms, 1),
+            "roofline": {"bound": "latency", "achieved": round(tf, 3), "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": round(tf / 157.3, 5),
+                         "flop_per_update": int(flop),
+                         "note": "FP32 vector peak; a 256-row update is a chain of small "
+                                 "dependent kernels"}}
 
 
 def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
@@ -733,6 +784,12 @@ def main():
         ptask = paper_task()
         log(f"[bench] paper task: {ptask}")
 
+    learner = None
+    if not args.no_asl:
+        log("[bench] learner updates back to back")
+        learner = learner_leg()
+        log(f"[bench] learner: {learner['ms_per_update']} ms per update")
+
     asl = None
     if not args.no_asl:
         log("[bench] actor + learner paced by the time feedback mechanism")
@@ -777,6 +834,7 @@ def main():
                           "note": "a different workload (map size and ray count not stated); "
                                   "not the target, so vs_baseline stays null"},
         "asl_tfm": asl,
+        "learner": learner,
     }
     print(json.dumps(out), flush=True)
 

@@ -12,9 +12,13 @@
 //   k_learn_loss  a* = argmax Q_online(s') (lowest index on ties), y = r +
 //                 gamma (1 - done) Q_target(s')[a*], delta = Q(s)[a] - y,
 //                 dloss/dQ[a] = clip(delta, -k, k) / B, loss = mean Huber
-//   k_learn_g3 / k_learn_g2 / k_learn_d1 / k_learn_g1
-//                 back-propagation: one thread per gradient entry, the sum
-//                 over the mini-batch in row order; relu'(0) = 0
+//   k_learn_delta G[b][o] = [a_b == o] dloss/dQ_b (the output error as a
+//                 B x A matrix) and da2[b][u] = [a2 > 0] dloss/dQ_b W3[a_b][u]
+//   k_learn_gemm  back-propagation as four small products, C = X^T Y over
+//                 the mini-batch (or over the units for da1), tiled through
+//                 LDS: gW3 = G^T a2, gW2 = da2^T a1, da1 = [a1 > 0] (da2 W2),
+//                 gW1 = da1^T s; each bias gradient is the column sum of X,
+//                 computed as an extra column of ones in Y; relu'(0) = 0
 //   k_learn_adam  Adam on every weight and bias, then the transposed copies
 //                 the forward pass reads; every target_every-th update the
 //                 target network becomes a copy of the online one
@@ -121,74 +125,96 @@ k_learn_loss(Dims dm, int32_t B, float gamma, float k_h, const int32_t* __restri
   if (tid == 0 && loss) loss[0] = part[0] / (float)B;
 }
 
-// layer 3: gW3[o][h] = sum_b [a_b == o] g_b a2[b][h]; gb3[o] likewise
-__global__ void k_learn_g3(Dims dm, int32_t B, const int32_t* __restrict__ a,
-                           const float* __restrict__ g, const float* __restrict__ a2,
-                           float* __restrict__ gW3, float* __restrict__ gb3) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= dm.A * (dm.h2 + 1)) return;
-  const int o = t / (dm.h2 + 1), h = t % (dm.h2 + 1);
-  float acc = 0.0f;
-  for (int b = 0; b < B; ++b)
-    if (a[b] == o) acc += g[b] * (h < dm.h2 ? a2[(size_t)b * dm.h2 + h] : 1.0f);
-  if (h < dm.h2)
-    gW3[(size_t)o * dm.h2 + h] = acc;
-  else
-    gb3[o] = acc;
-}
-
-// da2[b][o] = [a2 > 0] g_b W3[a_b][o]; layer 2: gW2[o][k] = sum_b da2[b][o] a1[b][k]
-__global__ void k_learn_g2(Dims dm, int32_t B, const int32_t* __restrict__ a,
-                           const float* __restrict__ g, const float* __restrict__ W3,
-                           const float* __restrict__ a1, const float* __restrict__ a2,
-                           float* __restrict__ gW2, float* __restrict__ gb2) {
-  const int o = blockIdx.y;  // one row of W2 per grid row
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > dm.h1) return;
-  float acc = 0.0f;
-  for (int b = 0; b < B; ++b) {
-    const float a2v = a2[(size_t)b * dm.h2 + o];
-    const float d2 = a2v > 0.0f ? g[b] * W3[(size_t)a[b] * dm.h2 + o] : 0.0f;
-    acc += d2 * (k < dm.h1 ? a1[(size_t)b * dm.h1 + k] : 1.0f);
-  }
-  if (k < dm.h1)
-    gW2[(size_t)o * dm.h1 + k] = acc;
-  else
-    gb2[o] = acc;
-}
-
-// da1[b][k] = [a1 > 0] sum_o da2[b][o] W2[o][k]
-__global__ void k_learn_d1(Dims dm, int32_t B, const int32_t* __restrict__ a,
-                           const float* __restrict__ g, const float* __restrict__ W2,
-                           const float* __restrict__ W3, const float* __restrict__ a1,
-                           const float* __restrict__ a2, float* __restrict__ da1) {
-  const int b = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= dm.h1) return;
+// G[b][o] = [a_b == o] g_b (B x A); da2[b][u] = [a2[b][u] > 0] g_b W3[a_b][u]
+__global__ void k_learn_delta(Dims dm, int32_t B, const int32_t* __restrict__ a,
+                              const float* __restrict__ g, const float* __restrict__ W3,
+                              const float* __restrict__ a2, float* __restrict__ G,
+                              float* __restrict__ da2) {
+  const int b = blockIdx.x;
   const float gb = g[b];
-  const float* w3row = W3 + (size_t)a[b] * dm.h2;
-  float acc = 0.0f;
-  for (int o = 0; o < dm.h2; ++o) {
-    const float a2v = a2[(size_t)b * dm.h2 + o];
-    const float d2 = a2v > 0.0f ? gb * w3row[o] : 0.0f;
-    acc += d2 * W2[(size_t)o * dm.h1 + k];
+  const int ab = a[b];
+  for (int u = threadIdx.x; u < dm.h2; u += blockDim.x) {
+    const float a2v = a2[(size_t)b * dm.h2 + u];
+    da2[(size_t)b * dm.h2 + u] = a2v > 0.0f ? gb * W3[(size_t)ab * dm.h2 + u] : 0.0f;
   }
-  da1[(size_t)b * dm.h1 + k] = a1[(size_t)b * dm.h1 + k] > 0.0f ? acc : 0.0f;
+  for (int o = threadIdx.x; o < dm.A; o += blockDim.x)
+    G[(size_t)b * dm.A + o] = o == ab ? gb : 0.0f;
 }
 
-// layer 1: gW1[o][k] = sum_b da1[b][o] s[b][k]; gb1[o] likewise
-__global__ void k_learn_g1(Dims dm, int32_t B, const float* __restrict__ da1,
-                           const float* __restrict__ s, float* __restrict__ gW1,
-                           float* __restrict__ gb1) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= dm.h1 * (dm.d0 + 1)) return;
-  const int o = t / (dm.d0 + 1), k = t % (dm.d0 + 1);
-  float acc = 0.0f;
-  for (int b = 0; b < B; ++b)
-    acc += da1[(size_t)b * dm.h1 + o] * (k < dm.d0 ? s[(size_t)b * dm.d0 + k] : 1.0f);
-  if (k < dm.d0)
-    gW1[(size_t)o * dm.d0 + k] = acc;
-  else
-    gb1[o] = acc;
+// C[m][n] = sum_k X(k, m) Y(k, n), X(k, m) = X[k sxk + m sxm], Y(k, n) =
+// Y[k syk + n syn], for m < M and n < N; with Cb, column N of Y is ones and
+// Cb[m] = sum_k X(k, m) (a bias gradient); with mask, C[m][n] is kept only
+// where mask[m ldm + n] > 0 (relu'). 32 x 32 output tiles, 256 threads of
+// 2 x 2 outputs, K in chunks of 16 staged through LDS with the next chunk's
+// loads in flight during the current chunk's products. Each output sums its
+// K terms in ascending k.
+constexpr int kGT = 32, kGK = 16;
+
+__device__ __forceinline__ void gemm_load(const float* X, int sxk, int sxm, int M, const float* Y,
+                                          int syk, int syn, int N, bool ones, int K, int k0,
+                                          int m0, int n0, float (&xr)[2], float (&yr)[2]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int e = threadIdx.x + r * 256;  // 512 elements of each 16 x 32 tile
+    // consecutive threads walk the operand's unit-stride index
+    const int xk = sxm == 1 ? e / kGT : e % kGK, xm = sxm == 1 ? e % kGT : e / kGK;
+    const int yk = syn == 1 ? e / kGT : e % kGK, yn = syn == 1 ? e % kGT : e / kGK;
+    const int kx = k0 + xk, ky = k0 + yk, m = m0 + xm, n = n0 + yn;
+    xr[r] = (kx < K && m < M) ? X[(size_t)kx * sxk + (size_t)m * sxm] : 0.0f;
+    yr[r] = (ky < K && n < N) ? Y[(size_t)ky * syk + (size_t)n * syn]
+            : (ky < K && ones && n == N) ? 1.0f : 0.0f;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_learn_gemm(int M, int N, int K, const float* __restrict__ X, int sxk, int sxm,
+             const float* __restrict__ Y, int syk, int syn, float* __restrict__ C, int ldc,
+             float* __restrict__ Cb, const float* __restrict__ mask, int ldm) {
+  __shared__ float xs[kGK][kGT];
+  __shared__ float ys[kGK][kGT];
+  const int m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
+  const int tm = (threadIdx.x / 16) * 2, tn = (threadIdx.x % 16) * 2;
+  const bool ones = Cb != nullptr;
+  float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+  float xr[2], yr[2];
+  gemm_load(X, sxk, sxm, M, Y, syk, syn, N, ones, K, 0, m0, n0, xr, yr);
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = threadIdx.x + r * 256;
+      const int xk = sxm == 1 ? e / kGT : e % kGK, xm = sxm == 1 ? e % kGT : e / kGK;
+      const int yk = syn == 1 ? e / kGT : e % kGK, yn = syn == 1 ? e % kGT : e / kGK;
+      xs[xk][xm] = xr[r];
+      ys[yk][yn] = yr[r];
+    }
+    __syncthreads();
+    if (k0 + kGK < K)
+      gemm_load(X, sxk, sxm, M, Y, syk, syn, N, ones, K, k0 + kGK, m0, n0, xr, yr);
+#pragma unroll
+    for (int kk = 0; kk < kGK; ++kk) {
+      const float x0 = xs[kk][tm], x1 = xs[kk][tm + 1];
+      const float y0 = ys[kk][tn], y1 = ys[kk][tn + 1];
+      acc[0][0] += x0 * y0;
+      acc[0][1] += x0 * y1;
+      acc[1][0] += x1 * y0;
+      acc[1][1] += x1 * y1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int m = m0 + tm + i, n = n0 + tn + j;
+      if (m >= M) continue;
+      if (n < N) {
+        float v = acc[i][j];
+        if (mask && !(mask[(size_t)m * ldm + n] > 0.0f)) v = 0.0f;
+        C[(size_t)m * ldc + n] = v;
+      } else if (ones && n == N) {
+        Cb[m] = acc[i][j];
+      }
+    }
 }
 
 __global__ void k_learn_adam(int64_t n, float* __restrict__ p, float* __restrict__ m,
@@ -235,6 +261,7 @@ struct sparrow_learner {
   float *w1t = nullptr, *w2t = nullptr, *w1t_t = nullptr, *w2t_t = nullptr;
   // per-batch scratch
   float *a1 = nullptr, *a2 = nullptr, *q = nullptr, *g = nullptr, *da1 = nullptr;
+  float *da2 = nullptr, *G = nullptr;
 };
 
 namespace {
@@ -308,6 +335,8 @@ int sparrow_learner_create(const int32_t* dims, const float* w_host, const float
   if (!rc) rc = lalloc(L, &L->a1, B * d.h1);
   if (!rc) rc = lalloc(L, &L->a2, B * d.h2);
   if (!rc) rc = lalloc(L, &L->da1, B * d.h1);
+  if (!rc) rc = lalloc(L, &L->da2, B * d.h2);
+  if (!rc) rc = lalloc(L, &L->G, B * d.A);
   if (!rc) rc = lalloc(L, &L->q, 3 * B * d.A);
   if (!rc) rc = lalloc(L, &L->g, B);
   if (rc) {
@@ -362,14 +391,25 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   const int64_t off2 = (int64_t)d.h1 * d.d0, off3 = off2 + (int64_t)d.h2 * d.h1;
   const float* W2 = L->w + off2;
   const float* W3 = L->w + off3;
-  hipLaunchKernelGGL(k_learn_g3, dim3(blocks_for((int64_t)d.A * (d.h2 + 1), 256)), dim3(256), 0,
-                     L->stream, d, B, a, L->g, L->a2, L->gw + off3, L->gb + d.h1 + d.h2);
-  hipLaunchKernelGGL(k_learn_g2, dim3(blocks_for(d.h1 + 1, 256), d.h2), dim3(256), 0, L->stream,
-                     d, B, a, L->g, W3, L->a1, L->a2, L->gw + off2, L->gb + d.h1);
-  hipLaunchKernelGGL(k_learn_d1, dim3(blocks_for(d.h1, 256), B), dim3(256), 0, L->stream, d, B, a,
-                     L->g, W2, W3, L->a1, L->a2, L->da1);
-  hipLaunchKernelGGL(k_learn_g1, dim3(blocks_for((int64_t)d.h1 * (d.d0 + 1), 256)), dim3(256), 0,
-                     L->stream, d, B, L->da1, s, L->gw, L->gb);
+  hipLaunchKernelGGL(k_learn_delta, dim3(B), dim3(256), 0, L->stream, d, B, a, L->g, W3, L->a2,
+                     L->G, L->da2);
+  // C[M][N] (+ bias column) = X^T Y over K
+  auto gemm = [&](int M, int N, int K, const float* X, int sxk, int sxm, const float* Y, int syk,
+                  int syn, float* C, int ldc, float* Cb, const float* mask, int ldm) {
+    const int cols = N + (Cb ? 1 : 0);
+    hipLaunchKernelGGL(k_learn_gemm, dim3((cols + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
+                       0, L->stream, M, N, K, X, sxk, sxm, Y, syk, syn, C, ldc, Cb, mask, ldm);
+  };
+  // gW3[o][u] = sum_b G[b][o] a2[b][u]; gb3[o] = sum_b G[b][o]
+  gemm(d.A, d.h2, B, L->G, d.A, 1, L->a2, d.h2, 1, L->gw + off3, d.h2, L->gb + d.h1 + d.h2,
+       nullptr, 0);
+  // gW2[u][k] = sum_b da2[b][u] a1[b][k]; gb2[u] = sum_b da2[b][u]
+  gemm(d.h2, d.h1, B, L->da2, d.h2, 1, L->a1, d.h1, 1, L->gw + off2, d.h1, L->gb + d.h1, nullptr,
+       0);
+  // da1[b][k] = [a1[b][k] > 0] sum_u da2[b][u] W2[u][k]
+  gemm(B, d.h1, d.h2, L->da2, 1, d.h2, W2, d.h1, 1, L->da1, d.h1, nullptr, L->a1, d.h1);
+  // gW1[k][i] = sum_b da1[b][k] s[b][i]; gb1[k] = sum_b da1[b][k]
+  gemm(d.h1, d.d0, B, L->da1, d.h1, 1, s, d.d0, 1, L->gw, d.d0, L->gb, nullptr, 0);
   HIP_TRY(hipGetLastError());
   L->steps += 1;
   const double c1 = 1.0 - std::pow((double)L->cfg.beta1, (double)L->steps);
