@@ -19,9 +19,10 @@
 //                 LDS: gW3 = G^T a2, gW2 = da2^T a1, da1 = [a1 > 0] (da2 W2),
 //                 gW1 = da1^T s; each bias gradient is the column sum of X,
 //                 computed as an extra column of ones in Y; relu'(0) = 0
-//   k_learn_adam  Adam on every weight and bias, then the transposed copies
-//                 the forward pass reads; every target_every-th update the
-//                 target network becomes a copy of the online one
+//   k_learn_adam  Adam on every weight and bias in one launch, writing the
+//                 transposed copies the forward pass reads as it goes; every
+//                 target_every-th update the target network becomes a copy
+//                 of the online one
 // Weights are row-major [out][in], concatenated [W1 | W2 | W3]; biases
 // [b1 | b2 | b3].
 #include <hip/hip_runtime.h>
@@ -217,17 +218,39 @@ k_learn_gemm(int M, int N, int K, const float* __restrict__ X, int sxk, int sxm,
     }
 }
 
-__global__ void k_learn_adam(int64_t n, float* __restrict__ p, float* __restrict__ m,
-                             float* __restrict__ v, const float* __restrict__ g, float lr,
-                             float beta1, float beta2, float eps, float c1, float c2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
+// Adam on the nw weights (threads [0, nw)) and the nb biases (threads
+// [nw, nw + nb)) in one launch; each updated W1 or W2 entry is also written to
+// the transposed copy the forward pass reads.
+__global__ void k_learn_adam(Dims dm, int64_t nw, int64_t nb, float* __restrict__ w,
+                             float* __restrict__ mw, float* __restrict__ vw,
+                             const float* __restrict__ gw, float* __restrict__ b,
+                             float* __restrict__ mb, float* __restrict__ vb,
+                             const float* __restrict__ gb, float* __restrict__ w1t,
+                             float* __restrict__ w2t, float lr, float beta1, float beta2,
+                             float eps, float c1, float c2) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nw + nb) return;
+  const bool is_w = t < nw;
+  const int64_t i = is_w ? t : t - nw;
+  float* p = is_w ? w : b;
+  float* m = is_w ? mw : mb;
+  float* v = is_w ? vw : vb;
+  const float gi = (is_w ? gw : gb)[i];
   const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
   const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  if (!is_w) return;
+  const int64_t n1 = (int64_t)dm.h1 * dm.d0, n2 = (int64_t)dm.h2 * dm.h1;
+  if (i < n1) {
+    const int64_t r = i / dm.d0, c = i % dm.d0;  // W1[r][c] -> W1T[c][r]
+    w1t[c * dm.h1 + r] = pi;
+  } else if (i < n1 + n2) {
+    const int64_t j = i - n1, r = j / dm.h1, c = j % dm.h1;  // W2[r][c] -> W2T[c][r]
+    w2t[c * dm.h2 + r] = pi;
+  }
 }
 
 // W [rows][cols] -> WT [cols][rows]
@@ -414,15 +437,11 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   L->steps += 1;
   const double c1 = 1.0 - std::pow((double)L->cfg.beta1, (double)L->steps);
   const double c2 = 1.0 - std::pow((double)L->cfg.beta2, (double)L->steps);
-  hipLaunchKernelGGL(k_learn_adam, dim3(blocks_for(L->nw, 256)), dim3(256), 0, L->stream, L->nw,
-                     L->w, L->mw, L->vw, L->gw, L->cfg.lr, L->cfg.beta1, L->cfg.beta2,
-                     L->cfg.adam_eps, (float)c1, (float)c2);
-  hipLaunchKernelGGL(k_learn_adam, dim3(blocks_for(L->nb, 256)), dim3(256), 0, L->stream, L->nb,
-                     L->b, L->mb, L->vb, L->gb, L->cfg.lr, L->cfg.beta1, L->cfg.beta2,
-                     L->cfg.adam_eps, (float)c1, (float)c2);
+  hipLaunchKernelGGL(k_learn_adam, dim3(blocks_for(L->nw + L->nb, 256)), dim3(256), 0, L->stream,
+                     d, L->nw, L->nb, L->w, L->mw, L->vw, L->gw, L->b, L->mb, L->vb, L->gb,
+                     L->w1t, L->w2t, L->cfg.lr, L->cfg.beta1, L->cfg.beta2, L->cfg.adam_eps,
+                     (float)c1, (float)c2);
   HIP_TRY(hipGetLastError());
-  rc = refresh_transposes(L, false);
-  if (rc) return rc;
   if (L->cfg.target_every > 0 && L->steps % L->cfg.target_every == 0) {
     HIP_TRY(hipMemcpyAsync(L->wt, L->w, sizeof(float) * L->nw, hipMemcpyDeviceToDevice, L->stream));
     HIP_TRY(hipMemcpyAsync(L->bt, L->b, sizeof(float) * L->nb, hipMemcpyDeviceToDevice, L->stream));
