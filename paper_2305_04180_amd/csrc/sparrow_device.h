@@ -341,7 +341,7 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
 }
 
 #ifndef SPARROW_UNROLL
-#define SPARROW_UNROLL 4
+#define SPARROW_UNROLL 10
 #endif
 constexpr int kUnroll = SPARROW_UNROLL;  // samples per lane per iteration (independent LDS reads)
 static_assert(kUnroll <= 31, "hit bits of one block and the sentinel fit a word");
