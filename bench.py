@@ -648,6 +648,31 @@ def main():
     samples_last = float(torch.where(hits < 0, torch.full_like(hits, M), hits).add(1).sum().item())
     log(f"[bench] fused: {fused_rate / 1e6:.1f} M env-steps/s ({fused_ms / steps_fused * 1e3:.2f} us/step)")
 
+    # ---------------- the same steps in 256-step launches ----------------
+    # (the workload's rollouts are 64 steps; longer launches amortise the
+    # per-launch map staging and graph launch over more steps)
+    K2 = 256
+    n2, rem2 = divmod(args.steps, K2)
+    a2 = torch.zeros(K2, N, dtype=torch.int32, device="cuda")
+    r2 = torch.zeros(K2, N, dtype=torch.float32, device="cuda")
+    d2 = torch.zeros(K2, N, dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        env.rollout(K2, True, a2, r2, d2, obs)
+    if rem2:
+        env.rollout(rem2, True, a2, r2, d2, obs)
+    torch.cuda.synchronize()
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for _ in range(n2):
+        env.rollout(K2, True, a2, r2, d2, obs)
+    if rem2:
+        env.rollout(rem2, True, a2, r2, d2, obs)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    fused_k256 = N * args.steps / (k0.elapsed_time(k1) / 1e3)
+    log(f"[bench] fused, 256-step launches: {fused_k256 / 1e6:.1f} M env-steps/s")
+
     # ---------------- fused rollout that also fills the ring ----------------
     # Alg. 1 steps 2-5 in one kernel: the same rollouts, each step's N
     # transitions added to a 2^22-slot device ring inside the kernel.
@@ -818,6 +843,7 @@ def main():
         "plain_actor_env_steps_per_s": round(pa_rate, 1),
         "fused_over_plain": round(fused_rate / plain_rate, 3),
         "fused_collect": fused_collect,
+        "fused_k256_env_steps_per_s": round(fused_k256, 1),
         "wall_s_timed": round(wall, 4),
         "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)},
         "kernel_source_sha1": kernel_source_hash(),
