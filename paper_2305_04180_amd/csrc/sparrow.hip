@@ -2,7 +2,7 @@
 //
 // Kernels:
 //   k_pack      uint8 grids -> bit-packed rows with an occupied ring (LDS-ready)
-//   k_step<L, TK> one vectorized step (or reset) per launch; each workgroup
+//   k_step<L, TK, U> one vectorized step (or reset) per launch; each workgroup
 //               stages its group's maps into LDS, then every env runs on L lanes
 //   k_rollout<L, QNET, COLL, TK>
 //               persistent K-step rollout: maps staged once per group and kept
@@ -120,7 +120,7 @@ __device__ __forceinline__ int32_t ring_slot(const Params& p, int t, int i) {
 // capacity: s from the library's copy of the current observation, the
 // action as given, s' the observation after the step (for a done env the
 // terminal one when p.ring_terminal is set).
-template <int L, bool TK>
+template <int L, bool TK, int U>
 __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
   extern __shared__ uint32_t lds[];
   const int grp = blockIdx.x;
@@ -162,9 +162,9 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
     reset_now = o.done != 0;
     const bool term_row = coll && p.ring_terminal;
     if (reset_now && (p.final_obs || term_row))
-      observe<L, TK>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn,
-                     p.final_obs ? p.final_obs + (size_t)i * D : nullptr, nullptr, nullptr,
-                     nullptr, false, term_row ? sn_row : RingRow{nullptr, nullptr});
+      observe<L, TK, U>(p, ln, rd, m, e, i, p.g, kNoise, inv_dn,
+                        p.final_obs ? p.final_obs + (size_t)i * D : nullptr, nullptr, nullptr,
+                        nullptr, false, term_row ? sn_row : RingRow{nullptr, nullptr});
     if (reset_now && term_row) sn_row = RingRow{nullptr, nullptr};  // s' written
   }
   bool free_pose = true;  // not done: the step's collision test passed
@@ -173,8 +173,8 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
     if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
     m = stage_window<L>(p, ln, mm, buf, e.y);
   }
-  observe<L, TK>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow, crow,
-                 hk, nullptr, free_pose, sn_row);
+  observe<L, TK, U>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow,
+                    crow, hk, nullptr, free_pose, sn_row);
   if (ln.q == 0) {
     store_env(p.s, i, e);
     if (mode == 0) {
@@ -605,15 +605,33 @@ bool task_is_default(const sparrow_task& t) {
          t.state == SPARROW_STATE_TARGET && t.arrive_reward == 10.0f && t.collide_reward == -10.0f;
 }
 
-template <int L, bool TK>
-int launch_step_LT(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
+template <int L, bool TK, int U>
+int launch_step_LTU(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
   const int threads = std::max(64, gr.epw * L);
   const size_t shmem = (size_t)gr.max_words * 4;
-  HIP_TRY(hipFuncSetAttribute((const void*)k_step<L, TK>,
+  HIP_TRY(hipFuncSetAttribute((const void*)k_step<L, TK, U>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  hipLaunchKernelGGL((k_step<L, TK>), dim3(gr.G), dim3(threads), shmem, e->stream, p, mode);
+  hipLaunchKernelGGL((k_step<L, TK, U>), dim3(gr.G), dim3(threads), shmem, e->stream, p, mode);
   HIP_TRY(hipGetLastError());
   return SPARROW_OK;
+}
+
+// March block size for the plain step: the one whose iterations (P lanes per
+// ray, P * U samples each) cover the samples past the free disk with the
+// smaller issue cost, about (13.5 U + 12) VALU per iteration.
+int step_unroll(const sparrow_env* e, const Params& p, int L) {
+  int R2 = 1;
+  while (R2 < e->cfg.n_rays) R2 <<= 1;
+  const int P = L >= R2 ? L / R2 : 1;
+  const int n = std::max(1, p.M + 1 - p.k_free);
+  auto cost = [&](int U) { return (double)((n + P * U - 1) / (P * U)) * (13.5 * U + 12.0); };
+  return cost(kUnrollLong) < cost(kUnroll) ? kUnrollLong : kUnroll;
+}
+
+template <int L, bool TK>
+int launch_step_LT(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
+  return step_unroll(e, p, L) == kUnrollLong ? launch_step_LTU<L, TK, kUnrollLong>(e, p, gr, mode)
+                                             : launch_step_LTU<L, TK, kUnroll>(e, p, gr, mode);
 }
 
 template <int L>

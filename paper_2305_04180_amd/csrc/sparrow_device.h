@@ -340,67 +340,68 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
   return ln.ballot(hit) != 0ull;
 }
 
-#ifndef SPARROW_UNROLL
-#define SPARROW_UNROLL 10
-#endif
-constexpr int kUnroll = SPARROW_UNROLL;  // samples per lane per iteration (independent LDS reads)
-static_assert(kUnroll <= 31, "hit bits of one block and the sentinel fit a word");
+// Samples per lane per march iteration (independent LDS reads): 10 by
+// default; the plain step also has a 16-sample instantiation for long ranges
+// (the host picks the one that wastes fewer samples past the range).
+constexpr int kUnroll = 10;
+constexpr int kUnrollLong = 16;
 
-// kUnroll samples k0 + u * stride of one ray: all addresses first, then all
+// U samples k0 + u * stride of one ray: all addresses first, then all
 // LDS reads, then the tests, so the reads are in flight together. Sample
 // distances are t_k = (float)k * ds; with ds == 1 that is (float)k, formed
 // here as (float)k0 + (float)(u * stride), exact for k < 2^24. Returns the
-// smallest hitting k of the block, or k0 + kUnroll * stride (one past the
+// smallest hitting k of the block, or k0 + U * stride (one past the
 // block) when none hits; hits past M are the caller's to discard. CLAMPED
 // selects the per-axis clamp (any start) over the march address (a start
 // inside the map).
-template <bool UNIT, bool CLAMPED>
+template <bool UNIT, bool CLAMPED, int U>
 __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, float ux, float uy,
                                             float ds, int k0, int stride) {
-  const uint32_t* adr[kUnroll];
-  int bit[kUnroll];
+  static_assert(U <= 31, "hit bits of one block and the sentinel fit a word");
+  const uint32_t* adr[U];
+  int bit[U];
   const float tk0 = (float)k0;
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
+  for (int u = 0; u < U; ++u) {
     const float tk = UNIT ? tk0 + (float)(u * stride) : (float)(k0 + u * stride) * ds;
     const float px = x + tk * ux;
     const float py = y + tk * uy;
     adr[u] = CLAMPED ? m.word_of(cvt_flr(px), cvt_flr(py), bit[u])
                      : m.word_of_march(cvt_flr(px), cvt_flr(py), bit[u]);
   }
-  uint32_t wv[kUnroll];
+  uint32_t wv[U];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) wv[u] = *adr[u];
-  uint32_t hits = 1u << kUnroll;  // sentinel: no hit -> one past the block
+  for (int u = 0; u < U; ++u) wv[u] = *adr[u];
+  uint32_t hits = 1u << U;  // sentinel: no hit -> one past the block
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) hits |= __builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) << u;
+  for (int u = 0; u < U; ++u) hits |= __builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) << u;
   return k0 + (int)__builtin_ctz(hits) * stride;
 }
 
 // First hit of one ray marched by one lane, from sample k_start (earlier
 // samples are known to be free). Returns -1 when no sample up to M hits.
-template <bool UNIT, bool CLAMPED>
+template <bool UNIT, bool CLAMPED, int U>
 __device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float ux, float uy,
                                           float ds, int M, int k_start) {
   int k0 = k_start;
-  for (;; k0 += kUnroll) {
-    const int kh = sample_block<UNIT, CLAMPED>(m, x, y, ux, uy, ds, k0, 1);
-    if (kh < k0 + kUnroll) return kh <= M ? kh : -1;
-    if (k0 + kUnroll > M) return -1;
+  for (;; k0 += U) {
+    const int kh = sample_block<UNIT, CLAMPED, U>(m, x, y, ux, uy, ds, k0, 1);
+    if (kh < k0 + U) return kh <= M ? kh : -1;
+    if (k0 + U > M) return -1;
   }
 }
 
 // P lanes per ray (P = L / Lr, a power of two): in iteration `it` lane
 // `phase` tests samples it*P*U + u*P + phase; the lanes of the ray then take
 // the minimum, so the ray stops at the first iteration with any hit.
-template <bool UNIT, bool CLAMPED>
+template <bool UNIT, bool CLAMPED, int U>
 __device__ __forceinline__ int march_split(const Slot& m, float x, float y, float ux, float uy,
                                            float ds, int M, int P, int phase, int Lr, int L,
                                            int k_start) {
-  const int span = P * kUnroll;
+  const int span = P * U;
   for (int kb = k_start;; kb += span) {
     // a lane with no hit reports kb + phase + span: past the block either way
-    int kl = sample_block<UNIT, CLAMPED>(m, x, y, ux, uy, ds, kb + phase, P);
+    int kl = sample_block<UNIT, CLAMPED, U>(m, x, y, ux, uy, ds, kb + phase, P);
     if (L == 64 && Lr == 32) {
       // partner lane is lane ^ 32: v_permlane32_swap leaves {own, partner}
       // in the two results of every lane, with no LDS round trip
@@ -446,7 +447,7 @@ __device__ __forceinline__ RayDirs<L> load_rays(const float2* rays, int nr, int 
 // ------------------------------------------------------------------------
 // Observation of one env: rays (march + noise), velocities, target.
 // ------------------------------------------------------------------------
-template <int L, bool TK = false>
+template <int L, bool TK = false, int U = kUnroll>
 __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, const RayDirs<L>& rd, const Slot& m,
                         Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
                         float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
@@ -485,12 +486,12 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       // 16-lane envs, which march several rays per lane, keep one path to
       // stay within the register budget)
       if (L >= 32 && p.ds == 1.0f && inside)
-        kh = P == 1 ? march_lane<true, false>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
-                    : march_split<true, false>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
+        kh = P == 1 ? march_lane<true, false, U>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                    : march_split<true, false, U>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
                                                k_start);
       else
-        kh = P == 1 ? march_lane<false, true>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
-                    : march_split<false, true>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
+        kh = P == 1 ? march_lane<false, true, U>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                    : march_split<false, true, U>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
                                                k_start);
     }
     if (valid && phase == 0) {
