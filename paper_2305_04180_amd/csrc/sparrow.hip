@@ -72,10 +72,15 @@ __global__ void k_actions(int32_t n, uint32_t g, uint32_t key0, uint32_t key1,
 }
 
 // Copy the group's maps into LDS (16-byte words; offsets are multiples of 4).
+// With march padding, the words after the group's last map up to the end of
+// the maps region are set too (a group with fewer or smaller maps than the
+// largest leaves stale words there).
 __device__ __forceinline__ void stage_maps(const Params& p, int grp, uint32_t* lds) {
+  int end = 0;
   for (int s = 0; s < p.epw; ++s) {
     const int4 sl = p.slots[grp * p.epw + s];
     if (sl.x < 0) break;
+    end = sl.z + sl.w;
     const uint4* src = reinterpret_cast<const uint4*>(p.words + p.meta[sl.y].off);
     uint4* dst = reinterpret_cast<uint4*>(lds + sl.z);
     const int n4 = sl.w >> 2, bd = blockDim.x;
@@ -90,6 +95,8 @@ __device__ __forceinline__ void stage_maps(const Params& p, int grp, uint32_t* l
     }
     for (; w < n4; w += bd) dst[w] = src[w];
   }
+  if (p.march_pad > 0)
+    for (int w = end + (int)threadIdx.x; w < p.maps_words; w += blockDim.x) lds[w] = 0xFFFFFFFFu;
 }
 
 __device__ __forceinline__ Slot make_slot(const Params& p, const int4& sl, const uint32_t* lds) {
@@ -208,6 +215,12 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
   const int N = p.n_envs, D = p.obs_dim;
   typename QC::Weights qw;
   qw.load(qp, threadIdx.x);
+  // LDS: [march_pad set words][maps region][march_pad set words][actor]
+  uint32_t* const maps = lds + p.march_pad;
+  for (int k = threadIdx.x; k < p.march_pad; k += blockDim.x) {
+    lds[k] = 0xFFFFFFFFu;
+    maps[p.maps_words + k] = 0xFFFFFFFFu;
+  }
   if constexpr (kQ) {
     // clear the actor's LDS so padded rows and columns hold finite values
     uint32_t* a = lds + qp.lds_base_words;
@@ -216,7 +229,7 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
   }
   for (int grp = blockIdx.x; grp < p.n_groups; grp += gridDim.x) {
     __syncthreads();
-    stage_maps(p, grp, lds);
+    stage_maps(p, grp, maps);
     int4 sl = make_int4(-1, 0, 0, 0);
     if (slot < p.epw) sl = p.slots[grp * p.epw + slot];
     const bool live = sl.x >= 0;
@@ -226,7 +239,7 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
     float inv_dn = 0.0f, eps = 0.0f;
     if (live) {
       e = load_env(p.s, i);
-      m = make_slot(p, sl, lds);
+      m = make_slot(p, sl, maps);
       inv_dn = p.inv_dn[sl.y];
       if constexpr (kQ) eps = p.eps[i];
     }
@@ -306,7 +319,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
               free_pose = reset_env<L>(p, ln, m, e, i, g);
               if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
             }
-            observe<L, TK>(p, ln, rd, m, e, i, g, (terminal || !o.done) ? kNoise : kNoiseReset,
+            observe<L, TK, kUnroll, true>(p, ln, rd, m, e, i, g,
+                                          (terminal || !o.done) ? kNoise : kNoiseReset,
                            inv_dn,
                        terminal ? nullptr : orow, terminal ? nullptr : crow,
                        terminal ? nullptr : hk, terminal ? nullptr : act_in,
@@ -324,8 +338,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
             free_pose = reset_env<L>(p, ln, m, e, i, g);
             if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
           }
-          observe<L, TK>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise, inv_dn, orow, crow,
-                         hk, act_in, free_pose);
+          observe<L, TK, kUnroll, true>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise,
+                                        inv_dn, orow, crow, hk, act_in, free_pose);
         }
         if (ln.q == 0) {
           const size_t o_idx = (size_t)t * N + i;
@@ -603,6 +617,28 @@ int check_L(int L) { return L == 16 || L == 32 || L == 64; }
 bool task_is_default(const sparrow_task& t) {
   return t.n_actions == SPARROW_N_ACTIONS && t.reward == SPARROW_REWARD_PROGRESS &&
          t.state == SPARROW_STATE_TARGET && t.arrive_reward == 10.0f && t.collide_reward == -10.0f;
+}
+
+// Set words on each side of a rollout's maps region that let its march go
+// unclamped (0: it clamps). Only for the unit-step march (ds = 1, 32 or 64
+// lanes per env) over maps that all have the same row length, and only if
+// both pads fit the LDS left over (`spare` words). The march tests at most
+// P U samples (P lanes per ray, U samples per lane) past the last sample
+// inside the map. Samples n apart differ by at most n + 10^-3 per axis (a
+// unit direction, and binary32 rounding of coordinates and products below
+// 2^10 on maps of side <= 512), so their cells by at most n + 1: those
+// samples lie within P U + 1 cells of the map, and (P U + 4) rows and four
+// words cover them with room to spare.
+int march_pad_words(const sparrow_env* e, int L, int U, int spare) {
+  if (L < 32 || e->cfg.march_step != 1.0f || e->h_meta.empty()) return 0;
+  const int wpr = e->h_meta[0].wpr;
+  for (const MapMeta& m : e->h_meta)
+    if (m.wpr != wpr) return 0;
+  int R2 = 1;
+  while (R2 < e->cfg.n_rays) R2 <<= 1;
+  const int P = L >= R2 ? L / R2 : 1;
+  const int pad = ((P * U + 4) * wpr + 4 + 3) & ~3;
+  return 2 * pad <= spare ? pad : 0;
 }
 
 template <int L, bool TK, int U>
@@ -1073,8 +1109,9 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   Groups* gr = nullptr;
   int rc = get_groups(e, epw, budget_words, &gr);
   if (rc) return rc;
+  const int pad = march_pad_words(e, L, kUnroll, budget_words - gr->max_words);
   const int threads = q ? kQThreads : std::max(64, epw * L);
-  const size_t shmem = (size_t)reserve + (size_t)gr->max_words * 4;
+  const size_t shmem = (size_t)reserve + (size_t)(gr->max_words + 2 * pad) * 4;
   const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0, ring != nullptr,
                                   task_is_default(e->task));
   HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
@@ -1088,6 +1125,8 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   p.n_groups = gr->G;
   p.epw = gr->epw;
   p.K_steps = K;
+  p.march_pad = pad;
+  p.maps_words = gr->max_words;
   p.obs = obs;
   p.r_actions = actions;
   p.r_reward = reward;
@@ -1101,7 +1140,7 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
     if (rc) return rc;
   }
   QParams qp = e->qp;
-  qp.lds_base_words = gr->max_words;
+  qp.lds_base_words = gr->max_words + 2 * pad;
   void* args[] = {&p, &qp};
   if (!use_graph) {
     HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(threads), args, shmem, e->stream));

@@ -152,6 +152,9 @@ struct Params {
   float near_r;             // robot radius + the r_d margin
   float w_d1, w_d2, w_v, w_a, w_d;  // Eq. (11) weights
   int32_t win_rows;         // rows staged on each side of the robot's row (windowed step)
+  // k_rollout: set words before and after the group's maps in LDS (0: no
+  // padding, the march clamps), and the words of the maps region
+  int32_t march_pad, maps_words;
   float ds, range, inv_R, robot_r, arrive_r, omega_max;
   float dt_lo, dt_span, K_lo, K_span, mu_lo, mu_span, vmax_lo, vmax_span, sigma_lo,
       sigma_span;
@@ -298,6 +301,21 @@ struct Slot {
     asm("" : "+v"(w));
     return w1 + w;
   }
+  // The march's address with no clamp at all, for a whole-map slot staged
+  // between set words (see k_rollout's LDS layout): every map of the env has
+  // the same row length n, the slots sit back to back with their set
+  // alignment words, and at least march_pad set words lie before the first
+  // and after the last. Then rows -2 and H + 1 of a slot (and the word before
+  // row -2) read as set, so the first sample outside the map (within two
+  // cells of the last one inside) still reads its correct, set bit; later
+  // samples of the block, at most P U + 1 cells further, stay within the
+  // padding and never count.
+  __device__ __forceinline__ const uint32_t* word_of_free(int ix, int iy, int& bit) const {
+    bit = ix;
+    int w = __mul24(iy, wpr) + (ix >> 5);
+    asm("" : "+v"(w));
+    return w1 + w;
+  }
   __device__ __forceinline__ const uint32_t* word_of(int ix, int iy, int& bit) const {
     ix = med3i(ix, -1, W);
     iy = med3i(iy, -1, H);
@@ -346,15 +364,19 @@ __device__ __forceinline__ bool collides_env(const Lanes<L>& ln, const Slot& m, 
 constexpr int kUnroll = 10;
 constexpr int kUnrollLong = 16;
 
+// Sample addresses: per-axis clamp (any start), the word index clamped to
+// the slot (a start inside the map), or no clamp (a start inside the map, in
+// a padded whole-map layout).
+enum : int { kAddrAxis = 0, kAddrWord = 1, kAddrFree = 2 };
+
 // U samples k0 + u * stride of one ray: all addresses first, then all
 // LDS reads, then the tests, so the reads are in flight together. Sample
 // distances are t_k = (float)k * ds; with ds == 1 that is (float)k, formed
 // here as (float)k0 + (float)(u * stride), exact for k < 2^24. Returns the
 // smallest hitting k of the block, or k0 + U * stride (one past the
-// block) when none hits; hits past M are the caller's to discard. CLAMPED
-// selects the per-axis clamp (any start) over the march address (a start
-// inside the map).
-template <bool UNIT, bool CLAMPED, int U>
+// block) when none hits; hits past M are the caller's to discard. ADDR is
+// one of the address modes above.
+template <bool UNIT, int ADDR, int U>
 __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, float ux, float uy,
                                             float ds, int k0, int stride) {
   static_assert(U <= 31, "hit bits of one block and the sentinel fit a word");
@@ -366,26 +388,31 @@ __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, flo
     const float tk = UNIT ? tk0 + (float)(u * stride) : (float)(k0 + u * stride) * ds;
     const float px = x + tk * ux;
     const float py = y + tk * uy;
-    adr[u] = CLAMPED ? m.word_of(cvt_flr(px), cvt_flr(py), bit[u])
-                     : m.word_of_march(cvt_flr(px), cvt_flr(py), bit[u]);
+    adr[u] = ADDR == kAddrAxis   ? m.word_of(cvt_flr(px), cvt_flr(py), bit[u])
+             : ADDR == kAddrWord ? m.word_of_march(cvt_flr(px), cvt_flr(py), bit[u])
+                                 : m.word_of_free(cvt_flr(px), cvt_flr(py), bit[u]);
   }
   uint32_t wv[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) wv[u] = *adr[u];
+  // hit bit u of the block: one shift-or per sample on the extracted bit
   uint32_t hits = 1u << U;  // sentinel: no hit -> one past the block
 #pragma unroll
-  for (int u = 0; u < U; ++u) hits |= __builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u) << u;
+  for (int u = 0; u < U; ++u) {
+    const uint32_t b = __builtin_amdgcn_ubfe(wv[u], (uint32_t)bit[u], 1u);
+    asm("v_lshl_or_b32 %0, %1, %2, %0" : "+v"(hits) : "v"(b), "I"(u));
+  }
   return k0 + (int)__builtin_ctz(hits) * stride;
 }
 
 // First hit of one ray marched by one lane, from sample k_start (earlier
 // samples are known to be free). Returns -1 when no sample up to M hits.
-template <bool UNIT, bool CLAMPED, int U>
+template <bool UNIT, int ADDR, int U>
 __device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float ux, float uy,
                                           float ds, int M, int k_start) {
   int k0 = k_start;
   for (;; k0 += U) {
-    const int kh = sample_block<UNIT, CLAMPED, U>(m, x, y, ux, uy, ds, k0, 1);
+    const int kh = sample_block<UNIT, ADDR, U>(m, x, y, ux, uy, ds, k0, 1);
     if (kh < k0 + U) return kh <= M ? kh : -1;
     if (k0 + U > M) return -1;
   }
@@ -394,14 +421,14 @@ __device__ __forceinline__ int march_lane(const Slot& m, float x, float y, float
 // P lanes per ray (P = L / Lr, a power of two): in iteration `it` lane
 // `phase` tests samples it*P*U + u*P + phase; the lanes of the ray then take
 // the minimum, so the ray stops at the first iteration with any hit.
-template <bool UNIT, bool CLAMPED, int U>
+template <bool UNIT, int ADDR, int U>
 __device__ __forceinline__ int march_split(const Slot& m, float x, float y, float ux, float uy,
                                            float ds, int M, int P, int phase, int Lr, int L,
                                            int k_start) {
   const int span = P * U;
   for (int kb = k_start;; kb += span) {
     // a lane with no hit reports kb + phase + span: past the block either way
-    int kl = sample_block<UNIT, CLAMPED, U>(m, x, y, ux, uy, ds, kb + phase, P);
+    int kl = sample_block<UNIT, ADDR, U>(m, x, y, ux, uy, ds, kb + phase, P);
     if (L == 64 && Lr == 32) {
       // partner lane is lane ^ 32: v_permlane32_swap leaves {own, partner}
       // in the two results of every lane, with no LDS round trip
@@ -447,7 +474,10 @@ __device__ __forceinline__ RayDirs<L> load_rays(const float2* rays, int nr, int 
 // ------------------------------------------------------------------------
 // Observation of one env: rays (march + noise), velocities, target.
 // ------------------------------------------------------------------------
-template <int L, bool TK = false, int U = kUnroll>
+// PADDED: the slot is a whole map in the padded layout (k_rollout); its
+// start-inside march takes the unclamped address when p.march_pad > 0 and the
+// per-axis clamp otherwise. Else (windowed slots) it takes the word clamp.
+template <int L, bool TK = false, int U = kUnroll, bool PADDED = false>
 __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, const RayDirs<L>& rd, const Slot& m,
                         Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
                         float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
@@ -485,14 +515,15 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       // (the generic path gives the same t_k = (float)k * 1 when ds == 1;
       // 16-lane envs, which march several rays per lane, keep one path to
       // stay within the register budget)
-      if (L >= 32 && p.ds == 1.0f && inside)
-        kh = P == 1 ? march_lane<true, false, U>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
-                    : march_split<true, false, U>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
-                                               k_start);
+      constexpr int kUnitAddr = PADDED ? kAddrFree : kAddrWord;
+      if (L >= 32 && p.ds == 1.0f && inside && (!PADDED || p.march_pad > 0))
+        kh = P == 1 ? march_lane<true, kUnitAddr, U>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                    : march_split<true, kUnitAddr, U>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr,
+                                                      L, k_start);
       else
-        kh = P == 1 ? march_lane<false, true, U>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
-                    : march_split<false, true, U>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase, Lr, L,
-                                               k_start);
+        kh = P == 1 ? march_lane<false, kAddrAxis, U>(m, e.x, e.y, ux, uy, p.ds, p.M, k_start)
+                    : march_split<false, kAddrAxis, U>(m, e.x, e.y, ux, uy, p.ds, p.M, P, phase,
+                                                       Lr, L, k_start);
     }
     if (valid && phase == 0) {
       const float d = kh < 0 ? p.range : (float)kh * p.ds;
