@@ -208,3 +208,38 @@ def test_c5_full_collection_loop_sampled(torch_gpu):
     lid = ids[live]
     compare_state(gf[lid], gi[lid], of[lid], oi[lid], "c5 final state")
     assert env.status() == 0 and ring.status() == 0
+
+
+def test_rollout_partial_group_after_full_group(torch_gpu):
+    """One more group than the grid has workgroups (eight envs per group, one
+    workgroup per CU): a workgroup stages a full group and then the last,
+    partial one, whose maps do not overwrite all of the first group's words
+    in LDS. Uniform actions, every env against the oracle."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    N, K = 8 * n_cu + 5, 16
+    cfg = inputs.workload("c2", n_envs=N)
+    banner(f"rollout uniform c2 N={N} ({n_cu} CUs) K={K}")
+    maps = inputs.make_maps(cfg)
+    env = sparrow.Env(cfg, maps)
+    assert env.get_variant(1) == (8, 64)
+    orc = oracle.Oracle(cfg, maps)
+    env.reset()
+    orc.reset()
+    for rep in range(2):
+        acts, rew, done, obs = env.rollout(K, use_qnet=False)
+        torch.cuda.synchronize()
+        for t in range(K):
+            a = orc.uniform_actions()
+            r = orc.step(a, hit_k=True)
+            w = f"rollout {rep} t={t}"
+            compare_exact(to_np(acts[t]), a, "actions", w)
+            compare_exact(to_np(rew[t]), r["reward"], "reward", w)
+            compare_exact(to_np(done[t]), r["done"], "done", w)
+        compare_obs(to_np(obs), r["obs"], cfg["n_rays"], True, f"rollout {rep} final obs")
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", f"rollout {rep} final")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf, gi, of, oi, "partial group final")
