@@ -572,12 +572,25 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       o[4] = e.va / p.omega_max;
     }
     const int ns = 4 + smode;
+    // the state's four leading values as one 16-byte store where the row
+    // allows it (one store from this lane, not four)
+    const float4 o4 = make_float4(o[0], o[1], o[2], o[3]);
+    auto put = [&](float* row) {
+      if ((reinterpret_cast<uintptr_t>(row + nr) & 15u) == 0u) {
+        *reinterpret_cast<float4*>(row + nr) = o4;
+      } else {
+        for (int a = 0; a < 4; ++a) row[nr + a] = o[a];
+      }
+      if (ns == 5) row[nr + 4] = o[4];
+    };
+    if (dst) put(dst);
+    if (dst2) put(dst2);
+    if (dst_bf16) {
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
-      if (a >= ns) break;
-      if (dst) dst[nr + a] = o[a];
-      if (dst2) dst2[nr + a] = o[a];
-      if (dst_bf16) dst_bf16[nr + a] = bf16_rne(o[a]);
+      for (int a = 0; a < 5; ++a) {
+        if (a >= ns) break;
+        dst_bf16[nr + a] = bf16_rne(o[a]);
+      }
     }
     if (qa.c || qb.c) {
       // the four binary16 codes as one 8-byte store (rows are 8-byte aligned)
