@@ -572,8 +572,8 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       o[4] = e.va / p.omega_max;
     }
     const int ns = 4 + smode;
-    // the state's four leading values as one 16-byte store where the row
-    // allows it (one store from this lane, not four)
+    // the state's four leading values through one float4 store where the
+    // row is 16-byte aligned, else one by one
     const float4 o4 = make_float4(o[0], o[1], o[2], o[3]);
     auto put = [&](float* row) {
       if ((reinterpret_cast<uintptr_t>(row + nr) & 15u) == 0u) {
