@@ -557,8 +557,8 @@ def greedy_agreement(env, cfg, maps, dims, w, b):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; envs are independent, so N GPUs would "
-              "each run their own shard with no per-step exchange (see the design notes). "
+        print("bench.py measures one GPU; envs are independent, so N GPUs would each run "
+              "their own shard with no per-step exchange (see the design notes). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -9,7 +9,7 @@
  * includes, links or calls it.
  *
  * Reading of the storage format (the paper stores full-precision tensors;
- * this build stores a compact transition):
+ * the device buffer stores a compact transition):
  *   - ranges (the first n_rays observation entries, each in [0, 1]) as
  *     uint8 q = nearest integer to 255 * clamp(o, 0, 1), ties to even, with
  *     the product rounded to binary32 first; read back as the binary32

@@ -67,4 +67,5 @@ def asm(out_dir: str) -> list[str]:
 if __name__ == "__main__":
     build(verbose=True)
     if len(sys.argv) > 1 and sys.argv[1] == "asm":
-        print(asm(sys.argv[2] if len(sys.argv) > 2 else "_work/asm"))
+        import tempfile
+        print(asm(sys.argv[2] if len(sys.argv) > 2 else os.path.join(tempfile.gettempdir(), "sparrow_asm")))
