@@ -861,7 +861,15 @@ __device__ __forceinline__ Slot stage_window(const Params& p, const Lanes<L>& ln
   const int n4 = (int)((we - ws4 + 3u) >> 2);
   const uint4* src = reinterpret_cast<const uint4*>(p.words + ws4);
   uint4* dst = reinterpret_cast<uint4*>(buf);
+  // eight 16-byte loads in flight per lane before their LDS stores
   int k = ln.q;
+  for (; k + 7 * L < n4; k += 8 * L) {
+    uint4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[k + u * L];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dst[k + u * L] = v[u];
+  }
   for (; k + 3 * L < n4; k += 4 * L) {
     uint4 v[4];
 #pragma unroll
