@@ -224,3 +224,65 @@ def test_windowed_step_extreme_poses(torch_gpu):
         of, oi = orc.get_state()
         compare_state(gf, gi, of, oi, f"window {variant} final")
         assert env.status() == orc.status
+
+
+def rollout_lockstep(cfg, maps, torch, K, variants=((8, 64), (8, 32))):
+    """Fused rollouts (uniform actions) against the oracle stepped K times."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    noisy = cfg["sigma_hi"] > 0
+    for epw, L in variants:
+        env = sparrow.Env(cfg, maps)
+        env.set_variant(1, epw, L)
+        orc = oracle.Oracle(cfg, maps)
+        env.reset()
+        orc.reset()
+        acts, rew, done, obs = env.rollout(K, use_qnet=False)
+        torch.cuda.synchronize()
+        w0 = f"{cfg.get('label', cfg['name'])} rollout {(epw, L)}"
+        for t in range(K):
+            a = orc.uniform_actions()
+            r = orc.step(a, hit_k=True)
+            compare_exact(to_np(acts[t]), a, "actions", f"{w0} t={t}")
+            compare_exact(to_np(rew[t]), r["reward"], "reward", f"{w0} t={t}")
+            compare_exact(to_np(done[t]), r["done"], "done", f"{w0} t={t}")
+        compare_obs(to_np(obs), r["obs"], cfg["n_rays"], noisy, f"{w0} final")
+        compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", f"{w0} final")
+        gf, gi = env.get_state()
+        of, oi = orc.get_state()
+        compare_state(gf, gi, of, oi, f"{w0} final state")
+
+
+def test_fused_rollout_edge_maps_and_ray_counts(torch_gpu):
+    """The fused rollout's unit-step march at its extremes: 512^2 maps with
+    128 rays to range 255; one ray (all 64 lanes of the env on it, the
+    longest overshoot past a hit); 7 rays over a full circle; tiny unbordered
+    maps of one word per row; and maps of different row lengths (the march
+    then clamps per axis)."""
+    torch = torch_gpu
+    cfg = inputs.workload("c2", n_envs=9, n_rays=128, range=255.0, robot_r=8.0, sides=(512,),
+                          label="max")
+    banner("rollout: 512^2 maps, 128 rays, range 255, r = 8")
+    rollout_lockstep(cfg, inputs.make_maps(cfg), torch, 24)
+    cfg = inputs.workload("c2", n_envs=1, n_rays=1, fov=0.0, label="one")
+    banner("rollout: N = 1, one ray")
+    rollout_lockstep(cfg, inputs.make_maps(cfg), torch, 40, variants=((8, 64),))
+    cfg = inputs.workload("c2", n_envs=3, n_rays=7, fov=2 * math.pi, label="circle")
+    banner("rollout: N = 3, 7 rays over a full circle")
+    rollout_lockstep(cfg, inputs.make_maps(cfg), torch, 30, variants=((8, 64),))
+    g_a = np.zeros((20, 25), np.uint8)
+    g_a[8:12, 5:9] = 1
+    g_b = np.zeros((25, 20), np.uint8)
+    g_b[3:5, 10:18] = 1
+    cfg = inputs.workload("c2", n_envs=6, robot_r=2.0, arrive_r=2.0, range=40.0,
+                          label="tiny")
+    banner("rollout: tiny unbordered maps, one word per row")
+    rollout_lockstep(cfg, inputs.single_maps([g_a, g_b], env_to_map=[0, 1, 0, 1, 1, 0]),
+                     torch, 30)
+    g_empty = np.zeros((40, 40), np.uint8)
+    g_open = np.zeros((300, 200), np.uint8)
+    g_open[100:110, 50:150] = 1
+    cfg = inputs.workload("c2", n_envs=5, label="mixed")
+    banner("rollout: maps of different row lengths")
+    rollout_lockstep(cfg, inputs.single_maps([g_empty, g_open], env_to_map=[0, 1, 1, 0, 1]),
+                     torch, 30)
