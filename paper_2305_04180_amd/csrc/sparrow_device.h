@@ -547,7 +547,64 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       if (qb.r) qb.r[j] = quant_u8(o);
     }
   }
-  if (ln.q == 0) {
+  if constexpr (PADDED) {
+    if (ln.q == 0) {
+      const float dx = e.tx - e.x, dy = e.ty - e.y;
+      const float bx = dx * fx + dy * fy;
+      const float by = dy * fx - dx * fy;
+      const float bearing = atan2f(by, bx) * kInvPiF;
+      float o[5];
+      const int smode = TaskOf<TK>::state(p);
+      if (smode == 0) {
+        const float d2 = dx * dx + dy * dy;
+        o[0] = e.vl / e.vmax;
+        o[1] = e.va / p.omega_max;
+        o[2] = sqrtf(d2) * inv_dn;
+        o[3] = bearing;
+        o[4] = 0.0f;
+      } else {
+        // relative pose (Sec. 4.3.1): position relative to the target over
+        // the planning distance, orientation relative to the target, then the
+        // velocities
+        o[0] = (e.x - e.tx) * p.inv_D;
+        o[1] = (e.y - e.ty) * p.inv_D;
+        o[2] = bearing;
+        o[3] = e.vl / e.vmax;
+        o[4] = e.va / p.omega_max;
+      }
+      const int ns = 4 + smode;
+      // the state's four leading values through one float4 store where the
+      // row is 16-byte aligned, else one by one
+      const float4 o4 = make_float4(o[0], o[1], o[2], o[3]);
+      auto put = [&](float* row) {
+        if ((reinterpret_cast<uintptr_t>(row + nr) & 15u) == 0u) {
+          *reinterpret_cast<float4*>(row + nr) = o4;
+        } else {
+          for (int a = 0; a < 4; ++a) row[nr + a] = o[a];
+        }
+        if (ns == 5) row[nr + 4] = o[4];
+      };
+      if (dst) put(dst);
+      if (dst2) put(dst2);
+      if (dst_bf16) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+          if (a >= ns) break;
+          dst_bf16[nr + a] = bf16_rne(o[a]);
+        }
+      }
+      if (qa.c || qb.c) {
+        // the four binary16 codes as one 8-byte store (rows are 8-byte aligned)
+        const uint2 h = make_uint2((uint32_t)f16_bits(o[0]) | ((uint32_t)f16_bits(o[1]) << 16),
+                                   (uint32_t)f16_bits(o[2]) | ((uint32_t)f16_bits(o[3]) << 16));
+        if (qa.c) *reinterpret_cast<uint2*>(qa.c) = h;
+        if (qb.c) *reinterpret_cast<uint2*>(qb.c) = h;
+      }
+    }
+  } else {
+    // the plain step: every lane computes the state values (the same issue
+    // cost as one lane) and lane a < ns writes value a, one store
+    // instruction per row
     const float dx = e.tx - e.x, dy = e.ty - e.y;
     const float bx = dx * fx + dy * fy;
     const float by = dy * fx - dx * fy;
@@ -562,9 +619,6 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       o[3] = bearing;
       o[4] = 0.0f;
     } else {
-      // relative pose (Sec. 4.3.1): position relative to the target over
-      // the planning distance, orientation relative to the target, then the
-      // velocities
       o[0] = (e.x - e.tx) * p.inv_D;
       o[1] = (e.y - e.ty) * p.inv_D;
       o[2] = bearing;
@@ -572,28 +626,14 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       o[4] = e.va / p.omega_max;
     }
     const int ns = 4 + smode;
-    // the state's four leading values through one float4 store where the
-    // row is 16-byte aligned, else one by one
-    const float4 o4 = make_float4(o[0], o[1], o[2], o[3]);
-    auto put = [&](float* row) {
-      if ((reinterpret_cast<uintptr_t>(row + nr) & 15u) == 0u) {
-        *reinterpret_cast<float4*>(row + nr) = o4;
-      } else {
-        for (int a = 0; a < 4; ++a) row[nr + a] = o[a];
-      }
-      if (ns == 5) row[nr + 4] = o[4];
-    };
-    if (dst) put(dst);
-    if (dst2) put(dst2);
-    if (dst_bf16) {
-#pragma unroll
-      for (int a = 0; a < 5; ++a) {
-        if (a >= ns) break;
-        dst_bf16[nr + a] = bf16_rne(o[a]);
-      }
+    const int a = ln.q;
+    const float mine = a == 0 ? o[0] : a == 1 ? o[1] : a == 2 ? o[2] : a == 3 ? o[3] : o[4];
+    if (a < ns) {
+      if (dst) dst[nr + a] = mine;
+      if (dst2) dst2[nr + a] = mine;
+      if (dst_bf16) dst_bf16[nr + a] = bf16_rne(mine);
     }
-    if (qa.c || qb.c) {
-      // the four binary16 codes as one 8-byte store (rows are 8-byte aligned)
+    if (a == 0 && (qa.c || qb.c)) {
       const uint2 h = make_uint2((uint32_t)f16_bits(o[0]) | ((uint32_t)f16_bits(o[1]) << 16),
                                  (uint32_t)f16_bits(o[2]) | ((uint32_t)f16_bits(o[3]) << 16));
       if (qa.c) *reinterpret_cast<uint2*>(qa.c) = h;
