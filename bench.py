@@ -113,7 +113,7 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(cfg, maps, w, b, eps, seconds, cores=None):
+def cpu_baseline(cfg, maps, w, b, seconds, cores=None):
     """The oracle (FP32 step + FP64 Q-network + VEM) on the host cores, on a
     bounded sample of envs, one Python thread per core over env shards (the
     C calls release the GIL)."""
@@ -127,6 +127,9 @@ def cpu_baseline(cfg, maps, w, b, eps, seconds, cores=None):
     obs, _ = o.reset()
     dims = cfg["qnet"]
     D = o.obs_dim
+    # the oracle's own VEM schedule over the full batch, first n_sample envs
+    eps = oracle.vem_epsilon(cfg["n_envs"], cfg["n_envs"], cfg["eps"][0],
+                             cfg["eps"][1] - cfg["eps"][0])
     eps_s = np.ascontiguousarray(eps[:n_sample])
     shards = np.array_split(np.arange(n_sample), cores)
     acts = np.zeros(n_sample, np.int32)
@@ -174,9 +177,8 @@ def collection_c5(cfg, maps, steps, warmup, fused_add=False):
     D = nr + 4
     dims = cfg["qnet"]
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
     env = sparrow.Env(cfg, maps)
-    env.set_qnet(dims, w, b, eps)
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0]))
     ring = sparrow.Ring(1 << 22, nr, seed=cfg["seed"])
     cur = env.reset()
     env.autotune(steps=4)
@@ -283,8 +285,7 @@ def paper_task(steps=2048, K=64):
     dims = cfg["qnet"]
     w, b, _ = inputs.qnet_weights(dims)
     env = sparrow.Env(cfg, maps)
-    env.set_qnet(dims, w, b, sparrow.vem_epsilon(N, N, cfg["eps"][0],
-                                                 cfg["eps"][1] - cfg["eps"][0]))
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0]))
     env.reset()
     env.autotune(steps=8)
     acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
@@ -392,7 +393,7 @@ def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
     s_learn = torch.cuda.Stream()
     with torch.cuda.stream(s_act):
         env = sparrow.Env(cfg, maps, stream=s_act)
-        env.set_qnet(dims, wb, b, sparrow.vem_epsilon(N, N, 0.01, 0.8))
+        env.set_qnet(dims, wb, b, env.vem_epsilon(N, 0.01, 0.8))
         ring = sparrow.Ring(1 << 20, cfg["n_rays"], seed=3, stream=s_act)
         cur = env.reset()
         nxt, fo = torch.zeros_like(cur), torch.zeros_like(cur)
@@ -585,10 +586,9 @@ def main():
     log(f"[bench] maps ready in {time.time() - t0:.1f}s")
     dims = cfg["qnet"]
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
 
     env = sparrow.Env(cfg, maps)
-    env.set_qnet(dims, w, b, eps)
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0]))
     env.reset()
     tune = {}
     if not args.no_tune:
@@ -789,8 +789,8 @@ def main():
     precision = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(cfg, maps, w, b, eps, args.cpu_seconds)
-        one = cpu_baseline(cfg, maps, w, b, eps, args.cpu_seconds / 3, cores=1)
+        cpu = cpu_baseline(cfg, maps, w, b, args.cpu_seconds)
+        one = cpu_baseline(cfg, maps, w, b, args.cpu_seconds / 3, cores=1)
         cpu["single_thread_value"] = one["value"]
         cpu["cpu_model"] = cpu_model()
         cpu["nproc"] = os.cpu_count()

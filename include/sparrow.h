@@ -193,9 +193,23 @@ int32_t sparrow_obs_dim(const sparrow_env *env);
  * patterns, [W1 (h1 x obs_dim) | W2 (h2 x h1) | W3 (A x h2)], each row-major
  * [out][in] (Sec. 4.3.2 fully connected layers with ReLU). b_f32: dev
  * [h1 + h2 + A]. eps: dev [N] per-env exploration probability of VEM
- * (Sec. 3.1.1). All three are copied. */
+ * (Sec. 3.1.1; sparrow_vem_epsilon computes the schedule). All three are
+ * copied; the call synchronises the stream. On any failure the network
+ * installed before the call (if any) stays installed and usable. */
 int sparrow_set_qnet(sparrow_env *env, const int32_t *dims, const uint16_t *w_bf16,
                      const float *b_f32, const float *eps);
+
+/* VEM's per-env exploration probabilities for a fixed exploring interval
+ * (Sec. 3.1.1: the last m envs form the exploring interval, whose
+ * probabilities rise linearly across it from e_min to e_min + e_max; the
+ * other envs hold e_min):
+ *   eps_i = e_min for i < n_envs - m, else e_min + e_max * (i - (n_envs - m))
+ *       / (m - 1) (m = 1: e_min + e_max),
+ * in binary64 rounded once to binary32. Writes dev eps [n_envs] on the env's
+ * stream, ready for sparrow_set_qnet (m = n_envs, e_min 0.01, e_max 0.29
+ * gives the workloads' linspace(0.01, 0.3)). EINVAL unless 0 <= m <= n_envs
+ * and e_min, e_max >= 0. */
+int sparrow_vem_epsilon(sparrow_env *env, int32_t m, double e_min, double e_max, float *eps);
 
 /* VEM whose exploring interval shrinks during training (Sec. 3.1.1: "the OR
  * is linearly diminished"; Table 6: OR 16 -> 3 over 500K transitions, E_min

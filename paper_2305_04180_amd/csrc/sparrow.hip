@@ -10,6 +10,7 @@
 //               Q-network + VEM (Alg. 1 steps 2-4 fused); COLL also adds each
 //               step's transitions to the experience buffer (step 5)
 //   k_actions   uniform random actions (one thread per env)
+//   k_vem_eps   per-env exploration probabilities of VEM (one thread per env)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -69,6 +70,14 @@ __global__ void k_actions(int32_t n, uint32_t g, uint32_t key0, uint32_t key1,
   if (i >= n) return;
   const U4 w = philox((uint32_t)i, g, kActionUniform, 0u, key0, key1);
   actions[i] = scale_u32(w.x, (uint32_t)n_actions);
+}
+
+// VEM's per-env exploration probability (Sec. 3.1.1) for a fixed exploring
+// interval: the schedule's value at any step, since its decay is off.
+__global__ void k_vem_eps(VemSchedule v, float* __restrict__ eps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= v.n) return;
+  eps[i] = vem_eps(v, i, 0u);
 }
 
 // Copy the group's maps into LDS (16-byte words; offsets are multiples of 4).
@@ -992,28 +1001,29 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
     return fail(SPARROW_EUNSUPPORTED,
                 "the actor supports (h1, h2) = (256, 256) or (512, 512) with obs_dim <= 96, "
                 "and (256, 128) with obs_dim <= 64");
-  if (e->q_block) {
-    (void)hipFree(e->q_block);
-    e->q_block = nullptr;
-  }
-  if (e->eps) {
-    (void)hipFree(e->eps);
-    e->eps = nullptr;
-  }
   QParams qp{};
   qp.d0 = d0;
   qp.h1 = h1;
   qp.h2 = h2;
   qp.n_actions = A;
   qp.d0p = d0 <= 64 ? 64 : 96;
-  const size_t w_elems = (size_t)h1 * d0 + (size_t)h2 * h1 + (size_t)A * h2;
   const size_t b_elems = (size_t)h1 + h2 + A;
   const size_t w1p = (size_t)h1 * qp.d0p, w2p = (size_t)h2 * h1, w3p = (size_t)16 * h2;
   const size_t bytes = (w1p + w2p + w3p) * 2 + (size_t)(h1 + h2 + 16) * 4 + 256;
-  if (hipMalloc(&e->q_block, bytes) != hipSuccess) return fail(SPARROW_ENOMEM, "hipMalloc failed");
-  if (hipMalloc((void**)&e->eps, sizeof(float) * e->cfg.n_envs) != hipSuccess)
-    return fail(SPARROW_ENOMEM, "hipMalloc failed");
-  char* base = (char*)e->q_block;
+  // The new network is built in buffers of its own; the installed one stays
+  // in place (and usable) until every step below has succeeded.
+  void* blk = nullptr;
+  float* eps_new = nullptr;
+  auto drop = [&](int code, const std::string& msg) {
+    (void)hipStreamSynchronize(e->stream);  // no queued copy still targets them
+    if (blk) (void)hipFree(blk);
+    if (eps_new) (void)hipFree(eps_new);
+    return fail(code, msg);
+  };
+  if (hipMalloc(&blk, bytes) != hipSuccess) return drop(SPARROW_ENOMEM, "hipMalloc failed");
+  if (hipMalloc((void**)&eps_new, sizeof(float) * e->cfg.n_envs) != hipSuccess)
+    return drop(SPARROW_ENOMEM, "hipMalloc failed");
+  char* base = (char*)blk;
   qp.w1 = (uint16_t*)base;
   qp.w2 = qp.w1 + w1p;
   qp.w3 = qp.w2 + w2p;
@@ -1021,20 +1031,51 @@ int sparrow_set_qnet(sparrow_env* e, const int32_t* dims, const uint16_t* w_bf16
   qp.b2 = qp.b1 + h1;
   qp.b3 = qp.b2 + h2;
   // repack on the device: W1 rows padded to d0p, W3 padded to 16 rows, b3 to 16
-  HIP_TRY(hipMemsetAsync(e->q_block, 0, bytes, e->stream));
-  HIP_TRY(hipMemcpy2DAsync((void*)qp.w1, qp.d0p * 2, w_bf16, (size_t)d0 * 2, (size_t)d0 * 2, h1,
-                           hipMemcpyDeviceToDevice, e->stream));
-  HIP_TRY(hipMemcpyAsync((void*)qp.w2, w_bf16 + (size_t)h1 * d0, w2p * 2, hipMemcpyDeviceToDevice, e->stream));
-  HIP_TRY(hipMemcpyAsync((void*)qp.w3, w_bf16 + (size_t)h1 * d0 + w2p, (size_t)A * h2 * 2,
-                         hipMemcpyDeviceToDevice, e->stream));
-  HIP_TRY(hipMemcpyAsync((void*)qp.b1, b_f32, (size_t)b_elems * 4, hipMemcpyDeviceToDevice, e->stream));
-  HIP_TRY(hipMemcpyAsync(e->eps, eps, sizeof(float) * e->cfg.n_envs, hipMemcpyDeviceToDevice,
-                         e->stream));
-  (void)w_elems;
-  HIP_TRY(hipStreamSynchronize(e->stream));
+  hipError_t he = hipMemsetAsync(blk, 0, bytes, e->stream);
+  if (he == hipSuccess)
+    he = hipMemcpy2DAsync((void*)qp.w1, qp.d0p * 2, w_bf16, (size_t)d0 * 2, (size_t)d0 * 2, h1,
+                          hipMemcpyDeviceToDevice, e->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync((void*)qp.w2, w_bf16 + (size_t)h1 * d0, w2p * 2, hipMemcpyDeviceToDevice,
+                        e->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync((void*)qp.w3, w_bf16 + (size_t)h1 * d0 + w2p, (size_t)A * h2 * 2,
+                        hipMemcpyDeviceToDevice, e->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync((void*)qp.b1, b_f32, (size_t)b_elems * 4, hipMemcpyDeviceToDevice,
+                        e->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(eps_new, eps, sizeof(float) * e->cfg.n_envs, hipMemcpyDeviceToDevice,
+                        e->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+  if (he != hipSuccess)
+    return drop(SPARROW_EHIP, std::string("installing the Q-network: ") + hipGetErrorString(he));
+  // the stream is idle: nothing in flight reads the old network any more
+  if (e->q_block) (void)hipFree(e->q_block);
+  if (e->eps) (void)hipFree(e->eps);
+  e->q_block = blk;
+  e->eps = eps_new;
   qp.vem = e->vem;
   e->qp = qp;
   e->has_qnet = true;
+  return SPARROW_OK;
+}
+
+int sparrow_vem_epsilon(sparrow_env* e, int32_t m, double e_min, double e_max, float* eps) {
+  if (!e || !eps) return fail(SPARROW_EINVAL, "NULL argument");
+  const int N = e->cfg.n_envs;
+  if (m < 0 || m > N || !(e_min >= 0.0) || !(e_max >= 0.0))
+    return fail(SPARROW_EINVAL, "need 0 <= m <= n_envs and e_min, e_max >= 0");
+  VemSchedule v{};
+  v.on = 1;
+  v.n = N;
+  v.or_start = m;
+  v.or_final = m;
+  v.decay = 0;
+  v.e_min = e_min;
+  v.e_max = e_max;
+  hipLaunchKernelGGL(k_vem_eps, dim3((N + 255) / 256), dim3(256), 0, e->stream, v, eps);
+  HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
 

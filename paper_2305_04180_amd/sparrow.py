@@ -28,7 +28,8 @@ EXPORTS = (
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
-    "sparrow_set_vem_schedule", "sparrow_rollout_collect", "sparrow_step_collect",
+    "sparrow_set_vem_schedule", "sparrow_vem_epsilon", "sparrow_rollout_collect",
+    "sparrow_step_collect",
     "sparrow_set_task",
     "sparrow_obs_dim",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
@@ -120,6 +121,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_destroy": (None, [P]),
             "sparrow_last_error": (C.c_char_p, []),
             "sparrow_set_vem_schedule": (I32, [P, C.c_double, C.c_double, I32, I32, C.c_int64]),
+            "sparrow_vem_epsilon": (I32, [P, I32, C.c_double, C.c_double, P]),
             "sparrow_learner_create": (I32, [P, P, P, C.POINTER(LearnerConfig), P, C.POINTER(P)]),
             "sparrow_learner_update": (I32, [P, I32, P, P, P, P, P, P]),
             "sparrow_learner_q": (I32, [P, I32, I32, P, P]),
@@ -300,12 +302,24 @@ class Env:
         nb = int(dims[1]) + int(dims[2]) + int(dims[3])
         w = torch.as_tensor(np.asarray(w_bf16).view(np.int16)).to(self.device)
         b = torch.as_tensor(np.asarray(b_f32, np.float32)).to(self.device)
-        e = torch.as_tensor(np.asarray(eps, np.float32)).to(self.device)
+        if isinstance(eps, torch.Tensor):
+            e = self._b(eps, torch.float32, self.n, "eps")
+        else:
+            e = torch.as_tensor(np.asarray(eps, np.float32)).to(self.device)
         for t, k, name in ((w, nw, "weights"), (b, nb, "biases"), (e, self.n, "eps")):
             if t.numel() != k:
                 raise ValueError(f"{name}: expected {k} values for dims {tuple(dims)}, got {t.numel()}")
         _check(lib().sparrow_set_qnet(self._h, d, _ptr(w), _ptr(b), _ptr(e)))
         self._qkeep = (w, b, e)
+
+    def vem_epsilon(self, m, e_min, e_max, out=None):
+        """VEM's per-env exploration probabilities for a fixed exploring
+        interval of the last m envs (sparrow_vem_epsilon), on the device."""
+        t = self.torch
+        out = t.zeros(self.n, dtype=t.float32, device=self.device) if out is None else out
+        self._b(out, t.float32, self.n, "eps")
+        _check(lib().sparrow_vem_epsilon(self._h, int(m), float(e_min), float(e_max), _ptr(out)))
+        return out
 
     def set_vem_schedule(self, e_min, e_max, or_start, or_final, decay_transitions):
         """VEM with an exploring interval shrinking linearly over training."""
@@ -406,18 +420,6 @@ class Env:
 
     def status(self):
         return lib().sparrow_status(self._h)
-
-
-def vem_epsilon(n: int, m: int, e_min: float, e_max: float) -> np.ndarray:
-    """Per-env exploration probabilities of VEM (Sec. 3.1.1): the exploiting
-    interval holds e_min; the last m envs (the exploring interval) rise
-    linearly from e_min to e_min + e_max."""
-    eps = np.full(n, e_min, np.float64)
-    if m > 0:
-        j = np.arange(m, dtype=np.float64)
-        frac = j / (m - 1) if m > 1 else np.ones(1)
-        eps[n - m:] = e_min + e_max * frac
-    return eps.astype(np.float32)
 
 
 class Ring:

@@ -143,8 +143,9 @@ def _actor512(env, cfg):
     from paper_2305_04180_amd import sparrow
     dims = (env.obs_dim, 512, 512, 7)
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(env.n, env.n, 0.01, 0.29)
-    env.set_qnet(dims, w, b, eps)
+    import oracle
+    eps = oracle.vem_epsilon(env.n, env.n, 0.01, 0.29)
+    env.set_qnet(dims, w, b, env.vem_epsilon(env.n, 0.01, 0.29))
     return dims, w, b, eps
 
 
@@ -433,8 +434,8 @@ def test_rollout_collect_fused_actor_lockstep(torch_gpu):
     orc = oracle.Oracle(cfg, maps)
     dims = (env.obs_dim, 256, 256, 7)
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(N, N, 0.01, 0.29)
-    env.set_qnet(dims, w, b, eps)
+    eps = oracle.vem_epsilon(N, N, 0.01, 0.29)
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, 0.01, 0.29))
     env.reset()
     o_obs, _ = orc.reset()
     ring = sparrow.Ring(2048, nr, seed=2)

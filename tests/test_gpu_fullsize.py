@@ -40,9 +40,9 @@ def test_m4096_fused_rollout_every_env(torch_gpu, m_maps):
     banner(f"fused rollout N={N} K={K} default variant")
     dims = cfg["qnet"]
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(N, N, 0.01, 0.29)
+    eps = oracle.vem_epsilon(N, N, 0.01, 0.29)
     env = sparrow.Env(cfg, m_maps)
-    env.set_qnet(dims, w, b, eps)
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, 0.01, 0.29))
     assert env.get_variant(1) == (8, 64)
     orc = oracle.Oracle(cfg, m_maps)
     env.reset()
@@ -141,9 +141,9 @@ def test_c5_full_collection_loop_sampled(torch_gpu):
     maps.env_to_map = (np.arange(N) % 512).astype(np.int32)
     dims = cfg["qnet"]
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
+    eps = oracle.vem_epsilon(N, N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0])
     env = sparrow.Env(cfg, maps)
-    env.set_qnet(dims, w, b, eps)
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0]))
     cur = env.reset()
     env.autotune(steps=2)
     ring = sparrow.Ring(1 << 22, nr, seed=5)

@@ -125,8 +125,8 @@ def test_task_actor_forward_and_fused_rollout(torch_gpu):
     maps = inputs.make_maps(cfg)
     env, orc = make(cfg, maps)
     w, b, _ = inputs.qnet_weights(dims)
-    eps = sparrow.vem_epsilon(env.n, env.n, 0.01, 0.29)
-    env.set_qnet(dims, w, b, eps)
+    eps = oracle.vem_epsilon(env.n, env.n, 0.01, 0.29)
+    env.set_qnet(dims, w, b, env.vem_epsilon(env.n, 0.01, 0.29))
     env.reset()
     o_obs, _ = orc.reset()
     rows = [o_obs]

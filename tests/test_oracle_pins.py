@@ -62,6 +62,25 @@ def get(o, name):
 # --------------------------------------------------------------------------
 # Philox4x32-10
 # --------------------------------------------------------------------------
+_MASK = 0xFFFFFFFF
+
+
+def philox_py(ctr, key):
+    """Philox4x32-10 written here from its definition (Salmon et al., SC'11:
+    ten rounds of two 32x32->64 multiplies by 0xD2511F53 and 0xCD9E8D57, the
+    high halves xored with the other counter words and the round key, the key
+    bumped by the Weyl constants 0x9E3779B9 and 0xBB67AE85): a second
+    implementation, independent of the oracle's C code."""
+    c = [int(v) & _MASK for v in ctr]
+    k0, k1 = int(key[0]) & _MASK, int(key[1]) & _MASK
+    for _ in range(10):
+        p0, p1 = 0xD2511F53 * c[0], 0xCD9E8D57 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & _MASK, p1 & _MASK, ((p0 >> 32) ^ c[3] ^ k1) & _MASK,
+             p0 & _MASK]
+        k0, k1 = (k0 + 0x9E3779B9) & _MASK, (k1 + 0xBB67AE85) & _MASK
+    return c
+
+
 def test_philox_matches_rocrand_engine(tmp_path):
     """The oracle's Philox equals rocRAND's Philox4x32-10 engine (a library
     implementation of the same SC'11 generator) on random counters and keys."""
@@ -85,6 +104,9 @@ def test_philox_matches_rocrand_engine(tmp_path):
     got = np.stack([oracle.philox4x32_10(c.astype(np.uint32), k.astype(np.uint32))
                     for c, k in zip(ctr, key)]).astype(np.uint64)
     assert np.array_equal(got, ref)
+    # the tests' own Python Philox (used to pin the reset order) agrees too
+    py = np.array([philox_py(c, k) for c, k in zip(ctr, key)], np.uint64)
+    assert np.array_equal(py, ref)
 
 
 def test_philox_uniformity_chi2():
@@ -516,6 +538,90 @@ def test_reset_draws_within_ranges_and_free():
         assert not o.collides(e, S["tx"][e], S["ty"][e])
         assert (S["tx"][e] - S["x"][e]) ** 2 + (S["ty"][e] - S["y"][e]) ** 2 > 16.0
         assert S["x"][e] % 1.0 == 0.5 and S["y"][e] % 1.0 == 0.5
+
+
+def _disk_free(grid, px, py, r):
+    """Brute force over every cell of the map and a margin around it: no
+    occupied cell (outside the map counts as occupied) whose square lies
+    within distance r of (px, py), touching included."""
+    H, W = grid.shape
+    for j in range(int(math.floor(py - r)) - 2, int(math.floor(py + r)) + 3):
+        for i in range(int(math.floor(px - r)) - 2, int(math.floor(px + r)) + 3):
+            occ = not (0 <= i < W and 0 <= j < H) or grid[j, i] != 0
+            if not occ:
+                continue
+            dx = max(i - px, 0.0, px - (i + 1))
+            dy = max(j - py, 0.0, py - (j + 1))
+            if dx * dx + dy * dy <= r * r:
+                return False
+    return True
+
+
+def test_reset_takes_first_free_candidate_and_documented_words():
+    """Reading R10 (Sec. 3.2.4 per-episode randomisation, Sec. 3.2.5 reset),
+    pinned with draws the test makes itself (its own Philox, above): the
+    cells of the first start and target candidates are made occupied, and
+    the oracle must take the first candidate in counter order whose disk is
+    free (the target also farther than the arrival radius from the start).
+    Each randomised parameter must come from its documented Philox word:
+    (RESET_DR, 0) words 0-3 -> dt, K, mu, v_max; (RESET_DR, 1) words 0-2 ->
+    sigma, delay, heading."""
+    seed = (5 << 32) | 123
+    key = (seed & _MASK, seed >> 32)
+    side, n_envs, g = 48, 3, 0
+    cfg = base_cfg(n_envs=n_envs, seed=seed, dt_lo=0.05, dt_hi=0.2, K_lo=0.0, K_hi=0.6,
+                   mu_lo=0.5, mu_hi=1.0, vmax_lo=5.0, vmax_hi=15.0, sigma_lo=0.0,
+                   sigma_hi=2.0, delay_lo=0, delay_hi=2, arrive_r=4.0)
+    r, ra = cfg["robot_r"], cfg["arrive_r"]
+
+    def cand(i, purpose, n):
+        w = philox_py((i, g, purpose, n), key)
+        return (w[0] * side) >> 32, (w[1] * side) >> 32  # floor(w * side / 2^32)
+
+    grids, want = [], []
+    for i in range(n_envs):
+        grid = np.zeros((side, side), np.uint8)
+        blocked_s, blocked_t = 2 + i, 1 + i  # leading candidates made occupied
+        for n in range(blocked_s):
+            cx, cy = cand(i, 2, n)
+            grid[cy, cx] = 1
+        for n in range(blocked_t):
+            cx, cy = cand(i, 3, n)
+            grid[cy, cx] = 1
+        ns = next(n for n in range(1024) if _disk_free(grid, cand(i, 2, n)[0] + 0.5,
+                                                         cand(i, 2, n)[1] + 0.5, r))
+        sx, sy = cand(i, 2, ns)[0] + 0.5, cand(i, 2, ns)[1] + 0.5
+
+        def target_ok(n):
+            px, py = cand(i, 3, n)[0] + 0.5, cand(i, 3, n)[1] + 0.5
+            return _disk_free(grid, px, py, r) and (px - sx) ** 2 + (py - sy) ** 2 > ra * ra
+        nt = next(n for n in range(1024) if target_ok(n))
+        assert ns >= blocked_s and nt >= blocked_t
+        grids.append(grid)
+        want.append((ns, nt, sx, sy, cand(i, 3, nt)[0] + 0.5, cand(i, 3, nt)[1] + 0.5))
+    maps = inputs.Maps(grids=grids, env_to_map=np.arange(n_envs, dtype=np.int32))
+    o = oracle.Oracle(cfg, maps)
+    assert o.global_step == g
+    _, rc = o.reset()
+    assert rc == 0
+    f32 = np.float32
+    u24 = lambda w: f32(w >> 8) * f32(2.0 ** -24)
+    for i in range(n_envs):
+        ns, nt, sx, sy, tx, ty = want[i]
+        for name, v in (("x", sx), ("y", sy), ("tx", tx), ("ty", ty)):
+            assert get(o, name)[i] == f32(v), (i, name, ns, nt)
+        a = philox_py((i, g, 1, 0), key)
+        b = philox_py((i, g, 1, 1), key)
+        span = lambda lo, hi: f32(cfg[hi]) - f32(cfg[lo])
+        exp = {"dt": f32(cfg["dt_lo"]) + span("dt_lo", "dt_hi") * u24(a[0]),
+               "K": f32(cfg["K_lo"]) + span("K_lo", "K_hi") * u24(a[1]),
+               "mu": f32(cfg["mu_lo"]) + span("mu_lo", "mu_hi") * u24(a[2]),
+               "vmax": f32(cfg["vmax_lo"]) + span("vmax_lo", "vmax_hi") * u24(a[3]),
+               "sigma": f32(cfg["sigma_lo"]) + span("sigma_lo", "sigma_hi") * u24(b[0]),
+               "phi": u24(b[2]) * f32(2.0 * math.pi) - f32(math.pi)}
+        for name, v in exp.items():
+            assert get(o, name)[i].view(np.uint32) == f32(v).view(np.uint32), (i, name)
+        assert get(o, "delay")[i] == cfg["delay_lo"] + ((b[1] * 3) >> 32)
 
 
 def test_full_map_fails_reset():
