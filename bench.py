@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBS = 8000.0
 MI355X_CUS, MI355X_CLOCK_GHZ = 256, 2.4
-MI355X_LDS_GBS = MI355X_CUS * 128 * MI355X_CLOCK_GHZ  # 128 B/clk/CU
+# LDS: 128 B/clk/CU (the CDNA3 figure; CDNA4's is measured by the LDS probe,
+# and the roofline takes the larger of the two)
+MI355X_LDS_GBS = MI355X_CUS * 128 * MI355X_CLOCK_GHZ
 # 32-bit vector lane-ops per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (the 157.3 TFLOP/s FP32 figure counts an FMA as 2 and packed FP32 as 2)
 MI355X_VALU_TOPS = MI355X_CUS * 4 * 16 * MI355X_CLOCK_GHZ / 1e3
@@ -52,6 +54,16 @@ MI355X_BF16_TFLOPS = 2500.0
 ALG_OPS_PER_SAMPLE = 13
 ALG_OPS_PER_RAY = 110
 ALG_OPS_PER_ENV = 707
+# The paper task's Eq. (11) adds per env-step: r_d1, r_d2, r_v (~12), r_alpha
+# (the bearing's atan2 and |alpha|, ~45), the weighted sum (~10), and r_d,
+# the margin-disk test (radius r + 15 = 18 cells, a 38-row box): per row, the
+# run of cells within the disk around the robot's column (a square root and
+# the two ends' exact per-cell tests, ~20) and one to three word reads (~10)
+# -> 38 x 30 = 1,140
+ALG_OPS_PER_ENV_EQ11 = 12 + 45 + 10 + 38 * 30
+# LDS bytes of one env-step beyond the march's one word per sample: the
+# collision test's 7 rows x 2 words x 4 B
+LDS_COLLISION_BYTES = 56
 # HBM bytes of one plain step of one env: the rows of its packed map within
 # range of the robot (staged into LDS every step) + SoA state read and
 # written (15 x 4 B x 2) + action (4) +
@@ -61,6 +73,17 @@ ALG_OPS_PER_ENV = 707
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def under_profiler():
+    """True when a profiler's library is preloaded: it initialises the GPU
+    before main() runs, so no fork pool may be started."""
+    pre = os.environ.get("LD_PRELOAD", "")
+    return "rocprof" in pre or any(k.startswith(("ROCP_", "ROCPROF")) for k in os.environ)
+
+
+def map_workers():
+    return 1 if under_profiler() else max(1, min(16, os.cpu_count() or 1))
 
 
 def parse():
@@ -85,6 +108,13 @@ def parse():
                     help="skip the paper's own task (27 rays, 5 actions, Eq. (11), 32-256-128-5)")
     ap.add_argument("--no-asl", action="store_true",
                     help="skip the actor/learner leg paced by the time feedback mechanism")
+    ap.add_argument("--roofline-launches", type=int, default=16,
+                    help="K-step launches timed for the roofline (K = --rollout), whatever --steps is")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the batching leg (16384 envs, uneven sides, 64 rays)")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the precision leg (8192 envs, 2048 traced fused steps)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the LDS / HBM / MFMA probes")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -273,7 +303,7 @@ def collection_c5(cfg, maps, steps, warmup, fused_add=False):
     }
 
 
-def paper_task(steps=2048, K=64):
+def paper_task(lds_peak, steps=2048, K=64):
     """The paper's own task (Sec. 4.3.1/4.3.2) at 4096 envs on 366^2 maps:
     27 rays, five actions, Eq. (11) reward, 32-entry relative-pose state,
     the 32-256-128-5 actor with VEM; fused rollouts and the plain step."""
@@ -303,11 +333,10 @@ def paper_task(steps=2048, K=64):
     torch.cuda.synchronize()
     fused_ms = e0.elapsed_time(e1)
     fused = N * (steps // K) * K / (fused_ms / 1e3)
-    hits = env.debug_hits().to(torch.int32)
-    M = int(cfg["range"] / cfg["ds"])
-    samples = float(torch.where(hits < 0, torch.full_like(hits, M), hits).add(1).sum().item()) / N
-    ops = ALG_OPS_PER_SAMPLE * samples + ALG_OPS_PER_RAY * cfg["n_rays"] + ALG_OPS_PER_ENV
-    alu = ops * fused / 1e12
+    roof = fused_roofline(env, cfg, maps, K, 8, stream, lds_peak,
+                          extra_env_ops=ALG_OPS_PER_ENV_EQ11,
+                          kernel="k_rollout<64, QNetCfg<64,256,128>, false, true> "
+                                 "(paper task: 27 rays, 5 actions, Eq. (11))")
     a = torch.zeros(N, dtype=torch.int32, device="cuda")
     for _ in range(16):
         env.random_actions(a)
@@ -326,11 +355,7 @@ def paper_task(steps=2048, K=64):
                         "32-entry relative-pose state, Q-MLP 32-256-128-5 bf16",
             "fused_env_steps_per_s": round(fused, 1), "plain_env_steps_per_s": round(plain, 1),
             "fused_steps": (steps // K) * K, "plain_steps": 256,
-            "roofline": {"bound": "alu", "achieved": round(alu, 3), "peak": MI355X_VALU_TOPS,
-                         "unit": "TFLOP/s", "frac": round(alu / MI355X_VALU_TOPS, 4),
-                         "samples_per_env_step": round(samples, 2),
-                         "units": "the default task's lane-op counts (13/sample, 110/ray, "
-                                  "707/env); Eq. (11)'s terms are not counted"},
+            "roofline": roof,
             "variants": {"step": env.get_variant(0), "rollout": env.get_variant(1)}}
 
 
@@ -534,25 +559,244 @@ def env_window_bytes(maps, cfg, y):
     return tot
 
 
-def greedy_agreement(env, cfg, maps, dims, w, b):
-    """BF16 MFMA actor vs the FP64 oracle on observations the oracle itself
-    produced: its reset of the same envs and three uniform-action steps."""
+def peaks(skip):
+    """The device's own peak rates from the library's probes (LDS reads of 16
+    and 4 bytes per lane, an HBM copy, dense BF16 MFMA)."""
+    if skip:
+        return None
+    from paper_2305_04180_amd import sparrow
+    out = {}
+    for name, kind, size, iters, unit in (
+            ("lds_b128", sparrow.PEAK_LDS128, 0, 2048, "GB/s"),
+            ("lds_b32", sparrow.PEAK_LDS32, 0, 2048, "GB/s"),
+            ("hbm_copy", sparrow.PEAK_HBM_COPY, 1 << 30, 8, "GB/s"),
+            ("mfma_bf16", sparrow.PEAK_MFMA_BF16, 0, 256, "TFLOP/s")):
+        rate, _ = sparrow.peak(kind, size, iters)
+        out[name] = round(rate / (1e12 if unit == "TFLOP/s" else 1e9), 1)
+    out["units"] = {"lds_b128": "GB/s", "lds_b32": "GB/s", "hbm_copy": "GB/s (read + write)",
+                    "mfma_bf16": "TFLOP/s"}
+    out["per_cu_clk"] = {"lds_b128_bytes": round(out["lds_b128"] / MI355X_CUS / MI355X_CLOCK_GHZ, 1),
+                         "lds_b32_bytes": round(out["lds_b32"] / MI355X_CUS / MI355X_CLOCK_GHZ, 1)}
+    return out
+
+
+def fused_roofline(env, cfg, maps, K, launches, stream, lds_peak, extra_env_ops=0,
+                   kernel="", counter_key=None):
+    """Roofline of the fused rollout kernel on its own K-step launches (graph
+    replays, HIP events around each on the launch stream), whatever the
+    metric's step count. Algorithmic work per launch (N K env-steps):
+      LDS  4 B per marched sample of the definition (k = 0 .. first hit, or
+           0 .. M without one; counted over one traced launch) + the
+           collision test's 56 B per env-step + the maps staged once
+      HBM  maps once + state in and out + final observation and hit indices
+           + per step reward, done and action
+      MFMA the Q-network's 2 (d0 h1 + h1 h2 + h2 A) FLOP per env-step
+    bound / frac: the largest of the three fractions (published peaks for HBM
+    and MFMA; for LDS the larger of 128 B/clk/CU and the probe's
+    measurement). The vector-ALU lane-op count is reported beside it."""
+    import torch
+    N, nr, D = cfg["n_envs"], cfg["n_rays"], env.obs_dim
+    dims = cfg["qnet"]
+    acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
+    rew = torch.zeros(K, N, dtype=torch.float32, device="cuda")
+    done = torch.zeros(K, N, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(N, D, dtype=torch.float32, device="cuda")
+    env.rollout(K, True, acts, rew, done, obs)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(launches)]
+    for a, b2 in ev:
+        a.record(stream)
+        env.rollout(K, True, acts, rew, done, obs)
+        b2.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = np.array([a.elapsed_time(b2) for a, b2 in ev])
+    _, _, _, _, _, hits_t = env.rollout_trace(K, True)
+    torch.cuda.synchronize()
+    M = int(cfg["range"] / cfg["ds"])
+    h = hits_t.to(torch.int64)
+    samples = float(torch.where(h < 0, torch.full_like(h, M), h).add(1).sum().item()) / (K * N)
+    del hits_t, h
+    assert env.status() == 0
+    avg_s = float(launch_ms.mean()) / 1e3
+    es = N * K
+    maps_b = env_map_bytes(maps)
+    lds_b = (4.0 * samples + LDS_COLLISION_BYTES) * es + maps_b
+    hbm_b = maps_b + N * (15 * 4 * 2 + 4 * D * 2 + 2 * nr + 4) + es * (4 + 1 + 4)
+    flops = 2.0 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3]) * es
+    ops = (ALG_OPS_PER_SAMPLE * samples + ALG_OPS_PER_RAY * nr + ALG_OPS_PER_ENV
+           + extra_env_ops) * es
+    lds_gbs, hbm_gbs = lds_b / avg_s / 1e9, hbm_b / avg_s / 1e9
+    mfma_tf, alu_t = flops / avg_s / 1e12, ops / avg_s / 1e12
+    fr = {"lds": lds_gbs / lds_peak, "hbm": hbm_gbs / MI355X_HBM_GBS,
+          "mfma": mfma_tf / MI355X_BF16_TFLOPS}
+    bound = max(fr, key=fr.get)
+    ach = {"lds": (lds_gbs, lds_peak, "GB/s"), "hbm": (hbm_gbs, MI355X_HBM_GBS, "GB/s"),
+           "mfma": (mfma_tf, MI355X_BF16_TFLOPS, "TFLOP/s")}[bound]
+    return {"bound": bound, "achieved": round(ach[0], 2), "peak": round(ach[1], 1), "unit": ach[2],
+            "frac": round(fr[bound], 5),
+            "traffic": counter_traffic(counter_key) if counter_key else None,
+            "traffic_alg_bytes": int(hbm_b),
+            "kernel": kernel, "rollout_k": K, "launches": launches,
+            "avg_launch_ms": round(avg_s * 1e3, 4),
+            "launch_ms_min_max": [round(float(launch_ms.min()), 4), round(float(launch_ms.max()), 4)],
+            "samples_per_env_step": round(samples, 2),
+            "lds_frac": round(fr["lds"], 5), "hbm_frac": round(fr["hbm"], 5),
+            "mfma_frac": round(fr["mfma"], 5),
+            "alg_per_launch": {"lds_bytes": int(lds_b), "hbm_bytes": int(hbm_b),
+                               "mfma_flop": int(flops), "env_steps": es},
+            "alu": {"achieved": round(alu_t, 3), "peak": round(MI355X_VALU_TOPS, 2),
+                    "unit": "T lane-ops/s", "frac": round(alu_t / MI355X_VALU_TOPS, 4),
+                    "units": f"32-bit lane-ops from the definition: {ALG_OPS_PER_SAMPLE}/sample, "
+                             f"{ALG_OPS_PER_RAY}/ray, {ALG_OPS_PER_ENV + extra_env_ops}/env; "
+                             "peak 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"}}
+
+
+def c3_leg(cfg, maps, launches=16, K=64):
+    """Batching workload: 16384 envs on uneven square maps (sides 64..512),
+    64 rays to range 128, full randomisation; uniform random actions;
+    autotuned variant; K = 64 rollouts replayed from the graph cache."""
+    import torch
+    from paper_2305_04180_amd import sparrow
+    N = cfg["n_envs"]
+    env = sparrow.Env(cfg, maps)
+    env.reset()
+    tune = env.autotune(steps=4)
+    stream = torch.cuda.current_stream()
+    acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
+    rew = torch.zeros(K, N, dtype=torch.float32, device="cuda")
+    done = torch.zeros(K, N, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(N, env.obs_dim, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        env.rollout(K, False, acts, rew, done, obs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        env.rollout(K, False, acts, rew, done, obs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert env.status() == 0
+    return {"value": round(N * K * launches / (ms / 1e3), 1), "unit": "env-steps/s",
+            "n_envs": N, "steps": K * launches, "rollout_k": K, "launches": launches,
+            "ms_per_step": round(ms / (K * launches), 5),
+            "config": {"workload": "16384 envs, own map each, sides uniform in {64,128,256,366,512}, "
+                                   "64 rays/270 deg/range 128, full DR, uniform random actions, "
+                                   "64-step rollouts from the graph cache, autotuned"},
+            "variants": {"rollout": env.get_variant(1), "step": env.get_variant(0)},
+            "autotune_chosen": tune.get("chosen")}
+
+
+def c4_leg(cfg, maps, launches=16, K=64):
+    """Precision workload's fused rollout at 8192 envs (366^2 maps, 32 rays,
+    BF16 36-256-256-7 actor, eps linspace(0.01, 0.3)): env-steps/s of K = 64
+    graph replays. Returns the env for the precision report."""
+    import torch
+    from paper_2305_04180_amd import sparrow
+    N = cfg["n_envs"]
+    dims = cfg["qnet"]
+    w, b, _ = inputs_mod().qnet_weights(dims)
+    env = sparrow.Env(cfg, maps)
+    env.set_qnet(dims, w, b, env.vem_epsilon(N, cfg["eps"][0], cfg["eps"][1] - cfg["eps"][0]))
+    env.reset()
+    stream = torch.cuda.current_stream()
+    acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
+    rew = torch.zeros(K, N, dtype=torch.float32, device="cuda")
+    done = torch.zeros(K, N, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(N, env.obs_dim, dtype=torch.float32, device="cuda")
+    env.rollout(K, True, acts, rew, done, obs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        env.rollout(K, True, acts, rew, done, obs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert env.status() == 0
+    return env, {"value": round(N * K * launches / (ms / 1e3), 1), "unit": "env-steps/s",
+                 "n_envs": N, "steps": K * launches, "rollout_k": K,
+                 "variants": {"rollout": env.get_variant(1)}}
+
+
+def inputs_mod():
+    from paper_2305_04180_amd import inputs
+    return inputs
+
+
+def oracle_checks(cfg4, env4, cfg, maps, sample_every=32, launches=32, K=64):
+    """Reports that need the oracle (run in the CPU leg):
+    c4: 2048 fused steps at 8192 envs with every step traced; on every
+        sample_every-th env, each greedy choice of the fused actor against the
+        FP64 oracle network's argmax on the observation that step's actor saw
+        (exploration draws from the oracle's own VEM), and max |dQ| of the
+        actor kernel's Q values on those rows;
+    m_shadow: the oracle's FP64 kinematics shadow on 256 envs of the headline
+        workload over 500 uniform-action steps: largest one-step relative
+        error against the 1e-5 tolerance, and the cell-boundary ties."""
     import torch
     import oracle
-    o = oracle.Oracle(cfg, maps)
-    obs, _ = o.reset()
-    rows = [obs]
-    for _ in range(3):
-        rows.append(o.step(o.uniform_actions())["obs"])
-    x = np.concatenate(rows)
-    q, g = env.qnet_forward(torch.as_tensor(x).cuda())
-    torch.cuda.synchronize()
-    q64 = oracle.qnet_f64(dims, w, b, x)
-    qg = q.cpu().numpy().astype(np.float64)
-    agree = float((g.cpu().numpy() == q64.argmax(1)).mean())
-    return {"rows": int(x.shape[0]), "greedy_agreement_vs_fp64": round(agree, 5),
-            "max_abs_dq": float(np.abs(qg - q64).max()),
-            "observations": "oracle reset + 3 uniform steps of the benchmark's envs"}
+    from paper_2305_04180_amd import inputs
+    from tests.parity_util import ExploreDraws, qnet_f64_threads, traced_actor_rows
+    out = {}
+    if env4 is not None:
+        N = cfg4["n_envs"]
+        dims = cfg4["qnet"]
+        w, b, _ = inputs.qnet_weights(dims)
+        e_min, e_span = cfg4["eps"][0], cfg4["eps"][1] - cfg4["eps"][0]
+        sample = np.arange(0, N, sample_every)
+        env4.reset()
+        t0 = time.time()
+        obs_in, acts, steps = traced_actor_rows(env4, launches, K, sample)
+        draws = ExploreDraws(cfg4["seed"], N, oracle.vem_epsilon(N, N, e_min, e_span))
+        ex = np.stack([draws.flags(g)[sample] for g in steps]).reshape(-1)
+        x = obs_in.reshape(-1, env4.obs_dim)
+        a = acts.reshape(-1)
+        q, greedy = env4.qnet_forward(torch.as_tensor(x).cuda())
+        torch.cuda.synchronize()
+        q = q.cpu().numpy().astype(np.float64)
+        greedy = greedy.cpu().numpy()
+        q64 = qnet_f64_threads(dims, w, b, x, workers=min(16, os.cpu_count() or 1))
+        top = q64.argmax(1)
+        srt = np.sort(q64, axis=1)
+        gap = srt[:, -1] - srt[:, -2]
+        g = ~ex
+        clear = g & (gap > 0.05)
+        out["c4_precision"] = {
+            "envs": N, "sampled_envs": int(len(sample)), "steps": int(launches * K),
+            "rows": int(x.shape[0]), "greedy_rows": int(g.sum()),
+            "greedy_agreement_vs_fp64": round(float((a[g] == top[g]).mean()), 6),
+            "agreement_fp64_gap_over_0.05": round(float((a[clear] == top[clear]).mean()), 6),
+            "rows_gap_over_0.05": int(clear.sum()),
+            "fused_equals_actor_kernel": bool(np.array_equal(greedy[g], a[g])),
+            "max_abs_dq": float(np.abs(q - q64).max()),
+            "observations": "the rollout's own: the observation each step's actor saw "
+                            f"(every step of {launches} traced K = {K} launches)",
+            "seconds": round(time.time() - t0, 1)}
+    # FP64 kinematics shadow and ties on a sample of the headline workload
+    n_s = 256
+    sub = dict(cfg, n_envs=n_s)
+    smaps = inputs.Maps(grids=maps.grids[:n_s], env_to_map=np.arange(n_s, dtype=np.int32))
+    o = oracle.Oracle(sub, smaps)
+    o.reset()
+    st = oracle.Stats()
+    n_steps = 500
+    for _ in range(n_steps):
+        o.step(o.uniform_actions(), stats=st)
+    d = st.as_dict()
+    rel = max(d["max_rel_x"], d["max_rel_y"], d["max_rel_phi"], d["max_rel_vl"], d["max_rel_va"])
+    out["m_shadow"] = {
+        "envs": n_s, "steps": n_steps, "tolerance": 1e-5,
+        "max_rel_one_step": rel, "within_tolerance": bool(rel <= 1e-5),
+        "max_rel": {k: d[k] for k in ("max_rel_x", "max_rel_y", "max_rel_phi", "max_rel_vl",
+                                      "max_rel_va")},
+        "boundary_ties_ray_samples": int(d["ties_ray"]), "samples": int(d["samples"]),
+        "boundary_ties_collision": int(d["ties_coll"]), "kin_steps": int(d["kin_steps"]),
+        "what": "FP32 step against the FP64 shadow re-synced every step; ties = samples or "
+                "collision tests whose cell differs between FP32 and FP64 positions "
+                "(counted, not failed)"}
+    return out
 
 
 def main():
@@ -570,13 +814,24 @@ def main():
         assert torch.cuda.is_available(), "bench.py needs the GPU"
         copy_calibration(args.copy_mb)
         return
-    maps5 = None
-    if not args.no_c5:
-        # generated with a process pool before this process touches the GPU
-        cfg5 = inputs.workload("c5")
+    # maps of the other workloads, generated with a process pool before this
+    # process touches the GPU (one process under a profiler, whose preloaded
+    # library has already initialised it)
+    maps5 = maps3 = maps4 = None
+    cfg3, cfg4, cfg5 = inputs.workload("c3"), inputs.workload("c4"), inputs.workload("c5")
+    for flag, cfg_x, name in ((args.no_c5, cfg5, "c5"), (args.no_c3, cfg3, "c3"),
+                              (args.no_c4, cfg4, "c4")):
+        if flag:
+            continue
         t0 = time.time()
-        maps5 = inputs.make_maps(cfg5, workers=max(1, min(16, os.cpu_count() or 1)))
-        log(f"[bench] c5: {len(maps5.grids)} maps in {time.time() - t0:.1f}s")
+        mx = inputs.make_maps(cfg_x, workers=map_workers())
+        log(f"[bench] {name}: {len(mx.grids)} maps in {time.time() - t0:.1f}s")
+        if name == "c5":
+            maps5 = mx
+        elif name == "c3":
+            maps3 = mx
+        else:
+            maps4 = mx
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     cfg = inputs.workload(args.workload)
     N = cfg["n_envs"]
@@ -597,10 +852,16 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    pk = peaks(args.no_peaks)
+    if pk:
+        log(f"[bench] peaks: {pk}")
+    lds_peak = max(MI355X_LDS_GBS, pk["lds_b128"] if pk else 0.0)
+
     # ---------------- fused rollout ----------------
-    # Each run times exactly args.steps vectorized steps: full K-step
-    # launches plus one shorter launch for the remainder.
-    K = args.rollout
+    # Each run times exactly args.steps vectorized steps: launches of K steps
+    # (K = --rollout, or --steps when that is smaller) plus one shorter launch
+    # for the remainder.
+    K = min(args.rollout, args.steps)
     n_full, rem = divmod(args.steps, K)
     n_warm = max(1, math.ceil(args.warmup / K))
     acts = torch.zeros(K, N, dtype=torch.int32, device="cuda")
@@ -640,15 +901,18 @@ def main():
     run_ms = [x[0] for x in runs]
     med = int(np.argsort(run_ms)[len(run_ms) // 2])
     fused_ms, wall, _ = runs[med]
-    # the K-step launches of every run (the remainder launch is left out)
-    launch_ms = np.array([d for x in runs for d in x[2]])
     steps_fused = args.steps
     fused_rate = N * steps_fused / (fused_ms / 1e3)
     assert env.status() == 0
-    hits = env.debug_hits().to(torch.int32)
-    M = int(cfg["range"] / cfg["ds"])
-    samples_last = float(torch.where(hits < 0, torch.full_like(hits, M), hits).add(1).sum().item())
     log(f"[bench] fused: {fused_rate / 1e6:.1f} M env-steps/s ({fused_ms / steps_fused * 1e3:.2f} us/step)")
+
+    # ---------------- roofline of the fused kernel ----------------
+    # on its own launches of the workload's rollout length, whatever --steps is
+    KR = args.rollout
+    roofline = fused_roofline(env, cfg, maps, KR, args.roofline_launches, stream, lds_peak,
+                              kernel="k_rollout<64, QNetCfg<64,256,256>> (fused actor + step)",
+                              counter_key="traffic_bytes_per_launch_k_rollout")
+    log(f"[bench] roofline: {json.dumps(roofline)}")
 
     # ---------------- the same steps in 256-step launches ----------------
     # (the workload's rollouts are 64 steps; longer launches amortise the
@@ -744,35 +1008,7 @@ def main():
     pa_rate = N * P / (q0.elapsed_time(q1) / 1e3)
     log(f"[bench] plain+actor: {pa_rate / 1e6:.1f} M env-steps/s")
 
-    # ---------------- roofline of the fused kernel ----------------
-    # The sample count per env-step (rays marched from k = 0 to the first hit,
-    # the definition's count) is taken from the last step's hit indices.
-    samples_per_env_step = samples_last / N
-    nr = cfg["n_rays"]
-    ops_per_env_step = (ALG_OPS_PER_SAMPLE * samples_per_env_step + ALG_OPS_PER_RAY * nr
-                        + ALG_OPS_PER_ENV)
-    avg_launch_s = float(launch_ms.mean()) / 1e3
-    alu_tops = ops_per_env_step * N * K / avg_launch_s / 1e12
-    lds_gbs = samples_per_env_step * 4.0 * N * K / avg_launch_s / 1e9  # one word per sample
-    D = env.obs_dim
-    # HBM per launch: maps staged once per group, state in and out, the final
-    # observation, per-step reward/done/action (the actor weights, 153 KB,
-    # come from L2 after the first read and are left out)
-    hbm_bytes = (env_map_bytes(maps) + N * (15 * 4 * 2 + 4 * D * 2 + 2 * nr + 4)
-                 + K * N * (4 + 1 + 4))
-    hbm_gbs = hbm_bytes / avg_launch_s / 1e9
-    mlp_flops = 2.0 * (dims[0] * dims[1] + dims[1] * dims[2] + dims[2] * dims[3])
-    roofline = {"bound": "alu", "achieved": round(alu_tops, 3), "peak": MI355X_VALU_TOPS,
-                "unit": "TFLOP/s", "frac": round(alu_tops / MI355X_VALU_TOPS, 4),
-                "traffic": counter_traffic("traffic_bytes_per_launch_k_rollout"),
-                "traffic_alg_bytes": int(hbm_bytes),
-                "kernel": "k_rollout<64, QNetCfg<64,256,256>> (fused actor + step)",
-                "units": "32-bit lane-ops from the definition (13/sample, 110/ray, 707/env)",
-                "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-                "samples_per_env_step": round(samples_per_env_step, 2),
-                "lds_frac": round(lds_gbs / MI355X_LDS_GBS, 5),
-                "hbm_frac": round(hbm_gbs / MI355X_HBM_GBS, 5),
-                "mfma_frac": round(mlp_flops * N * K / avg_launch_s / 1e12 / MI355X_BF16_TFLOPS, 5)}
+    D, nr = env.obs_dim, cfg["n_rays"]
     win_bytes = env_window_bytes(maps, cfg, env.get_state()[0][:, 1])
     step_bytes = win_bytes + N * (15 * 4 * 2 + 4 + 4 * D * 2 + 4 + 1 + 2 * nr)
     plain_hbm = step_bytes * P / (plain_ms / 1e3) / 1e9
@@ -785,8 +1021,19 @@ def main():
                       "staged_map_bytes_per_step": int(win_bytes),
                       "whole_map_bytes": int(env_map_bytes(maps))}
 
+    c3 = None
+    if maps3 is not None:
+        log("[bench] c3 batching (16384 envs, uneven sides, 64 rays)")
+        c3 = c3_leg(cfg3, maps3)
+        log(f"[bench] c3: {c3['value'] / 1e6:.1f} M env-steps/s, variant {c3['variants']}")
+    env4 = c4 = None
+    if maps4 is not None:
+        log("[bench] c4 fused rollout (8192 envs)")
+        env4, c4 = c4_leg(cfg4, maps4)
+        log(f"[bench] c4: {c4['value'] / 1e6:.1f} M env-steps/s")
+
     cpu = None
-    precision = None
+    checks = {}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(cfg, maps, w, b, args.cpu_seconds)
@@ -794,8 +1041,12 @@ def main():
         cpu["single_thread_value"] = one["value"]
         cpu["cpu_model"] = cpu_model()
         cpu["nproc"] = os.cpu_count()
-        precision = greedy_agreement(env, cfg, maps, dims, w, b)
-        log(f"[bench] precision: {precision}")
+        log("[bench] oracle checks: c4 precision, kinematics shadow")
+        checks = oracle_checks(cfg4, env4, cfg, maps)
+        log(f"[bench] oracle checks: {json.dumps(checks)}")
+    if c4 is not None and "c4_precision" in checks:
+        c4["precision"] = checks["c4_precision"]
+    env4 = None
 
     c5 = None
     if maps5 is not None:
@@ -812,7 +1063,7 @@ def main():
     ptask = None
     if not args.no_task:
         log("[bench] the paper's own task (Sec. 4.3.1/4.3.2)")
-        ptask = paper_task()
+        ptask = paper_task(lds_peak)
         log(f"[bench] paper task: {ptask}")
 
     learner = None
@@ -844,7 +1095,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "4096 envs, own 366x366 map each, 32 rays/270 deg/range 100, "
                                "full DR, Q-MLP 36-256-256-7 bf16, eps linspace(0.01,0.3)",
-                   "n_envs": N, "rollout_k": K, "parallelism": "single GPU"},
+                   "n_envs": N, "rollout_k": K, "remainder_k": rem, "launches": n_full + (rem > 0),
+                   "parallelism": "single GPU"},
         "plain_env_steps_per_s": round(plain_rate, 1),
         "plain_actor_env_steps_per_s": round(pa_rate, 1),
         "fused_over_plain": round(fused_rate / plain_rate, 3),
@@ -856,7 +1108,11 @@ def main():
         "roofline": roofline,
         "plain_roofline": plain_roofline,
         "cpu_baseline": cpu,
-        "precision": precision,
+        "precision": checks.get("c4_precision"),
+        "kinematics_shadow": checks.get("m_shadow"),
+        "peaks": pk,
+        "c3_batching": c3,
+        "c4_fused": c4,
         "collection_c5": c5,
         "paper_task": ptask,
         "paper_context": {"value": 8155.0, "unit": "env-steps/s", "kind": "context",

@@ -247,6 +247,18 @@ int sparrow_act(sparrow_env *env, const float *obs, int32_t *actions);
 int sparrow_rollout(sparrow_env *env, int32_t K, int32_t use_qnet, int32_t *actions,
                     float *reward, uint8_t *done, float *obs);
 
+/* sparrow_rollout that also returns what every step observed, for checks of
+ * the intermediate steps and precision reports: obs_steps (dev [K][N]
+ * [obs_dim] FP32, nullable) receives the observation after each step (row
+ * K - 1 equals obs), hits_steps (dev [K][N][n_rays] int16, nullable) the
+ * per-ray first-hit sample index of that observation (-1: none; row K - 1
+ * equals what sparrow_debug_hits then returns). Same kernel, variant and
+ * results as sparrow_rollout, launched directly rather than from the cached
+ * graph, plus copies of the last step's rows on the env's stream. */
+int sparrow_rollout_trace(sparrow_env *env, int32_t K, int32_t use_qnet, int32_t *actions,
+                          float *reward, uint8_t *done, float *obs, float *obs_steps,
+                          int16_t *hits_steps);
+
 /* Per-ray sample index of the first hit (-1: none) of the most recent
  * observation of each env (dev [N][n_rays] int16). For parity checks. */
 int sparrow_debug_hits(sparrow_env *env, int16_t *hit_k);
@@ -420,6 +432,25 @@ double sparrow_tfm_xi(const sparrow_tfm *t);
 double sparrow_tfm_actor_sleep(const sparrow_tfm *t);
 double sparrow_tfm_learner_sleep(const sparrow_tfm *t);
 void sparrow_tfm_destroy(sparrow_tfm *t);
+
+/* ---- Peak-rate probes -------------------------------------------------------
+ * Measurements of the device that bound the step kernels' rooflines; not part
+ * of the method. Each runs one untimed launch, then times its launches with
+ * HIP events on hip_stream (NULL: the default stream) and synchronises.
+ *   kind 0: LDS reads of 16 bytes per lane, bank-conflict free (iters reads
+ *           per lane; 2 workgroups of 1024 lanes per CU, 16 rounds), 3 launches
+ *   kind 1: LDS reads of 4 bytes per lane (the ray march's access width),
+ *           otherwise as kind 0
+ *   kind 2: HBM copy of size bytes (in [1 MiB, 16 GiB], a multiple of 16) into
+ *           a second buffer, iters launches; rate counts read + write bytes.
+ *           Allocates both buffers and frees them before returning.
+ *   kind 3: dense BF16 MFMA, v_mfma_f32_16x16x32_bf16 on register operands,
+ *           8 chains of iters products per wave, 16 waves per CU, 3 launches
+ * rate (host, required): bytes/s (kinds 0-2) or FLOP/s (kind 3); seconds
+ * (host, nullable): the timed launches' duration. EINVAL for a kind outside
+ * 0..3, iters outside [1, 2^20] or a bad size; ENOMEM, EHIP as usual. */
+int sparrow_peak(int32_t kind, int64_t size, int32_t iters, void *hip_stream, double *rate,
+                 double *seconds);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsparrow.so")
 SOURCES = [os.path.join(CSRC, "sparrow.hip"), os.path.join(CSRC, "sparrow_ring.hip"),
-           os.path.join(CSRC, "sparrow_learner.hip")]
+           os.path.join(CSRC, "sparrow_learner.hip"),
+           os.path.join(CSRC, "sparrow_peaks.hip")]
 HEADERS = [os.path.join(CSRC, "sparrow_device.h"), os.path.join(CSRC, "sparrow_qnet.h"),
            os.path.join(CSRC, "sparrow_mlp.h"), os.path.join(CSRC, "sparrow_ring_dev.h"),
            os.path.join(CSRC, "sparrow_host.h"),

@@ -306,9 +306,11 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if (live) {
         const StepOut o = step_env<L, TK>(p, ln, m, e, a_hat);
         const bool last = t == p.K_steps - 1;
-        float* orow = last ? p.obs + (size_t)i * D : nullptr;
+        const size_t ti = (size_t)t * N + i;
+        float* orow = last ? p.obs + (size_t)i * D : (p.t_obs ? p.t_obs + ti * D : nullptr);
         float* crow = (last || !kQ) ? p.cur_obs + (size_t)i * D : nullptr;
-        int16_t* hk = last ? p.hit_k + (size_t)i * p.n_rays : nullptr;
+        int16_t* hk = last ? p.hit_k + (size_t)i * p.n_rays
+                           : (p.t_hits ? p.t_hits + ti * p.n_rays : nullptr);
         bool free_pose = true;  // not done: the step's collision test passed
         if constexpr (COLL) {
           const int32_t s0 = ring_slot(p, t, i);
@@ -1144,7 +1146,8 @@ int sparrow_act(sparrow_env* e, const float* obs, int32_t* actions) {
 static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int32_t* actions,
                           float* reward, uint8_t* done, float* obs, bool use_graph,
                           const RingDev* ring = nullptr, int32_t ring_head = 0,
-                          bool ring_terminal = true) {
+                          bool ring_terminal = true, float* t_obs = nullptr,
+                          int16_t* t_hits = nullptr) {
   const int reserve = q ? (int)qnet_lds_bytes(e->qp) : 0;
   const int budget_words = (e->lds_max - reserve) / 4;
   Groups* gr = nullptr;
@@ -1172,6 +1175,8 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   p.r_actions = actions;
   p.r_reward = reward;
   p.r_done = done;
+  p.t_obs = t_obs;
+  p.t_hits = t_hits;
   if (ring) {
     p.ring = *ring;
     p.ring_head = ring_head;
@@ -1229,6 +1234,29 @@ int sparrow_rollout(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* action
   if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
   return launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done,
                         obs, true);
+}
+
+int sparrow_rollout_trace(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* actions,
+                          float* reward, uint8_t* done, float* obs, float* obs_steps,
+                          int16_t* hits_steps) {
+  if (!e || !reward || !done || !obs || K < 1) return fail(SPARROW_EINVAL, "bad argument");
+  if (use_qnet && !e->has_qnet) return fail(SPARROW_EINVAL, "no Q-network installed");
+  if (use_qnet && !qnet_in_registers(qnet_kind(e->qp)))
+    return fail(SPARROW_EUNSUPPORTED,
+                "the fused rollout needs a width-256 actor; use sparrow_act with width 512");
+  if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
+  const int rc = launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward,
+                                done, obs, false, nullptr, 0, true, obs_steps, hits_steps);
+  if (rc) return rc;
+  // the last step's rows are the launch's final observation and hit indices
+  const size_t N = (size_t)e->cfg.n_envs, D = (size_t)obs_dim(e), nr = (size_t)e->cfg.n_rays;
+  if (obs_steps)
+    HIP_TRY(hipMemcpyAsync(obs_steps + (size_t)(K - 1) * N * D, obs, N * D * sizeof(float),
+                           hipMemcpyDeviceToDevice, e->stream));
+  if (hits_steps)
+    HIP_TRY(hipMemcpyAsync(hits_steps + (size_t)(K - 1) * N * nr, e->hit_k,
+                           N * nr * sizeof(int16_t), hipMemcpyDeviceToDevice, e->stream));
+  return SPARROW_OK;
 }
 
 int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32_t use_qnet,

@@ -177,6 +177,10 @@ struct Params {
   int32_t* r_actions;
   float* r_reward;
   uint8_t* r_done;
+  // rollout trace (nullable): observation [K][N][obs_dim] and hit indices
+  // [K][N][n_rays] of steps 0 .. K - 2 (the last step's are obs and hit_k)
+  float* t_obs;
+  int16_t* t_hits;
   // actor
   const float* eps;         // [N]
   // collecting rollout: the experience buffer and the slot of its next add

@@ -24,7 +24,7 @@ STATE_I = ("t", "delay", "q0", "q1")
 
 EXPORTS = (
     "sparrow_create", "sparrow_reset", "sparrow_step", "sparrow_random_actions",
-    "sparrow_set_qnet", "sparrow_qnet_forward", "sparrow_act", "sparrow_rollout",
+    "sparrow_set_qnet", "sparrow_qnet_forward", "sparrow_act", "sparrow_rollout", "sparrow_rollout_trace",
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
     "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
@@ -34,6 +34,7 @@ EXPORTS = (
     "sparrow_obs_dim",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
     "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
+    "sparrow_peak",
     "sparrow_learner_create", "sparrow_learner_update", "sparrow_learner_q",
     "sparrow_learner_export_bf16", "sparrow_learner_read", "sparrow_learner_steps",
     "sparrow_learner_destroy",
@@ -105,6 +106,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_qnet_forward": (I32, [P, P, I32, P, P]),
             "sparrow_act": (I32, [P, P, P]),
             "sparrow_rollout": (I32, [P, I32, I32, P, P, P, P]),
+            "sparrow_rollout_trace": (I32, [P, I32, I32, P, P, P, P, P, P]),
             "sparrow_rollout_collect": (I32, [P, P, I32, I32, I32, P, P, P, P]),
             "sparrow_set_task": (I32, [P, C.POINTER(TaskStruct)]),
             "sparrow_step_collect": (I32, [P, P, P, P, P, P, P, I32]),
@@ -144,6 +146,8 @@ def lib(path: str = LIB_PATH):
             "sparrow_ring_head": (C.c_int64, [P]),
             "sparrow_ring_status": (I32, [P]),
             "sparrow_ring_destroy": (None, [P]),
+            "sparrow_peak": (I32, [I32, C.c_int64, I32, P, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -361,6 +365,32 @@ class Env:
         _check(lib().sparrow_rollout(self._h, K, int(bool(use_qnet)), _ptr(actions),
                                      _ptr(reward), _ptr(done), _ptr(obs)))
         return actions, reward, done, obs
+
+    def rollout_trace(self, K, use_qnet, actions=None, reward=None, done=None, obs=None,
+                      obs_steps=None, hits_steps=None):
+        """rollout() that also returns every step's observation [K][N][obs_dim]
+        and per-ray hit indices [K][N][n_rays] (sparrow_rollout_trace)."""
+        torch = self.torch
+        dev = self.device
+        n = self.n
+        actions = torch.zeros(K, n, dtype=torch.int32, device=dev) if actions is None else actions
+        reward = torch.zeros(K, n, dtype=torch.float32, device=dev) if reward is None else reward
+        done = torch.zeros(K, n, dtype=torch.uint8, device=dev) if done is None else done
+        obs = self.obs if obs is None else obs
+        if obs_steps is None:
+            obs_steps = torch.zeros(K, n, self.obs_dim, dtype=torch.float32, device=dev)
+        if hits_steps is None:
+            hits_steps = torch.zeros(K, n, self.n_rays, dtype=torch.int16, device=dev)
+        self._b(actions, torch.int32, K * n, "actions", nullable=True)
+        self._b(reward, torch.float32, K * n, "reward")
+        self._b(done, torch.uint8, K * n, "done")
+        self._b(obs, torch.float32, n * self.obs_dim, "obs")
+        self._b(obs_steps, torch.float32, K * n * self.obs_dim, "obs_steps")
+        self._b(hits_steps, torch.int16, K * n * self.n_rays, "hits_steps")
+        _check(lib().sparrow_rollout_trace(self._h, K, int(bool(use_qnet)), _ptr(actions),
+                                           _ptr(reward), _ptr(done), _ptr(obs), _ptr(obs_steps),
+                                           _ptr(hits_steps)))
+        return actions, reward, done, obs, obs_steps, hits_steps
 
     def rollout_collect(self, ring, K, use_qnet, actions=None, reward=None, done=None, obs=None,
                         terminal_obs=True):
@@ -616,3 +646,18 @@ class Tfm:
     @property
     def learner_sleep(self):
         return float(lib().sparrow_tfm_learner_sleep(self._h))
+
+
+PEAK_LDS128, PEAK_LDS32, PEAK_HBM_COPY, PEAK_MFMA_BF16 = 0, 1, 2, 3
+
+
+def peak(kind: int, size: int = 0, iters: int = 4096, stream=None):
+    """Peak-rate probe of the current device (sparrow_peak): returns
+    (rate, seconds), rate in bytes/s for the LDS and HBM probes and FLOP/s
+    for the MFMA probe. Synchronises."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rate, secs = C.c_double(), C.c_double()
+    _check(lib().sparrow_peak(int(kind), int(size), int(iters), C.c_void_p(st.cuda_stream),
+                              C.byref(rate), C.byref(secs)))
+    return rate.value, secs.value

@@ -25,6 +25,8 @@ def compare_obs(g, o, n_rays, noisy=True, where=""):
     g = np.asarray(g, np.float32)
     o = np.asarray(o, np.float32)
     assert g.shape == o.shape, where
+    if g.shape[0] == 0:
+        return
     rg, ro = g[:, :n_rays], o[:, :n_rays]
     if noisy:
         d = np.abs(rg.astype(np.float64) - ro)
@@ -182,18 +184,23 @@ def compare_obs_relative(g, o, n_rays, noisy=True, where=""):
     assert b.size == 0 or b.max() <= BEARING_TOL, f"{where}: alpha differs by {b.max()}"
 
 
-def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where, reward_tol=0.0):
+def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where, reward_tol=0.0,
+                   obs_steps=None, hits_steps=None, live=None, min_live=0.9):
     """Step the oracle with its own FP64 actor + VEM next to a GPU rollout
     (acts, rew, done: [K][N]) and compare; eps is the per-env VEM array, or
     a function of the step index giving it. Explored actions equal the
     oracle's draw; a greedy action equals the oracle's bf16-activation argmax
     wherever qnet_rounded_bound settles it; an env stays compared while its
     actions equal the FP64 actor's (its trajectory is then the oracle's).
+    With obs_steps / hits_steps ([K][N][...] from a traced rollout), every
+    step's observation and hit indices of the compared envs are checked too.
+    live: the envs still on the oracle's trajectory when the rollout starts
+    (default all); at least min_live of them must stay on it.
     Returns the mask of envs compared to the end and the oracle's last
     observation."""
     import oracle
     K, N = acts.shape
-    live = np.ones(N, bool)
+    live = np.ones(N, bool) if live is None else live.copy()
     n_settled = n_greedy = n_agree = 0
     for t in range(K):
         q64 = oracle.qnet_f64(dims, w, b, o_obs)
@@ -209,13 +216,69 @@ def actor_lockstep(orc, dims, w, b, eps, o_obs, acts, rew, done, where, reward_t
         n_settled += int(m.sum())
         n_agree += int((live & ~exb & (acts[t] == a_o)).sum())
         live &= acts[t] == a_o
-        r = orc.step(a_o)
+        r = orc.step(a_o, hit_k=hits_steps is not None)
         compare_reward(rew[t][live], r["reward"][live], reward_tol, w_)
         compare_exact(done[t][live], r["done"][live], "done", w_)
+        if hits_steps is not None:
+            compare_exact(hits_steps[t][live], r["hit_k"][live], "hit_k", w_)
+        if obs_steps is not None:
+            compare_obs(obs_steps[t][live], r["obs"][live], obs_steps.shape[2] - 4, True, w_ + " obs")
         o_obs = r["obs"]
     print(f"{where}: {live.sum()} of {N} envs compared over {K} steps; {n_settled} of "
           f"{n_greedy} greedy choices settled by the bound; agreement with the FP64 actor "
           f"{n_agree / max(n_greedy, 1):.5f}", flush=True)
-    assert live.mean() >= 0.9, (live.sum(), N)
+    assert live.mean() >= min_live, (live.sum(), N)
     assert n_agree >= 0.995 * n_greedy
     return live, o_obs
+
+
+def qnet_f64_threads(dims, w, b, obs, round_act=False, workers=16):
+    """oracle.qnet_f64 over row chunks on a thread pool (the C call releases
+    the GIL); same values as one call."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    obs = np.ascontiguousarray(obs, np.float32)
+    if obs.shape[0] < 4096:
+        return oracle.qnet_f64(dims, w, b, obs, round_act=round_act)
+    chunks = np.array_split(obs, 4 * workers)
+    with ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(lambda c: oracle.qnet_f64(dims, w, b, c, round_act=round_act), chunks))
+    return np.concatenate(parts)
+
+
+class ExploreDraws:
+    """VEM exploration flags of n envs by global step, from the oracle's own
+    VEM (the envs share one small map: only the draw counters matter)."""
+
+    def __init__(self, seed, n, eps):
+        import oracle
+        from paper_2305_04180_amd import inputs
+        cfg = inputs.workload("c2", n_envs=n, seed=seed)
+        maps = inputs.single_maps([np.zeros((16, 16), np.uint8)], n_envs=n)
+        self.orc = oracle.Oracle(cfg, maps)
+        self.eps = np.ascontiguousarray(eps, np.float32)
+        self.q0 = np.zeros((n, 7))
+
+    def flags(self, g):
+        self.orc.global_step = int(g)
+        _, ex = self.orc.vem(self.q0, self.eps)
+        return ex.astype(bool)
+
+
+def traced_actor_rows(env, launches, K, sample):
+    """Fused rollouts with every step traced (sparrow_rollout_trace): for the
+    sampled envs, the observation each step's actor saw, the action it took
+    and the global step, row by row (step-major)."""
+    import torch
+    prev = to_np(env.obs)[sample]
+    obs_in, acts, steps = [], [], []
+    for _ in range(launches):
+        g0 = env.global_step
+        a, _, _, _, obs_t, _ = env.rollout_trace(K, True)
+        torch.cuda.synchronize()
+        o = to_np(obs_t)[:, sample]
+        obs_in.append(np.concatenate([prev[None], o[:-1]]))
+        acts.append(to_np(a)[:, sample])
+        steps.append(g0 + np.arange(K))
+        prev = o[-1]
+    return np.concatenate(obs_in), np.concatenate(acts), np.concatenate(steps)

@@ -59,6 +59,17 @@ def test_m4096_fused_rollout_every_env(torch_gpu, m_maps):
     gf, gi = env.get_state()
     of, oi = orc.get_state()
     compare_state(gf[live], gi[live], of[live], oi[live], "final state")
+    # the next 32 steps traced (same kernel and variant): every step's
+    # observation and hit indices of the envs still on the oracle's trajectory
+    acts, rew, done, obs, obs_t, hits_t = env.rollout_trace(K, True)
+    torch.cuda.synchronize()
+    live, o_obs = actor_lockstep(orc, dims, w, b, eps, o_obs, to_np(acts), to_np(rew),
+                                 to_np(done), "m4096 traced", obs_steps=to_np(obs_t),
+                                 hits_steps=to_np(hits_t), live=live, min_live=0.8)
+    compare_obs(to_np(obs)[live], o_obs[live], cfg["n_rays"], True, "traced final obs")
+    gf, gi = env.get_state()
+    of, oi = orc.get_state()
+    compare_state(gf[live], gi[live], of[live], oi[live], "traced final state")
 
 
 def test_m4096_plain_step_every_env(torch_gpu, m_maps):

@@ -134,8 +134,10 @@ def test_rollout_uniform_parity(torch_gpu):
         env.set_variant(1, *variant)
         env.reset()
         orc.reset()
-        acts, rew, done, obs = env.rollout(K, use_qnet=False)
+        # the first launch returns every step's observation and hit indices
+        acts, rew, done, obs, obs_t, hits_t = env.rollout_trace(K, use_qnet=False)
         torch.cuda.synchronize()
+        obs_t, hits_t = to_np(obs_t), to_np(hits_t)
         for t in range(K):
             a = orc.uniform_actions()
             r = orc.step(a, hit_k=True)
@@ -143,6 +145,8 @@ def test_rollout_uniform_parity(torch_gpu):
             compare_exact(to_np(acts[t]), a, "actions", w)
             compare_exact(to_np(rew[t]), r["reward"], "reward", w)
             compare_exact(to_np(done[t]), r["done"], "done", w)
+            compare_exact(hits_t[t], r["hit_k"], "hit_k", w)
+            compare_obs(obs_t[t], r["obs"], env.n_rays, True, w + " obs")
         compare_obs(to_np(obs), r["obs"], env.n_rays, True, "rollout final obs")
         compare_exact(to_np(env.debug_hits()), r["hit_k"], "hit_k", "rollout final")
         gf, gi = env.get_state()
@@ -275,10 +279,11 @@ def test_fused_rollout_parity(torch_gpu):
         env.set_variant(1, *variant)
         env.reset()
         o_obs, _ = orc.reset()
-        acts, rew, done, obs = env.rollout(K, use_qnet=True)
+        acts, rew, done, obs, obs_t, hits_t = env.rollout_trace(K, use_qnet=True)
         torch.cuda.synchronize()
         live, o_obs = actor_lockstep(orc, dims, w, b, eps, o_obs, to_np(acts), to_np(rew),
-                                     to_np(done), f"fused {variant}")
+                                     to_np(done), f"fused {variant}", obs_steps=to_np(obs_t),
+                                     hits_steps=to_np(hits_t))
         compare_obs(to_np(obs)[live], o_obs[live], env.n_rays, True, f"fused {variant} final obs")
         gf, gi = env.get_state()
         of, oi = orc.get_state()
