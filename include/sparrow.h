@@ -330,6 +330,19 @@ int sparrow_ring_sample(sparrow_ring *ring, int32_t B, uint32_t draw, float *s, 
  * [0, size), checked on the host before anything is launched). */
 int sparrow_ring_gather(sparrow_ring *ring, int32_t n, const int32_t *slots_host, float *s,
                         int32_t *a, float *r, float *s_next, uint8_t *done);
+/* sparrow_ring_gather for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, such as tight serving loops or harnesses
+ * that forbid it): the same read-back and outputs, with the slots staged in
+ * a fixed array that the library holds on each GPU (SPARROW_GATHER_STATIC_MAX
+ * int32 entries, 256 KiB, kept until the process ends) instead of a
+ * library-allocated buffer. The call allocates nothing; n above
+ * SPARROW_GATHER_STATIC_MAX is EINVAL, as are slots outside [0, size).
+ * Synchronises the ring's stream before returning. Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other threads,
+ * other rings' streams) race, so the caller serialises them. */
+#define SPARROW_GATHER_STATIC_MAX 65536
+int sparrow_ring_gather_static(sparrow_ring *ring, int32_t n, const int32_t *slots_host, float *s,
+                               int32_t *a, float *r, float *s_next, uint8_t *done);
 int64_t sparrow_ring_size(const sparrow_ring *ring);
 int64_t sparrow_ring_head(const sparrow_ring *ring);
 /* Synchronise the ring's stream; SPARROW_OK or the HIP error. */

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -148,11 +149,47 @@ int grid_for(int64_t work) {
 
 }  // namespace
 
+// Staging of sparrow_ring_gather_static: the slots of one gather, copied from
+// the host. Each GPU the library runs on holds one copy of the array until
+// the process ends; every call on that GPU shares it. In host code the name
+// stands for no device address: its address on a device comes from
+// hipGetSymbolAddress with that device current (gather_scratch below).
+constexpr int32_t kGatherStaticMax = SPARROW_GATHER_STATIC_MAX;
+static __device__ __align__(256) int32_t scratch[kGatherStaticMax];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch[kMaxDevices] = {};
+
+// The staging array's address on `device`, looked up once per device with
+// that device current (the caller's current device is restored).
+int gather_scratch(int device, int32_t** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(SPARROW_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) HIP_TRY(hipSetDevice(cur));
+    if (err != hipSuccess || !ptr)
+      return fail(SPARROW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(err));
+    g_scratch[device] = (int32_t*)ptr;
+  }
+  *out = g_scratch[device];
+  return SPARROW_OK;
+}
+}  // namespace
+
 struct sparrow_ring {
   RingDev dev{};
   void* block = nullptr;
   int32_t* d_slots = nullptr;  // staging for sparrow_ring_gather
   int32_t d_slots_cap = 0;
+  int device = 0;                   // the device holding the ring
+  int32_t* gather_static = nullptr;  // this device's staging array (sparrow_ring_gather_static)
   int64_t head = 0, size = 0;
   uint32_t key0 = 0, key1 = 0;
   hipStream_t stream = nullptr;
@@ -166,6 +203,14 @@ int sparrow_ring_create(int32_t capacity, int32_t n_rays, uint64_t seed, void* h
   if (n_rays < 1 || n_rays > SPARROW_MAX_RAYS) return fail(SPARROW_EINVAL, "n_rays out of range");
   auto* R = new sparrow_ring();
   R->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&R->device) != hipSuccess) {
+    delete R;
+    return fail(SPARROW_EHIP, "hipGetDevice failed");
+  }
+  if (const int rc = gather_scratch(R->device, &R->gather_static)) {
+    delete R;
+    return rc;
+  }
   R->key0 = (uint32_t)seed;
   R->key1 = (uint32_t)(seed >> 32);
   const size_t cap = (size_t)capacity;
@@ -261,6 +306,24 @@ int sparrow_ring_gather(sparrow_ring* R, int32_t n, const int32_t* slots_host, f
   HIP_TRY(hipMemcpyAsync(R->d_slots, slots_host, sizeof(int32_t) * (size_t)n,
                          hipMemcpyHostToDevice, R->stream));
   const int rc = ring_read(R, n, 0u, R->d_slots, s, a, r, s_next, done, nullptr);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(R->stream));
+  return SPARROW_OK;
+}
+
+int sparrow_ring_gather_static(sparrow_ring* R, int32_t n, const int32_t* slots_host, float* s,
+                               int32_t* a, float* r, float* s_next, uint8_t* done) {
+  if (!R || (n > 0 && !slots_host)) return fail(SPARROW_EINVAL, "NULL argument");
+  if (n < 0 || n > kGatherStaticMax)
+    return fail(SPARROW_EINVAL, "gather size must be in [0, SPARROW_GATHER_STATIC_MAX]");
+  for (int32_t b = 0; b < n; ++b)
+    if (slots_host[b] < 0 || slots_host[b] >= R->size)
+      return fail(SPARROW_EINVAL, "slot outside the stored range");
+  if (n == 0) return SPARROW_OK;
+  // staged in this device's static array (looked up at create): no allocation
+  HIP_TRY(hipMemcpyAsync(R->gather_static, slots_host, sizeof(int32_t) * (size_t)n,
+                         hipMemcpyHostToDevice, R->stream));
+  const int rc = ring_read(R, n, 0u, R->gather_static, s, a, r, s_next, done, nullptr);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(R->stream));
   return SPARROW_OK;

@@ -33,7 +33,7 @@ EXPORTS = (
     "sparrow_set_task",
     "sparrow_obs_dim",
     "sparrow_ring_create", "sparrow_ring_push", "sparrow_ring_sample", "sparrow_ring_gather",
-    "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
+    "sparrow_ring_gather_static", "sparrow_ring_size", "sparrow_ring_head", "sparrow_ring_status", "sparrow_ring_destroy",
     "sparrow_peak",
     "sparrow_learner_create", "sparrow_learner_update", "sparrow_learner_q",
     "sparrow_learner_export_bf16", "sparrow_learner_read", "sparrow_learner_steps",
@@ -142,6 +142,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_ring_push": (I32, [P, I32, P, P, P, P, P, P]),
             "sparrow_ring_sample": (I32, [P, I32, U32, P, P, P, P, P, P]),
             "sparrow_ring_gather": (I32, [P, I32, P, P, P, P, P, P]),
+            "sparrow_ring_gather_static": (I32, [P, I32, P, P, P, P, P, P]),
             "sparrow_ring_size": (C.c_int64, [P]),
             "sparrow_ring_head": (C.c_int64, [P]),
             "sparrow_ring_status": (I32, [P]),
@@ -534,6 +535,16 @@ class Ring:
                                          _ptr(r), _ptr(sn), _ptr(d)))
         return s, a, r, sn, d
 
+    def gather_static(self, slots):
+        """gather() through sparrow_ring_gather_static: the slots are staged
+        in the library's fixed per-GPU array (at most GATHER_STATIC_MAX), and
+        the call allocates no device memory."""
+        sl = np.ascontiguousarray(slots, np.int32)
+        s, a, r, sn, d = self._outs(len(sl), None)
+        _check(lib().sparrow_ring_gather_static(self._h, len(sl), sl.ctypes.data, _ptr(s), _ptr(a),
+                                                _ptr(r), _ptr(sn), _ptr(d)))
+        return s, a, r, sn, d
+
     def status(self) -> int:
         return lib().sparrow_ring_status(self._h)
 
@@ -647,6 +658,8 @@ class Tfm:
     def learner_sleep(self):
         return float(lib().sparrow_tfm_learner_sleep(self._h))
 
+
+GATHER_STATIC_MAX = 65536  # SPARROW_GATHER_STATIC_MAX
 
 PEAK_LDS128, PEAK_LDS32, PEAK_HBM_COPY, PEAK_MFMA_BF16 = 0, 1, 2, 3
 
