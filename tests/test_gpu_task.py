@@ -152,6 +152,20 @@ def test_task_actor_forward_and_fused_rollout(torch_gpu):
     of, oi = orc.get_state()
     compare_state(gf[live], gi[live], of[live], oi[live], "task fused final")
     assert env.status() == 0
+    # the 32-lanes-per-env variant of the fused rollout on fresh envs
+    env2, orc2 = make(cfg, maps)
+    env2.set_qnet(dims, w, b, env2.vem_epsilon(env2.n, 0.01, 0.29))
+    env2.set_variant(1, 8, 32)
+    env2.reset()
+    o_obs2, _ = orc2.reset()
+    acts, rew, done, obs = env2.rollout(K, use_qnet=True)
+    torch.cuda.synchronize()
+    live, _ = actor_lockstep(orc2, dims, w, b, eps, o_obs2, to_np(acts), to_np(rew),
+                             to_np(done), "task fused (8, 32)", reward_tol=REWARD_TOL)
+    gf, gi = env2.get_state()
+    of, oi = orc2.get_state()
+    compare_state(gf[live], gi[live], of[live], oi[live], "task fused (8, 32) final")
+    assert env2.status() == 0
     # the ring stores the four scalars of the target state only
     ring = sparrow.Ring(4096, cfg["n_rays"])
     with pytest.raises(sparrow.SparrowError):
