@@ -364,7 +364,7 @@ def learner_leg(updates=200, batch=256):
     resident 256-row mini-batches of the 36-256-256-7 network, HIP events
     around them. Algorithmic FLOP per update: three forward passes (online
     s, online s', target s') and the backward pass of one (about two
-    forwards), FP32 on the vector units."""
+    forwards), FP32 on the vector units, as tiled products."""
     import torch
     from paper_2305_04180_amd import inputs, sparrow
     dims = (36, 256, 256, 7)
@@ -395,8 +395,9 @@ def learner_leg(updates=200, batch=256):
             "roofline": {"bound": "latency", "achieved": round(tf, 3), "peak": 157.3,
                          "unit": "TFLOP/s", "frac": round(tf / 157.3, 5),
                          "flop_per_update": int(flop),
-                         "note": "FP32 vector peak; a 256-row update is a chain of small "
-                                 "dependent kernels"}}
+                         "note": "FP32 vector peak; a 256-row update is seven small dependent "
+                                 "launches (three forward layers, loss and output error, two "
+                                 "backward product launches, Adam)"}}
 
 
 def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
