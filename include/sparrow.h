@@ -284,6 +284,15 @@ int sparrow_get_variant(const sparrow_env *env, int32_t kernel, int32_t *envs_pe
  * state (the env itself is not advanced), keep the fastest. Synchronises.
  * report (host, nullable) receives a JSON summary of the timings. */
 int sparrow_autotune(sparrow_env *env, int32_t steps, char *report, int32_t report_len);
+/* sparrow_autotune with its choice kept in a file (host path, JSON lines):
+ * the variants chosen for the same device and workload shape (envs, rays,
+ * march, robot radius, task, actor sizes and the count of envs per map
+ * shape) are read back and installed without timing; otherwise the
+ * variants are timed as by sparrow_autotune and the choice is appended.
+ * report receives {"cached": true, "chosen": ...} when read from the file.
+ * EINVAL if the file cannot be appended to. */
+int sparrow_autotune_cached(sparrow_env *env, int32_t steps, const char *path, char *report,
+                            int32_t report_len);
 
 /* Synchronise the stream and return the sticky asynchronous error (ERESET)
  * or a HIP error, else SPARROW_OK. */

@@ -449,6 +449,7 @@ struct sparrow_env {
   int device = 0;
   int lds_max = 65536;
   int n_cu = 256;
+  std::string device_name;  // the device's marketing name and architecture
   int n_maps = 0;
   uint32_t g = 0;
   bool was_reset = false;
@@ -798,6 +799,8 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
   e->stream = (hipStream_t)hip_stream;
   e->device = dev;
   e->n_cu = prop.multiProcessorCount;
+  e->device_name = std::string(prop.name) + " " + prop.gcnArchName + " " +
+                   std::to_string(prop.multiProcessorCount) + " CUs";
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
     e->lds_max = lds;
@@ -1489,6 +1492,71 @@ int sparrow_autotune(sparrow_env* e, int32_t steps, char* report, int32_t report
                 best_epw[0], best_L[0], best_epw[1], best_L[1], K);
   js += buf;
   if (report && report_len > 0) std::snprintf(report, report_len, "%s", js.c_str());
+  return SPARROW_OK;
+}
+
+// The autotune cache key: the device, the env's shape (envs, rays, march,
+// task, actor) and its maps (the packed size of each distinct map shape with
+// the number of envs using it). Two envs with equal keys run the same
+// kernels on the same amount of work per group.
+static std::string autotune_key(const sparrow_env* e) {
+  std::map<std::pair<int, int>, int> shapes;
+  for (int32_t m : e->h_env_map) shapes[{e->h_meta[m].W, e->h_meta[m].H}] += 1;
+  const sparrow_config& c = e->cfg;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "n=%d rays=%d range=%.6g ds=%.6g r=%.6g task=%d/%d/%d qnet=%d/%d/%d/%d",
+                c.n_envs, c.n_rays, (double)c.range_cells, (double)c.march_step,
+                (double)c.robot_radius, e->task.n_actions, e->task.reward, e->task.state,
+                e->has_qnet ? e->qp.d0 : 0, e->has_qnet ? e->qp.h1 : 0,
+                e->has_qnet ? e->qp.h2 : 0, e->has_qnet ? e->qp.n_actions : 0);
+  std::string key = e->device_name + " | " + buf + " | maps";
+  for (const auto& kv : shapes)
+    key += " " + std::to_string(kv.first.first) + "x" + std::to_string(kv.first.second) + ":" +
+           std::to_string(kv.second);
+  return key;
+}
+
+int sparrow_autotune_cached(sparrow_env* e, int32_t steps, const char* path, char* report,
+                            int32_t report_len) {
+  if (!e || steps < 1 || !path || !*path) return fail(SPARROW_EINVAL, "bad argument");
+  const std::string key = autotune_key(e);
+  // lines: {"key": "<key>", "step": [epw, L], "rollout": [epw, L]}; the last
+  // line with this key wins
+  int found = 0, se = 0, sl = 0, re = 0, rl = 0;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[4096];
+    const std::string want = "{\"key\": \"" + key + "\", ";
+    while (std::fgets(line, sizeof(line), f)) {
+      if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+      int a = 0, b = 0, c2 = 0, d = 0;
+      if (std::sscanf(line + want.size(), "\"step\": [%d, %d], \"rollout\": [%d, %d]", &a, &b, &c2,
+                      &d) == 4) {
+        found = 1;
+        se = a;
+        sl = b;
+        re = c2;
+        rl = d;
+      }
+    }
+    std::fclose(f);
+  }
+  if (found) {
+    int rc = sparrow_set_variant(e, 0, se, sl);
+    if (!rc) rc = sparrow_set_variant(e, 1, re, rl);
+    if (rc) return rc;
+    if (report && report_len > 0)
+      std::snprintf(report, report_len,
+                    "{\"cached\": true, \"chosen\": {\"step\": [%d, %d], \"rollout\": [%d, %d]}}",
+                    se, sl, re, rl);
+    return SPARROW_OK;
+  }
+  int rc = sparrow_autotune(e, steps, report, report_len);
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return fail(SPARROW_EINVAL, std::string("cannot append to the autotune cache ") + path);
+  std::fprintf(f, "{\"key\": \"%s\", \"step\": [%d, %d], \"rollout\": [%d, %d]}\n", key.c_str(),
+               e->var_epw[0], e->var_L[0], e->var_epw[1], e->var_L[1]);
+  std::fclose(f);
   return SPARROW_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = (
     "sparrow_set_qnet", "sparrow_qnet_forward", "sparrow_act", "sparrow_rollout", "sparrow_rollout_trace",
     "sparrow_debug_hits", "sparrow_get_state", "sparrow_set_state", "sparrow_global_step",
     "sparrow_set_global_step", "sparrow_set_variant", "sparrow_get_variant",
-    "sparrow_autotune", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
+    "sparrow_autotune", "sparrow_autotune_cached", "sparrow_status", "sparrow_destroy", "sparrow_last_error",
     "sparrow_set_vem_schedule", "sparrow_vem_epsilon", "sparrow_rollout_collect",
     "sparrow_step_collect",
     "sparrow_set_task",
@@ -119,6 +119,7 @@ def lib(path: str = LIB_PATH):
             "sparrow_set_variant": (I32, [P, I32, I32, I32]),
             "sparrow_get_variant": (I32, [P, I32, C.POINTER(I32), C.POINTER(I32)]),
             "sparrow_autotune": (I32, [P, I32, C.c_char_p, I32]),
+            "sparrow_autotune_cached": (I32, [P, I32, C.c_char_p, C.c_char_p, I32]),
             "sparrow_status": (I32, [P]),
             "sparrow_destroy": (None, [P]),
             "sparrow_last_error": (C.c_char_p, []),
@@ -444,9 +445,15 @@ class Env:
         _check(lib().sparrow_get_variant(self._h, kernel, C.byref(a), C.byref(b)))
         return a.value, b.value
 
-    def autotune(self, steps=8):
+    def autotune(self, steps=8, cache=None):
+        """Time the kernel variants and keep the fastest (sparrow_autotune);
+        with cache (a file path), reuse the choice recorded there for the
+        same device and workload shape (sparrow_autotune_cached)."""
         buf = C.create_string_buffer(1 << 16)
-        _check(lib().sparrow_autotune(self._h, steps, buf, len(buf)))
+        if cache:
+            _check(lib().sparrow_autotune_cached(self._h, steps, str(cache).encode(), buf, len(buf)))
+        else:
+            _check(lib().sparrow_autotune(self._h, steps, buf, len(buf)))
         return json.loads(buf.value.decode() or "{}")
 
     def status(self):

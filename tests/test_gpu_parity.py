@@ -418,3 +418,37 @@ def test_failed_set_qnet_keeps_the_installed_network(torch_gpu):
     a1 = env.act(obs)
     torch.cuda.synchronize()
     compare_exact(to_np(a1), to_np(a0), "actions after a failed set_qnet", "set_qnet")
+
+
+def test_autotune_cache(torch_gpu, tmp_path):
+    """sparrow_autotune_cached: the first call times the variants and records
+    the choice; an env of the same shape reads it back without timing; an
+    env of another shape misses the record."""
+    from paper_2305_04180_amd import sparrow
+    cfg = inputs.workload("c2", n_envs=40)
+    banner("autotune cache N=40")
+    maps = inputs.make_maps(cfg)
+    path = tmp_path / "autotune.jsonl"
+    env = sparrow.Env(cfg, maps)
+    _qnet_setup(cfg, env)
+    env.reset()
+    rep = env.autotune(steps=2, cache=path)
+    assert "step" in rep and not rep.get("cached")
+    chosen = (env.get_variant(0), env.get_variant(1))
+    assert len(path.read_text().splitlines()) == 1
+    env2 = sparrow.Env(cfg, maps)
+    _qnet_setup(cfg, env2)
+    env2.reset()
+    env2.set_variant(0, 1, 16)
+    env2.set_variant(1, 1, 16)
+    rep2 = env2.autotune(steps=2, cache=path)
+    assert rep2.get("cached") is True
+    assert (env2.get_variant(0), env2.get_variant(1)) == chosen
+    assert len(path.read_text().splitlines()) == 1
+    cfg3 = inputs.workload("c2", n_envs=41)
+    env3 = sparrow.Env(cfg3, inputs.make_maps(cfg3))
+    _qnet_setup(cfg3, env3)
+    env3.reset()
+    assert not env3.autotune(steps=2, cache=path).get("cached")
+    assert len(path.read_text().splitlines()) == 2
+    assert env.status() == env2.status() == env3.status() == 0
