@@ -224,6 +224,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
   const int N = p.n_envs, D = p.obs_dim;
   typename QC::Weights qw;
   qw.load(qp, threadIdx.x);
+  W3Frag<QC> w3;
+  qnet_load_w3<QC>(qp, threadIdx.x, w3);
   // LDS: [march_pad set words][maps region][march_pad set words][actor]
   uint32_t* const maps = lds + p.march_pad;
   for (int k = threadIdx.x; k < p.march_pad; k += blockDim.x) {
@@ -253,13 +255,13 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if constexpr (kQ) eps = p.eps[i];
     }
     uint16_t* act_in = nullptr;
-    W3Frag<QC> w3;
     // Per-step random draws (VEM exploration, or the uniform actions) are
     // taken L steps at a time: lane q of the env draws for step g + q, and
     // step t reads lane t % L of its env.
     int draws = -1;
+    float o_rew = 0.0f;
+    int o_done = 0, o_act = 0;
     if constexpr (kQ) {
-      qnet_load_w3<QC>(qp, threadIdx.x, w3);
       if (slot < kQRows) act_in = qnet_input_row(qp, lds, slot);
       // the current observation feeds the first actor step
       if (live)
@@ -296,9 +298,9 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
       if constexpr (kQ) {
         // barriers inside; the wave's env columns are slot % 16
         // LDS reads run ahead of the MFMAs where the registers allow it
-        const f32x4 tile = qnet_forward_group<QC, (L >= 32 ? 4 : 1)>(qp, qw, w3, lds, threadIdx.x);
-        float qa[kNumActions];
-        const int greedy = qnet_q_values(qp, tile, slot & 15, qa, TaskOf<TK>::n_actions(p));
+        const float qsum = qnet_forward_sum<QC, (L >= 32 ? 4 : 1)>(qp, qw, w3, lds, threadIdx.x,
+                                                                  slot & 15);
+        const int greedy = qnet_greedy<L>(qsum, ln.seg, TaskOf<TK>::n_actions(p));
         if (live) a_hat = draw >= 0 ? draw : greedy;
       } else {
         a_hat = draw;
@@ -352,17 +354,25 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
           observe<L, TK, kUnroll, true>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise,
                                         inv_dn, orow, crow, hk, act_in, free_pose);
         }
-        if (ln.q == 0) {
-          const size_t o_idx = (size_t)t * N + i;
-          if (p.r_reward) p.r_reward[o_idx] = o.reward;
-          if (p.r_done) p.r_done[o_idx] = o.done;
-          if (p.r_actions) p.r_actions[o_idx] = a_hat;
+        // step t's reward, done and action wait in lane t % L of the env;
+        // every L steps (and after the last) each lane writes the step it
+        // holds: one store instruction per L steps instead of one per step
+        const int tq = t % L;
+        if (ln.q == tq) {
+          o_rew = o.reward;
+          o_done = o.done;
+          o_act = a_hat;
+        }
+        if (tq == L - 1 || t == p.K_steps - 1) {
+          if (ln.q <= tq) {
+            const size_t o_idx = (size_t)(t - tq + ln.q) * N + i;
+            if (p.r_reward) p.r_reward[o_idx] = o_rew;
+            if (p.r_done) p.r_done[o_idx] = (uint8_t)o_done;
+            if (p.r_actions) p.r_actions[o_idx] = o_act;
+          }
         }
       }
-      if constexpr (kQ) {
-        qnet_load_w3<QC>(qp, threadIdx.x, w3);  // next step's, in the barrier's shadow
-        __syncthreads();
-      }
+      if constexpr (kQ) __syncthreads();
     }
     if (live && ln.q == 0) store_env(p.s, i, e);
   }
@@ -394,11 +404,12 @@ __global__ void __launch_bounds__(512) k_qnet(QParams qp, const float* __restric
       row[k] = (r0 + r < n && k < qp.d0) ? bf16_rne(obs[(size_t)(r0 + r) * qp.d0 + k]) : 0;
     }
     __syncthreads();
-    const f32x4 tile = qnet_forward_group<QC, 4>(qp, qw, w3, lds, threadIdx.x);
+    qnet_forward_sum<QC, 4>(qp, qw, w3, lds, threadIdx.x, 0);
     // wave 0 reports the 16 rows; lane r < 16 takes row r
     const int r = threadIdx.x & 15;
     float qa[kNumActions];
-    const int gi = qnet_q_values(qp, tile, r, qa, qp.n_actions);
+    int gi = 0;
+    if (threadIdx.x < kQRows) gi = qnet_q_row(qp, lds, r, qa, qp.n_actions);
     if (threadIdx.x < kQRows && r0 + r < n) {
       const int row = r0 + r;
       if (q)

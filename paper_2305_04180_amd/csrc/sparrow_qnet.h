@@ -9,14 +9,16 @@
 // Layout. Eight waves serve 16 rows (envs) at a time. Each wave keeps its
 // slice of the weights resident in VGPRs for the whole kernel (weight-
 // stationary): layer 1 and layer 2 are split by output tiles of 16 hidden
-// units; every wave computes the whole (16-row) layer 3 for the 16 envs so
-// that its own envs' Q values need no cross-wave reduction (its 8 KB of
-// weights are read per pass from the L1 cache). One MFMA
-// v_mfma_f32_16x16x32_bf16 computes D[h][env] += W[h][k] * X[env][k] over a
-// 16 x 16 x 32 block: A = weight rows, B = activation rows from LDS, D rows =
-// hidden units, D columns = envs. Activations live in LDS as bf16 rows [env][k]
-// padded by 16 bytes against bank conflicts; between layers they are rounded
-// to bf16 (RNE) after bias and ReLU.
+// units. Layer 2's output never leaves the registers: after bias, ReLU and
+// bf16 rounding, the rows a lane holds of its wave's tiles are exactly a B
+// fragment of a K = 32 (or K = 16) block, so one MFMA against the W3 columns
+// of those units (also resident) gives the wave's share of layer 3; the
+// eight partial [action][env] tiles meet in LDS and are summed in wave order.
+// One v_mfma_f32_16x16x32_bf16 computes D[h][env] += W[h][k] * X[env][k] over
+// a 16 x 16 x 32 block: A = weight rows, B = activation rows from LDS, D rows
+// = hidden units, D columns = envs. Activations live in LDS as bf16 rows
+// [env][k] padded by 16 bytes against bank conflicts; between layers they are
+// rounded to bf16 (RNE) after bias and ReLU.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -76,18 +78,20 @@ __device__ __forceinline__ float actor_eps(const QParams& q, const float* eps, i
 }
 
 // LDS: region A holds the bf16 input rows, region B the first hidden layer,
-// region C the second hidden layer.
+// region C the eight waves' partial layer-3 sums, FP32 [env][wave][action]
+// with kQPartStride floats per env (4 more than 8 x 8, so the 16 env rows of
+// one wave's 16-byte writes fall on distinct banks).
+constexpr int kQPartStride = 8 * kQWaves + 4;
 __host__ __device__ inline int qnet_stride0(const QParams& q) { return q.d0p + 8; }
 __host__ __device__ inline int qnet_stride1(const QParams& q) { return q.h1 + 8; }
-__host__ __device__ inline int qnet_stride2(const QParams& q) { return q.h2 + 8; }
 __host__ __device__ inline int qnet_region_a_bytes(const QParams& q) {
   return (kQRows * qnet_stride0(q) * 2 + 15) & ~15;
 }
 __host__ __device__ inline int qnet_region_b_bytes(const QParams& q) {
   return (kQRows * qnet_stride1(q) * 2 + 15) & ~15;
 }
-__host__ __device__ inline int qnet_region_c_bytes(const QParams& q) {
-  return (kQRows * qnet_stride2(q) * 2 + 15) & ~15;
+__host__ __device__ inline int qnet_region_c_bytes(const QParams&) {
+  return kQRows * kQPartStride * 4;
 }
 __host__ __device__ inline size_t qnet_lds_bytes(const QParams& q) {
   return (size_t)qnet_region_a_bytes(q) + (size_t)qnet_region_b_bytes(q) +
@@ -101,9 +105,9 @@ __device__ __forceinline__ uint16_t* qnet_region_b(const QParams& q, uint32_t* l
   return reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds + q.lds_base_words) +
                                      qnet_region_a_bytes(q));
 }
-__device__ __forceinline__ uint16_t* qnet_region_c(const QParams& q, uint32_t* lds) {
-  return reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds + q.lds_base_words) +
-                                     qnet_region_a_bytes(q) + qnet_region_b_bytes(q));
+__device__ __forceinline__ float* qnet_region_c(const QParams& q, uint32_t* lds) {
+  return reinterpret_cast<float*>(reinterpret_cast<char*>(lds + q.lds_base_words) +
+                                  qnet_region_a_bytes(q) + qnet_region_b_bytes(q));
 }
 __device__ __forceinline__ uint16_t* qnet_input_row(const QParams& q, uint32_t* lds, int row) {
   return qnet_region_a(q, lds) + row * qnet_stride0(q);
@@ -117,8 +121,12 @@ struct QNetCfg {
   static constexpr int K1 = D0P / 32;
   static constexpr int T2 = H2 / 16 / kQWaves;
   static constexpr int K2 = H1 / 32;
-  static constexpr int K3 = H2 / 32;  // layer-3 K steps (every wave does all)
+  // layer 3 over the wave's own units: pairs of tiles through K = 32 MFMAs,
+  // or one tile through a K = 16 MFMA
+  static constexpr int kW3Frags = T2 >= 2 ? T2 / 2 : 1;
+  static constexpr bool kW3Half = T2 == 1;
   static_assert(T1 >= 1 && T2 >= 1, "hidden sizes must be multiples of 128");
+  static_assert(T2 == 1 || T2 % 2 == 0, "layer-2 tiles per wave: 1 or even");
   static_assert(H1 % (16 * kQWaves) == 0 && H2 % (16 * kQWaves) == 0, "unsupported sizes");
 
   struct Weights {
@@ -154,7 +162,8 @@ struct QNetCfg {
 
 struct NoQ {
   static constexpr bool kOn = false;
-  static constexpr int K3 = 1;
+  static constexpr int kW3Frags = 1;
+  static constexpr bool kW3Half = false;
   struct Weights {
     __device__ __forceinline__ void load(const QParams&, int) {}
   };
@@ -209,84 +218,153 @@ __device__ __forceinline__ void qnet_layer(const bf16x8 (&a)[T][KS], const f32x4
   }
 }
 
-// Layer-3 weight fragments of this lane (8 KB shared by the workgroup,
-// L1-resident). The rollout loads them while it waits at the end of a step,
-// so the reads are done when the next forward pass needs them.
+typedef short bf16x4s __attribute__((ext_vector_type(4)));
+
+// Accumulate this wave's output tiles of one dense layer (no bias, no store).
+template <int T, int KS, int AHEAD>
+__device__ __forceinline__ void qnet_accum(const bf16x8 (&a)[T][KS], const uint16_t* in,
+                                           int in_stride, int l, f32x4 (&acc)[T]) {
+  const int env = l & 15, kq = (l >> 4) * 8;
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  constexpr int kAhead = KS < AHEAD ? KS : AHEAD;
+  bf16x8 b[kAhead];
+  if (kAhead > 1)
+#pragma unroll
+    for (int ks = 0; ks < kAhead; ++ks)
+      b[ks] = *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const bf16x8 cur = kAhead == 1 ? *reinterpret_cast<const bf16x8*>(in + env * in_stride + ks * 32 + kq)
+                                   : b[ks % kAhead];
+    if (kAhead > 1 && ks + kAhead < KS)
+      b[ks % kAhead] = *reinterpret_cast<const bf16x8*>(in + env * in_stride + (ks + kAhead) * 32 + kq);
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = mfma16x16x32(a[t][ks], cur, acc[t]);
+  }
+}
+
+// W3 columns of this wave's layer-2 units, in the order the lane holds the
+// activations: for a pair of tiles (t, t + 1), units hq..hq + 3 of tile t
+// then of tile t + 1 (a K = 32 A fragment); for a single tile its units
+// hq..hq + 3 (K = 16). Row = action l % 16 (rows past the actions are zero).
+// Loaded once per kernel: 4 (or 2) VGPRs per fragment.
 template <class QC>
 struct W3Frag {
-  bf16x8 a[QC::K3];
+  bf16x8 a[QC::kW3Frags];
+  bf16x4s h;
+  float b3;  // bias of action l % 8 (the action whose sum this lane forms)
 };
 
 template <class QC>
 __device__ __forceinline__ void qnet_load_w3(const QParams& q, int tid, W3Frag<QC>& f) {
   if constexpr (QC::kOn) {
-    const int l = tid & 63;
-    const int env = l & 15, kq = (l >> 4) * 8;
+    const int w = tid >> 6, l = tid & 63;
+    const int row = l & 15, hq = (l >> 4) * 4;
+    if constexpr (QC::kW3Half) {
+      const int h = w * 16 + hq;
+      f.h = __builtin_bit_cast(bf16x4s, *reinterpret_cast<const uint2*>(q.w3 + (size_t)row * q.h2 + h));
+    } else {
 #pragma unroll
-    for (int ks = 0; ks < QC::K3; ++ks)
-      f.a[ks] = *reinterpret_cast<const bf16x8*>(q.w3 + (size_t)env * q.h2 + ks * 32 + kq);
+      for (int p = 0; p < QC::kW3Frags; ++p) {
+        const int ha = (w * QC::T2 + 2 * p) * 16 + hq, hb = ha + 16;
+        const uint2 wa = *reinterpret_cast<const uint2*>(q.w3 + (size_t)row * q.h2 + ha);
+        const uint2 wb = *reinterpret_cast<const uint2*>(q.w3 + (size_t)row * q.h2 + hb);
+        f.a[p] = __builtin_bit_cast(bf16x8, uint4{wa.x, wa.y, wb.x, wb.y});
+      }
+    }
+    f.b3 = q.b3[l & 7];
   }
 }
 
 // Forward pass over the 16 input rows in LDS region A (the caller has made
-// them visible with a barrier). Returns this lane's layer-3 tile: Q[a][env]
-// for actions a = 4 * (lane / 16) + 0..3 and env = lane % 16.
+// them visible with a barrier). Returns, in every lane, Q[a][col] with
+// a = lane % 8 (bias included; a = 7 is a padding row of value 0 when seven
+// actions are in use): col is the env column the lane's env occupies.
+// Layer 3's eight wave partials are added in wave order 0..7, then the bias.
 template <class QC, int AHEAD>
-__device__ __forceinline__ f32x4 qnet_forward_group(const QParams& q,
-                                                    const typename QC::Weights& W,
-                                                    const W3Frag<QC>& w3, uint32_t* lds,
-                                                    int tid) {
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+__device__ __forceinline__ float qnet_forward_sum(const QParams& q,
+                                                  const typename QC::Weights& W,
+                                                  const W3Frag<QC>& w3, uint32_t* lds, int tid,
+                                                  int col) {
+  float out = 0.0f;
   if constexpr (QC::kOn) {
     const int w = tid >> 6, l = tid & 63;
-    const int env = l & 15, kq = (l >> 4) * 8;
     uint16_t* ra = qnet_region_a(q, lds);
     uint16_t* rb = qnet_region_b(q, lds);
-    uint16_t* rc = qnet_region_c(q, lds);
+    float* rc = qnet_region_c(q, lds);
     qnet_layer<QC::T1, QC::K1, AHEAD>(W.a1, W.bias1, ra, qnet_stride0(q), rb, qnet_stride1(q),
                                       w * QC::T1, l);
     __syncthreads();
-    qnet_layer<QC::T2, QC::K2, AHEAD>(W.a2, W.bias2, rb, qnet_stride1(q), rc, qnet_stride2(q),
-                                      w * QC::T2, l);
-    __syncthreads();
-    // two accumulator chains (even and odd K steps) halve the dependent
-    // MFMA latency; their sum is one more FP32 rounding of the same terms
-    f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
-    constexpr int kAhead = QC::K3 < AHEAD ? QC::K3 : AHEAD;
-    bf16x8 b[kAhead];
-    if (kAhead > 1)
+    f32x4 acc[QC::T2];
+    qnet_accum<QC::T2, QC::K2, AHEAD>(W.a2, rb, qnet_stride1(q), l, acc);
+    f32x4 q3 = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (QC::kW3Half) {
+      const f32x4 v = acc[0] + W.bias2[0];
+      const uint2 h2 = {pack_relu_bf16x2(v[0], v[1]), pack_relu_bf16x2(v[2], v[3])};
+      q3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3.h, __builtin_bit_cast(bf16x4s, h2), q3,
+                                                     0, 0, 0);
+    } else {
 #pragma unroll
-      for (int ks = 0; ks < kAhead; ++ks)
-        b[ks] = *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq);
-#pragma unroll
-    for (int ks = 0; ks < QC::K3; ++ks) {
-      const bf16x8 cur =
-          kAhead == 1 ? *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + ks * 32 + kq)
-                      : b[ks % kAhead];
-      if (kAhead > 1 && ks + kAhead < QC::K3)
-        b[ks % kAhead] =
-            *reinterpret_cast<const bf16x8*>(rc + env * qnet_stride2(q) + (ks + kAhead) * 32 + kq);
-      if (ks & 1)
-        acc2 = mfma16x16x32(w3.a[ks], cur, acc2);
-      else
-        acc = mfma16x16x32(w3.a[ks], cur, acc);
+      for (int p = 0; p < QC::kW3Frags; ++p) {
+        const f32x4 va = acc[2 * p] + W.bias2[2 * p], vb = acc[2 * p + 1] + W.bias2[2 * p + 1];
+        const uint4 h4 = {pack_relu_bf16x2(va[0], va[1]), pack_relu_bf16x2(va[2], va[3]),
+                          pack_relu_bf16x2(vb[0], vb[1]), pack_relu_bf16x2(vb[2], vb[3])};
+        q3 = mfma16x16x32(w3.a[p], __builtin_bit_cast(bf16x8, h4), q3);
+      }
     }
-    acc = acc + acc2;
+    // lane l holds actions 4 (l / 16) .. + 3 of env column l % 16; actions
+    // 8 .. 15 are zero rows, so only lanes below 32 store
+    if (l < 32)
+      *reinterpret_cast<f32x4*>(rc + (l & 15) * kQPartStride + w * 8 + (l >> 4) * 4) = q3;
+    __syncthreads();
+    const float* pc = rc + col * kQPartStride + (l & 7);
+    float s = pc[0];
+#pragma unroll
+    for (int ww = 1; ww < kQWaves; ++ww) s += pc[ww * 8];
+    out = w3.b3 + s;
   }
-  return acc;
+  return out;
 }
 
-// Q values of env column `row` of a wave's layer-3 tile (plus bias), gathered
-// from the lanes that hold them; every calling lane gets all of them and the
-// lowest index of the maximum over the q.n_actions actions in use.
-__device__ __forceinline__ int qnet_q_values(const QParams& q, const f32x4& tile, int row,
-                                             float (&qa)[kNumActions], int n_actions) {
+// All Q values of env column col (bias included) from region C, summed in
+// the same order as qnet_forward_sum; lowest index of the maximum over the
+// first n_actions. For callers that hold one env per lane.
+__device__ __forceinline__ int qnet_q_row(const QParams& q, uint32_t* lds, int col,
+                                          float (&qa)[kNumActions], int n_actions) {
+  const float* pc = qnet_region_c(q, lds) + col * kQPartStride;
   int best = 0;
 #pragma unroll
   for (int a = 0; a < kNumActions; ++a) {
-    const float v = __shfl(tile[a & 3], row + 16 * (a >> 2));
-    qa[a] = q.b3[a] + v;
+    float s = pc[a];
+#pragma unroll
+    for (int ww = 1; ww < kQWaves; ++ww) s += pc[ww * 8 + a];
+    qa[a] = q.b3[a] + s;
     if (a < n_actions && qa[a] > qa[best]) best = a;
+  }
+  return best;
+}
+
+// Greedy action of the env whose lanes start at seg: the Q values sit in
+// lanes seg + a (qnet_forward_sum); lowest index of the maximum.
+template <int L>
+__device__ __forceinline__ int qnet_greedy(float qsum, int seg, int n_actions) {
+  int best = 0;
+  float qb = 0.0f;
+#pragma unroll
+  for (int a = 0; a < kNumActions; ++a) {
+    float v;
+    if constexpr (L == 64) {
+      v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qsum), a));
+    } else {
+      v = __shfl(qsum, seg + a);
+    }
+    if (a == 0) {
+      qb = v;
+    } else if (a < n_actions && v > qb) {
+      qb = v;
+      best = a;
+    }
   }
   return best;
 }
