@@ -377,9 +377,8 @@ enum : int { kAddrAxis = 0, kAddrWord = 1, kAddrFree = 2 };
 
 // U samples k0 + u * stride of one ray: all addresses first, then all
 // LDS reads, then the tests, so the reads are in flight together. Sample
-// distances are t_k = (float)k * ds; with ds == 1 that is (float)k, formed
-// here as (float)k0 + (float)(u * stride), exact for k < 2^24. Returns the
-// smallest hitting k of the block, or k0 + U * stride (one past the
+// distances are t_k = (float)k * ds; with ds == 1 that is (float)k, exact
+// for k < 2^24. Returns the smallest hitting k of the block, or k0 + U * stride (one past the
 // block) when none hits; hits past M are the caller's to discard. ADDR is
 // one of the address modes above.
 template <bool UNIT, int ADDR, int U>
@@ -388,10 +387,13 @@ __device__ __forceinline__ int sample_block(const Slot& m, float x, float y, flo
   static_assert(U <= 31, "hit bits of one block and the sentinel fit a word");
   const uint32_t* adr[U];
   int bit[U];
-  const float tk0 = (float)k0;
+  const float tk0 = (float)k0, fst = (float)stride;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const float tk = UNIT ? tk0 + (float)(u * stride) : (float)(k0 + u * stride) * ds;
+    // unit step: t_k = (float)k formed as stride * u + k0 in one fused
+    // multiply-add, exact for the small integers involved
+    const float tk = UNIT ? (u == 0 ? tk0 : __builtin_fmaf(fst, (float)u, tk0))
+                          : (float)(k0 + u * stride) * ds;
     const float px = x + tk * ux;
     const float py = y + tk * uy;
     adr[u] = ADDR == kAddrAxis   ? m.word_of(cvt_flr(px), cvt_flr(py), bit[u])
