@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(512) k_step(Params p, int mode) {
     m = stage_window<L>(p, ln, mm, buf, e.y);
   }
   observe<L, TK, U>(p, ln, rd, m, e, i, p.g, reset_now ? kNoiseReset : kNoise, inv_dn, orow,
-                    crow, hk, nullptr, free_pose, sn_row);
+                    crow, hk, nullptr, free_pose, sn_row, RingRow{nullptr, nullptr}, true);
   if (ln.q == 0) {
     store_env(p.s, i, e);
     if (mode == 0) {
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
                        terminal ? nullptr : hk, terminal ? nullptr : act_in,
                        !terminal && free_pose,
                        (terminal || !term_pass) ? this_sn : RingRow{nullptr, nullptr},
-                       terminal ? RingRow{nullptr, nullptr} : next_s);
+                       terminal ? RingRow{nullptr, nullptr} : next_s, !terminal);
           }
           if (ln.q == 0) {
             p.ring.act[s0] = (int8_t)a_hat;
@@ -352,7 +352,8 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
             if (!free_pose && ln.q == 0) p.err[0] = SPARROW_ERESET;
           }
           observe<L, TK, kUnroll, true>(p, ln, rd, m, e, i, g, o.done ? kNoiseReset : kNoise,
-                                        inv_dn, orow, crow, hk, act_in, free_pose);
+                                        inv_dn, orow, crow, hk, act_in, free_pose,
+                                        RingRow{nullptr, nullptr}, RingRow{nullptr, nullptr}, true);
         }
         // step t's reward, done and action wait in lane t % L of the env;
         // every L steps (and after the last) each lane writes the step it

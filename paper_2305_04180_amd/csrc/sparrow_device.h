@@ -490,7 +490,7 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
                         Env& e, int i, uint32_t g, uint32_t purpose, float inv_dn,
                         float* dst, float* dst2, int16_t* hk, uint16_t* dst_bf16,
                         bool disk_free, RingRow qa = RingRow{nullptr, nullptr},
-                        RingRow qb = RingRow{nullptr, nullptr}) {
+                        RingRow qb = RingRow{nullptr, nullptr}, bool dist_current = false) {
   // With the robot disk known to be collision-free, every sample closer to
   // the centre than the radius lies in a cell a collision test would have
   // flagged, so none of the first k_free samples can hit.
@@ -565,7 +565,9 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
         const float d2 = dx * dx + dy * dy;
         o[0] = e.vl / e.vmax;
         o[1] = e.va / p.omega_max;
-        o[2] = sqrtf(d2) * inv_dn;
+        // dprev already holds sqrtf(d2) at this pose (same expression) after a
+        // step that went on or after an AutoReset
+        o[2] = (dist_current ? e.dprev : sqrtf(d2)) * inv_dn;
         o[3] = bearing;
         o[4] = 0.0f;
       } else {
@@ -621,7 +623,7 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
       const float d2 = dx * dx + dy * dy;
       o[0] = e.vl / e.vmax;
       o[1] = e.va / p.omega_max;
-      o[2] = sqrtf(d2) * inv_dn;
+      o[2] = (dist_current ? e.dprev : sqrtf(d2)) * inv_dn;
       o[3] = bearing;
       o[4] = 0.0f;
     } else {
@@ -651,23 +653,28 @@ __device__ __forceinline__ void observe(const Params& p, const Lanes<L>& ln, con
 // ------------------------------------------------------------------------
 // AutoReset of one env (Sec. 3.2.5) with per-episode randomisation (Sec.
 // 3.2.4): physics draws, then start and target as the first collision-free
-// candidate cell centre in counter order. Candidates are tested one after
-// the other (most are accepted within a few draws), each by the env's L
-// lanes splitting the disk's cells as in the per-step collision test.
-// Returns false when no candidate was accepted.
+// candidate cell centre in counter order. The env's lanes draw the Philox
+// words side by side: one stream gives the two physics draws (lanes 0 and 1)
+// and start candidates 0 .. L - 3 (lane 2 + n), the next streams L
+// candidates each (lane n - base); the candidates are then tested one after
+// the other in counter order (most are accepted within a few), each by the
+// env's L lanes splitting the disk's cells as in the per-step collision
+// test. Returns false when no candidate was accepted.
 // ------------------------------------------------------------------------
 template <int L>
 __device__ bool reset_env(const Params& p, const Lanes<L>& ln, const Slot& m, Env& e, int i,
                           uint32_t g) {
-  const U4 a = philox((uint32_t)i, g, kResetDR, 0u, p.key0, p.key1);
-  const U4 b = philox((uint32_t)i, g, kResetDR, 1u, p.key0, p.key1);
-  e.dt = p.dt_lo + p.dt_span * unit24(a.x);
-  e.K = p.K_lo + p.K_span * unit24(a.y);
-  e.mu = p.mu_lo + p.mu_span * unit24(a.z);
-  e.vmax = p.vmax_lo + p.vmax_span * unit24(a.w);
-  e.sigma = p.sigma_lo + p.sigma_span * unit24(b.x);
-  e.delay = p.delay_lo + scale_u32(b.y, (uint32_t)(p.delay_hi - p.delay_lo + 1));
-  e.phi = unit24(b.z) * kTwoPiF - kPiF;
+  const int q = ln.q;
+  U4 cw = philox((uint32_t)i, g, q < 2 ? kResetDR : kResetStart, (uint32_t)(q < 2 ? q : q - 2),
+                 p.key0, p.key1);
+  auto from = [&](uint32_t v, int lane) { return (uint32_t)__shfl((int)v, ln.seg + lane); };
+  e.dt = p.dt_lo + p.dt_span * unit24(from(cw.x, 0));
+  e.K = p.K_lo + p.K_span * unit24(from(cw.y, 0));
+  e.mu = p.mu_lo + p.mu_span * unit24(from(cw.z, 0));
+  e.vmax = p.vmax_lo + p.vmax_span * unit24(from(cw.w, 0));
+  e.sigma = p.sigma_lo + p.sigma_span * unit24(from(cw.x, 1));
+  e.delay = p.delay_lo + scale_u32(from(cw.y, 1), (uint32_t)(p.delay_hi - p.delay_lo + 1));
+  e.phi = unit24(from(cw.z, 1)) * kTwoPiF - kPiF;
   const uint32_t W = (uint32_t)m.W, H = (uint32_t)m.H;
   const float ra2 = p.arrive_r * p.arrive_r;
   bool ok = true;
@@ -675,12 +682,19 @@ __device__ bool reset_env(const Params& p, const Lanes<L>& ln, const Slot& m, En
 #pragma unroll
   for (int which = 0; which < 2; ++which) {
     const uint32_t purpose = which == 0 ? kResetStart : kResetTarget;
+    // counter of the stream's lane 0 (the start stream begins with the two
+    // physics draws)
+    int base = which == 0 ? -2 : 0;
+    if (which == 1) cw = philox((uint32_t)i, g, purpose, (uint32_t)q, p.key0, p.key1);
     float bx = 0.0f, by = 0.0f;
     bool found = false;
-    for (uint32_t n = 0; n < 16u * 64u; ++n) {  // the same draw in every lane
-      const U4 w = philox((uint32_t)i, g, purpose, n, p.key0, p.key1);
-      const float px = (float)scale_u32(w.x, W) + 0.5f;
-      const float py = (float)scale_u32(w.y, H) + 0.5f;
+    for (int n = 0; n < 16 * 64; ++n) {
+      if (n - base >= L) {
+        base = n;
+        cw = philox((uint32_t)i, g, purpose, (uint32_t)(n + q), p.key0, p.key1);
+      }
+      const float px = (float)scale_u32(from(cw.x, n - base), W) + 0.5f;
+      const float py = (float)scale_u32(from(cw.y, n - base), H) + 0.5f;
       if (n == 0) {
         bx = px;
         by = py;
