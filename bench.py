@@ -517,9 +517,10 @@ def kernel_source_hash():
 
 
 def counter_traffic(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE x calibration + WRITE_SIZE), or None when the summary was
-    taken on other kernel sources."""
+    """A per-launch figure from the committed rocprofv3 counter summary:
+    HBM bytes (FETCH_SIZE x calibration + WRITE_SIZE) for the
+    traffic_bytes_per_launch_* keys, the VALU busy fraction for valu_busy_*;
+    None when the summary was taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", "counters_m4096.md")
     if not os.path.exists(path):
         return None
@@ -531,7 +532,8 @@ def counter_traffic(kernel_key):
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("source_sha1") != kernel_source_hash() or kernel_key not in vals:
         return None
-    return int(vals[kernel_key])
+    v = float(vals[kernel_key])
+    return int(v) if v.is_integer() else v
 
 
 def env_map_bytes(maps):
@@ -582,7 +584,7 @@ def peaks(skip):
 
 
 def fused_roofline(env, cfg, maps, K, launches, stream, lds_peak, extra_env_ops=0,
-                   kernel="", counter_key=None):
+                   kernel="", counter_key=None, lds_b32_peak=None):
     """Roofline of the fused rollout kernel on its own K-step launches (graph
     replays, HIP events around each on the launch stream), whatever the
     metric's step count. Algorithmic work per launch (N K env-steps):
@@ -594,7 +596,10 @@ def fused_roofline(env, cfg, maps, K, launches, stream, lds_peak, extra_env_ops=
       MFMA the Q-network's 2 (d0 h1 + h1 h2 + h2 A) FLOP per env-step
     bound / frac: the largest of the three fractions (published peaks for HBM
     and MFMA; for LDS the larger of 128 B/clk/CU and the probe's
-    measurement). The vector-ALU lane-op count is reported beside it."""
+    measurement). The vector-ALU lane-op count is reported beside it, and
+    so are the LDS fraction against the probe's 4-byte read rate (the
+    march's own access width) and the VALU busy fraction that the committed
+    counter summary measured on the same kernel sources."""
     import torch
     N, nr, D = cfg["n_envs"], cfg["n_rays"], env.obs_dim
     dims = cfg["qnet"]
@@ -646,6 +651,10 @@ def fused_roofline(env, cfg, maps, K, launches, stream, lds_peak, extra_env_ops=
             "mfma_frac": round(fr["mfma"], 5),
             "alg_per_launch": {"lds_bytes": int(lds_b), "hbm_bytes": int(hbm_b),
                                "mfma_flop": int(flops), "env_steps": es},
+            "lds_b32_frac": round(lds_gbs / lds_b32_peak, 5) if lds_b32_peak else None,
+            "valu_busy_counters": counter_traffic(counter_key.replace("traffic_bytes_per_launch",
+                                                                      "valu_busy"))
+            if counter_key else None,
             "alu": {"achieved": round(alu_t, 3), "peak": round(MI355X_VALU_TOPS, 2),
                     "unit": "T lane-ops/s", "frac": round(alu_t / MI355X_VALU_TOPS, 4),
                     "units": f"32-bit lane-ops from the definition: {ALG_OPS_PER_SAMPLE}/sample, "
@@ -912,7 +921,8 @@ def main():
     KR = args.rollout
     roofline = fused_roofline(env, cfg, maps, KR, args.roofline_launches, stream, lds_peak,
                               kernel="k_rollout<64, QNetCfg<64,256,256>> (fused actor + step)",
-                              counter_key="traffic_bytes_per_launch_k_rollout")
+                              counter_key="traffic_bytes_per_launch_k_rollout",
+                              lds_b32_peak=pk["lds_b32"] if pk else None)
     log(f"[bench] roofline: {json.dumps(roofline)}")
 
     # ---------------- the same steps in 256-step launches ----------------
