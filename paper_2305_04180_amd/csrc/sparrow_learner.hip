@@ -8,7 +8,7 @@
 // vector units serve them and keep them within FP32 rounding of binary64).
 // Every product runs through one tiled kernel, k_learn_mm: a launch takes up
 // to three independent products C = X^T Y (16 x 16 output tiles, K staged
-// through LDS 64 at a time, each output summed in ascending k after its
+// through LDS 128 at a time, each output summed in ascending k after its
 // bias), so the forward pass is one launch per layer for the three passes
 // together and the backward pass two launches:
 //   forward       layer l of the online network on s (activations kept for
@@ -74,14 +74,15 @@ struct MMBatch {
   int32_t n_ops;
 };
 
-constexpr int kMT = 16, kMK = 64;  // output tile side, K chunk
+constexpr int kMT = 16, kMK = 128;  // output tile side, K chunk
+constexpr int kMR = kMT * kMK / 256;  // elements of each operand chunk per thread
 
-__device__ __forceinline__ void mm_load(const MMOp& o, int Ncols, int k0, int m0, int n0,
-                                        float (&xr)[4], float (&yr)[4]) {
+__device__ __forceinline__ void mm_load(const MMOp& o, int k0, int m0, int n0, float (&xr)[kMR],
+                                        float (&yr)[kMR]) {
   const bool ones = o.Cb != nullptr;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int e = (int)threadIdx.x + r * 256;  // 1024 elements of each 64 x 16 chunk
+  for (int r = 0; r < kMR; ++r) {
+    const int e = (int)threadIdx.x + r * 256;  // the chunk's kMK x kMT elements
     // consecutive threads walk the operand's unit-stride index
     const int xk = o.sxm == 1 ? e / kMT : e % kMK, xm = o.sxm == 1 ? e % kMT : e / kMK;
     const int yk = o.syn == 1 ? e / kMT : e % kMK, yn = o.syn == 1 ? e % kMT : e / kMK;
@@ -90,12 +91,15 @@ __device__ __forceinline__ void mm_load(const MMOp& o, int Ncols, int k0, int m0
     yr[r] = (ky < o.K && n < o.N) ? o.Y[(size_t)ky * o.syk + (size_t)n * o.syn]
             : (ky < o.K && ones && n == o.N) ? 1.0f : 0.0f;
   }
-  (void)Ncols;
 }
 
+// One 16 x 16 output tile per workgroup, one output per thread, summed over
+// ascending k after its bias. K goes through LDS 128 at a time (a 256-long
+// sum is two chunks); the next chunk's global loads are issued before this
+// chunk's multiply-adds.
 __global__ void __launch_bounds__(256) k_learn_mm(MMBatch bt) {
-  __shared__ float xs[2][kMK][kMT + 1];
-  __shared__ float ys[2][kMK][kMT + 1];
+  __shared__ float xs[kMK][kMT + 1];
+  __shared__ float ys[kMK][kMT + 1];
   int which = 0;
   for (int q = 1; q < bt.n_ops; ++q)
     if ((int)blockIdx.x >= bt.op[q].tile0) which = q;
@@ -103,26 +107,24 @@ __global__ void __launch_bounds__(256) k_learn_mm(MMBatch bt) {
   const int t = (int)blockIdx.x - o.tile0;
   const int m0 = (t / o.tiles_n) * kMT, n0 = (t % o.tiles_n) * kMT;
   const int tn = (int)threadIdx.x % kMT, tm = (int)threadIdx.x / kMT;
-  const int Ncols = o.N + (o.Cb ? 1 : 0);
   const int m = m0 + tm, n = n0 + tn;
   float acc = (o.bias && n < o.N) ? o.bias[n] : 0.0f;
-  float xr[4], yr[4];
-  mm_load(o, Ncols, 0, m0, n0, xr, yr);
-  int buf = 0;
+  float xr[kMR], yr[kMR];
+  mm_load(o, 0, m0, n0, xr, yr);
   for (int k0 = 0; k0 < o.K; k0 += kMK) {
+    if (k0 > 0) __syncthreads();  // every thread is done with the previous chunk
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kMR; ++r) {
       const int e = (int)threadIdx.x + r * 256;
       const int xk = o.sxm == 1 ? e / kMT : e % kMK, xm = o.sxm == 1 ? e % kMT : e / kMK;
       const int yk = o.syn == 1 ? e / kMT : e % kMK, yn = o.syn == 1 ? e % kMT : e / kMK;
-      xs[buf][xk][xm] = xr[r];
-      ys[buf][yk][yn] = yr[r];
+      xs[xk][xm] = xr[r];
+      ys[yk][yn] = yr[r];
     }
     __syncthreads();
-    if (k0 + kMK < o.K) mm_load(o, Ncols, k0 + kMK, m0, n0, xr, yr);
+    if (k0 + kMK < o.K) mm_load(o, k0 + kMK, m0, n0, xr, yr);
     const int kn = min(kMK, o.K - k0);
-    for (int kk = 0; kk < kn; ++kk) acc += xs[buf][kk][tm] * ys[buf][kk][tn];
-    buf ^= 1;  // the next chunk goes to the other buffers: one barrier per chunk
+    for (int kk = 0; kk < kn; ++kk) acc += xs[kk][tm] * ys[kk][tn];
   }
   if (m >= o.M) return;
   if (n < o.N) {
