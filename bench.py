@@ -97,7 +97,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--plain-steps", type=int, default=512)
+    ap.add_argument("--plain-steps", type=int, default=10000,
+                    help="plain-step leg length (the domain-randomized plain workload's 10^4 steps)")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the full-collection leg (32768 envs, ring buffer)")
     ap.add_argument("--c5-steps", type=int, default=2048)
@@ -193,6 +194,87 @@ def cpu_baseline(cfg, maps, w, b, seconds, cores=None):
             "kind": "oracle",
             "sample": f"{n_sample} of the {cfg['n_envs']} envs (same maps/physics), {steps} steps, "
                       f"FP64 Q-network + VEM + FP32 step, {dt:.1f} s"}
+
+
+def cpu_plain(cfg, maps, seconds, n_sample=256, cores=None, max_steps=None):
+    """The oracle's plain step (FP32, uniform random actions drawn by the
+    oracle itself) on the host cores, on a bounded sample of envs of the
+    workload, one Python thread per core over env shards."""
+    import oracle
+    from paper_2305_04180_amd import inputs
+    n_sample = min(n_sample, cfg["n_envs"])
+    cores = cores or min(os.cpu_count() or 1, 16)
+    sub = dict(cfg, n_envs=n_sample)
+    emap = np.asarray(maps.env_to_map[:n_sample])
+    used = np.unique(emap)
+    remap = np.searchsorted(used, emap).astype(np.int32)
+    smaps = inputs.Maps(grids=[maps.grids[k] for k in used], env_to_map=remap)
+    o = oracle.Oracle(sub, smaps)
+    obs, _ = o.reset()
+    shards = [sh for sh in np.array_split(np.arange(n_sample), cores) if len(sh)]
+    rew = np.zeros(n_sample, np.float32)
+    done = np.zeros(n_sample, np.uint8)
+    nobs = np.zeros_like(obs)
+
+    def step(sh, acts):
+        o.step_range(int(sh[0]), int(sh[-1]) + 1, acts, nobs, rew, done)
+
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and (max_steps is None or steps < max_steps):
+        acts = o.uniform_actions()
+        if len(shards) == 1:
+            step(shards[0], acts)
+        else:
+            th = [threading.Thread(target=step, args=(sh, acts)) for sh in shards]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+        o.advance()
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(n_sample * steps / dt, 1), "unit": "env-steps/s", "cores": len(shards),
+            "kind": "oracle",
+            "sample": f"{n_sample} of the {cfg['n_envs']} envs (same maps/physics), {steps} steps, "
+                      f"FP32 step with uniform actions, {dt:.1f} s"}
+
+
+def c1_leg(with_cpu):
+    """The small plain workload: 16 envs on 128^2 rectangle maps, 32 rays to
+    range 64, fixed physics, uniform random actions, its 1000 steps, one
+    sparrow_step per step (launch-bound at 16 envs); the oracle runs the same
+    1000 steps on one host thread beside it."""
+    import torch
+    from paper_2305_04180_amd import inputs, sparrow
+    cfg = inputs.workload("c1")
+    maps = inputs.make_maps(cfg)
+    env = sparrow.Env(cfg, maps)
+    env.reset()
+    a_buf = torch.zeros(cfg["n_envs"], dtype=torch.int32, device="cuda")
+    for _ in range(16):
+        env.random_actions(a_buf)
+        env.step(a_buf)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = cfg["steps"]
+    e0.record(stream)
+    for _ in range(steps):
+        env.random_actions(a_buf)
+        env.step(a_buf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert env.status() == 0
+    out = {"value": round(cfg["n_envs"] * steps / (ms / 1e3), 1), "unit": "env-steps/s",
+           "n_envs": cfg["n_envs"], "steps": steps, "ms_per_step": round(ms / steps, 5),
+           "config": {"workload": "16 envs, own 128x128 rectangle map each (10% fill, border), "
+                                  "32 rays/270 deg/range 64, dt 0.1 s, no delay, uniform actions"}}
+    if with_cpu:
+        out["cpu_baseline"] = cpu_plain(cfg, maps, 60.0, n_sample=cfg["n_envs"], cores=1,
+                                        max_steps=steps)
+    return out
 
 
 def collection_c5(cfg, maps, steps, warmup, fused_add=False):
@@ -1032,6 +1114,10 @@ def main():
                       "staged_map_bytes_per_step": int(win_bytes),
                       "whole_map_bytes": int(env_map_bytes(maps))}
 
+    log("[bench] c1 (16 envs, 1000 plain steps)")
+    c1 = c1_leg(not args.no_cpu)
+    log(f"[bench] c1: {json.dumps(c1)}")
+
     c3 = None
     if maps3 is not None:
         log("[bench] c3 batching (16384 envs, uneven sides, 64 rays)")
@@ -1044,6 +1130,7 @@ def main():
         log(f"[bench] c4: {c4['value'] / 1e6:.1f} M env-steps/s")
 
     cpu = None
+    c2_cpu = None
     checks = {}
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
@@ -1052,6 +1139,12 @@ def main():
         cpu["single_thread_value"] = one["value"]
         cpu["cpu_model"] = cpu_model()
         cpu["nproc"] = os.cpu_count()
+        log("[bench] cpu baselines of the plain workloads (oracle)")
+        c2_cpu = cpu_plain(inputs.workload("c2"), maps, args.cpu_seconds / 3)
+        c2_cpu["single_thread_value"] = cpu_plain(inputs.workload("c2"), maps,
+                                                  args.cpu_seconds / 6, cores=1)["value"]
+        if c3 is not None:
+            c3["cpu_baseline"] = cpu_plain(cfg3, maps3, args.cpu_seconds / 3)
         log("[bench] oracle checks: c4 precision, kinematics shadow")
         checks = oracle_checks(cfg4, env4, cfg, maps)
         log(f"[bench] oracle checks: {json.dumps(checks)}")
@@ -1110,6 +1203,12 @@ def main():
                    "parallelism": "single GPU"},
         "plain_env_steps_per_s": round(plain_rate, 1),
         "plain_actor_env_steps_per_s": round(pa_rate, 1),
+        "c2_plain": {"value": round(plain_rate, 1), "unit": "env-steps/s", "steps": P,
+                     "what": "the plain leg is the domain-randomized plain workload: the same "
+                             "4096 envs, maps and physics with uniform random actions, "
+                             f"{P} steps",
+                     "cpu_baseline": c2_cpu},
+        "c1_plain": c1,
         "fused_over_plain": round(fused_rate / plain_rate, 3),
         "fused_collect": fused_collect,
         "fused_k256_env_steps_per_s": round(fused_k256, 1) if fused_k256 else None,

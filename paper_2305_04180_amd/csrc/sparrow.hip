@@ -80,29 +80,51 @@ __global__ void k_vem_eps(VemSchedule v, float* __restrict__ eps) {
   eps[i] = vem_eps(v, i, 0u);
 }
 
-// Copy the group's maps into LDS (16-byte words; offsets are multiples of 4).
-// With march padding, the words after the group's last map up to the end of
-// the maps region are set too (a group with fewer or smaller maps than the
-// largest leaves stale words there).
+// Copy the group's maps into LDS (16-byte words; offsets are multiples of 4)
+// with direct global-to-LDS loads: wave w copies 1 KB pieces w, w + 8, ...
+// of every slot (lane l's 16 bytes land at the piece's LDS base + 16 l), so
+// every piece of the group is in flight before anything waits; the caller's
+// barrier waits for them. With march padding, the words after the group's
+// last map up to the end of the maps region are set too (a group with fewer
+// or smaller maps than the largest leaves stale words there).
+static_assert(sizeof(MapMeta) == 16 && offsetof(MapMeta, off) == 0,
+              "stage_maps reads a map's word offset as word 4 m of the table");
+
 __device__ __forceinline__ void stage_maps(const Params& p, int grp, uint32_t* lds) {
+  constexpr int kMaxSlots = 8;
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+  const int n_waves = (int)blockDim.x >> 6;
+  // every slot's descriptor and map offset first: a wait on these loads
+  // would also wait on copies issued before it
+  // (the slot table ends with eight empty entries, so all eight loads stay
+  // in it; entries past the group's width are ignored)
+  // Read through the constant address space: the tables do not change during
+  // the kernel, so these are scalar loads, which the copies' counter does not
+  // hold up.
+  using CInt = const __attribute__((address_space(4))) int32_t;
+  using CU32 = const __attribute__((address_space(4))) uint32_t;
+  CInt* slots = (CInt*)(p.slots + grp * p.epw);
+  CU32* meta = (CU32*)p.meta;  // MapMeta: off, W, H, wpr
+  int4 sl[kMaxSlots];
+  uint32_t off[kMaxSlots];
+#pragma unroll
+  for (int s = 0; s < kMaxSlots; ++s)
+    sl[s] = make_int4(slots[4 * s], slots[4 * s + 1], slots[4 * s + 2], slots[4 * s + 3]);
+#pragma unroll
+  for (int s = 0; s < kMaxSlots; ++s) off[s] = meta[4 * sl[s].y];
+#pragma unroll
+  for (int s = 0; s < kMaxSlots; ++s)
+    if (s >= p.epw) sl[s].x = -1;
   int end = 0;
-  for (int s = 0; s < p.epw; ++s) {
-    const int4 sl = p.slots[grp * p.epw + s];
-    if (sl.x < 0) break;
-    end = sl.z + sl.w;
-    const uint4* src = reinterpret_cast<const uint4*>(p.words + p.meta[sl.y].off);
-    uint4* dst = reinterpret_cast<uint4*>(lds + sl.z);
-    const int n4 = sl.w >> 2, bd = blockDim.x;
-    int w = threadIdx.x;
-    // eight 16-byte loads in flight per lane before their LDS stores
-    for (; w + 7 * bd < n4; w += 8 * bd) {
-      uint4 v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = src[w + u * bd];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) dst[w + u * bd] = v[u];
-    }
-    for (; w < n4; w += bd) dst[w] = src[w];
+  for (int s = 0; s < kMaxSlots; ++s) {
+    if (sl[s].x < 0) break;
+    end = sl[s].z + sl[s].w;
+    const uint4* src = reinterpret_cast<const uint4*>(p.words + off[s]);
+    uint32_t* dst = lds + sl[s].z;
+    const int n4 = sl[s].w >> 2;
+    for (int b = wave * 64; b < n4; b += n_waves * 64)
+      if (b + lane < n4) __builtin_amdgcn_global_load_lds(src + b + lane, dst + 4 * b, 16, 0, 0);
   }
   if (p.march_pad > 0)
     for (int w = end + (int)threadIdx.x; w < p.maps_words; w += blockDim.x) lds[w] = 0xFFFFFFFFu;
@@ -239,7 +261,9 @@ __global__ void __launch_bounds__(512) k_rollout(Params p, QParams qp) {
     for (int k = threadIdx.x; k < nw; k += blockDim.x) a[k] = 0u;
   }
   for (int grp = blockIdx.x; grp < p.n_groups; grp += gridDim.x) {
-    __syncthreads();
+    // the previous group's steps are done with the maps region (the first
+    // group's staging touches no LDS the set-up above writes)
+    if (grp != (int)blockIdx.x) __syncthreads();
     stage_maps(p, grp, maps);
     int4 sl = make_int4(-1, 0, 0, 0);
     if (slot < p.epw) sl = p.slots[grp * p.epw + slot];
@@ -564,6 +588,9 @@ int get_groups(sparrow_env* e, int epw, int budget_words, Groups** out, bool win
     cur += 1;
   }
   flush();
+  // eight empty entries past the last group: the rollout reads eight slot
+  // entries of a group whatever its width
+  for (int s = 0; s < 8; ++s) slots.push_back(make_int4(-1, 0, 0, 0));
   if (hipMalloc(&gr.d_slots, sizeof(int4) * slots.size()) != hipSuccess)
     return fail(SPARROW_ENOMEM, "slot table allocation failed");
   HIP_TRY(hipMemcpy(gr.d_slots, slots.data(), sizeof(int4) * slots.size(),

@@ -903,12 +903,19 @@ __device__ __forceinline__ Slot global_slot(const Params& p, const MapMeta& mm) 
   return s;
 }
 
+// Direct global-to-LDS load of 16 bytes per lane (global_load_lds_dwordx4):
+// the wave's LDS destination is that of its first active lane, lane l's
+// bytes land 16 l past it, so a full wave writes 1 KB in lane order.
+__device__ __forceinline__ void lds_dma16(const uint4* src, uint4* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
 // Copy the rows of map mm within p.win_rows of the robot's row (clamped to
 // the map's rows -1..H), with the word in front of the first, into the env's
 // LDS buffer `buf`, by the env's own L lanes (one wave, so no workgroup
 // barrier: the wave's LDS writes are done before its later LDS reads). The
 // copy starts at the 16-byte boundary at or below that word; packed maps are
-// 16-byte padded, so it never reads past the map.
+// 16-byte padded, so it never reads past the map. buf is 16-byte aligned.
 template <int L>
 __device__ __forceinline__ Slot stage_window(const Params& p, const Lanes<L>& ln,
                                              const MapMeta& mm, uint32_t* buf, float y) {
@@ -921,23 +928,33 @@ __device__ __forceinline__ Slot stage_window(const Params& p, const Lanes<L>& ln
   const int n4 = (int)((we - ws4 + 3u) >> 2);
   const uint4* src = reinterpret_cast<const uint4*>(p.words + ws4);
   uint4* dst = reinterpret_cast<uint4*>(buf);
-  // eight 16-byte loads in flight per lane before their LDS stores
-  int k = ln.q;
-  for (; k + 7 * L < n4; k += 8 * L) {
-    uint4 v[8];
+  if constexpr (L == 64) {
+    // the env is the whole wave: direct global-to-LDS loads of 1 KB pieces
+    // (lane l's 16 bytes land at the piece's LDS base + 16 l), all in flight
+    // before one wait
+    for (int b = 0; b < n4; b += 64)
+      if (b + ln.q < n4)
+        lds_dma16(src + b + ln.q, dst + b);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the pieces are in LDS
+  } else {
+    // eight 16-byte loads in flight per lane before their LDS stores
+    int k = ln.q;
+    for (; k + 7 * L < n4; k += 8 * L) {
+      uint4 v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[k + u * L];
+      for (int u = 0; u < 8; ++u) v[u] = src[k + u * L];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) dst[k + u * L] = v[u];
+      for (int u = 0; u < 8; ++u) dst[k + u * L] = v[u];
+    }
+    for (; k + 3 * L < n4; k += 4 * L) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = src[k + u * L];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) dst[k + u * L] = v[u];
+    }
+    for (; k < n4; k += L) dst[k] = src[k];
   }
-  for (; k + 3 * L < n4; k += 4 * L) {
-    uint4 v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = src[k + u * L];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) dst[k + u * L] = v[u];
-  }
-  for (; k < n4; k += L) dst[k] = src[k];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
