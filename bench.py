@@ -7,7 +7,7 @@ epsilon linearly spaced in [0.01, 0.3] (VEM).
 
 A "step" is one vectorized step of all N envs: actor + simulator step.
   fused : K-step rollouts of the persistent kernel (actor fused, maps in LDS),
-          replayed from a cached HIP graph; the headline value
+          one launch per K steps; the headline value
   plain : per step, uniform random actions + the plain step kernel
   plain+actor : per step, the separate actor kernel + the plain step kernel
   fused+collect : the fused rollouts adding every step's transitions to a
@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000, help="timed vectorized steps per run")
     ap.add_argument("--warmup", type=int, default=256)
-    ap.add_argument("--repeats", type=int, default=5, help="timed runs; the median is reported")
+    ap.add_argument("--repeats", type=int, default=15, help="timed runs; the median is reported")
     ap.add_argument("--workload", default="m")
     ap.add_argument("--rollout", type=int, default=64, help="steps per fused rollout launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -667,8 +667,8 @@ def peaks(skip):
 
 def fused_roofline(env, cfg, maps, K, launches, stream, lds_peak, extra_env_ops=0,
                    kernel="", counter_key=None, lds_b32_peak=None):
-    """Roofline of the fused rollout kernel on its own K-step launches (graph
-    replays, HIP events around each on the launch stream), whatever the
+    """Roofline of the fused rollout kernel on its own K-step launches (HIP
+    events around each on the launch stream), whatever the
     metric's step count. Algorithmic work per launch (N K env-steps):
       LDS  4 B per marched sample of the definition (k = 0 .. first hit, or
            0 .. M without one; counted over one traced launch) + the
@@ -747,7 +747,7 @@ def fused_roofline(env, cfg, maps, K, launches, stream, lds_peak, extra_env_ops=
 def c3_leg(cfg, maps, launches=16, K=64):
     """Batching workload: 16384 envs on uneven square maps (sides 64..512),
     64 rays to range 128, full randomisation; uniform random actions;
-    autotuned variant; K = 64 rollouts replayed from the graph cache."""
+    autotuned variant; K = 64 rollouts."""
     import torch
     from paper_2305_04180_amd import sparrow
     N = cfg["n_envs"]
@@ -775,7 +775,7 @@ def c3_leg(cfg, maps, launches=16, K=64):
             "ms_per_step": round(ms / (K * launches), 5),
             "config": {"workload": "16384 envs, own map each, sides uniform in {64,128,256,366,512}, "
                                    "64 rays/270 deg/range 128, full DR, uniform random actions, "
-                                   "64-step rollouts from the graph cache, autotuned"},
+                                   "64-step rollouts, autotuned"},
             "variants": {"rollout": env.get_variant(1), "step": env.get_variant(0)},
             "autotune_chosen": tune.get("chosen")}
 
@@ -783,7 +783,7 @@ def c3_leg(cfg, maps, launches=16, K=64):
 def c4_leg(cfg, maps, launches=16, K=64):
     """Precision workload's fused rollout at 8192 envs (366^2 maps, 32 rays,
     BF16 36-256-256-7 actor, eps linspace(0.01, 0.3)): env-steps/s of K = 64
-    graph replays. Returns the env for the precision report."""
+    rollouts. Returns the env for the precision report."""
     import torch
     from paper_2305_04180_amd import sparrow
     N = cfg["n_envs"]
@@ -944,11 +944,6 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
-    pk = peaks(args.no_peaks)
-    if pk:
-        log(f"[bench] peaks: {pk}")
-    lds_peak = max(MI355X_LDS_GBS, pk["lds_b128"] if pk else 0.0)
-
     # ---------------- fused rollout ----------------
     # Each run times exactly args.steps vectorized steps: launches of K steps
     # (K = --rollout, or --steps when that is smaller) plus one shorter launch
@@ -998,6 +993,13 @@ def main():
     assert env.status() == 0
     log(f"[bench] fused: {fused_rate / 1e6:.1f} M env-steps/s ({fused_ms / steps_fused * 1e3:.2f} us/step)")
 
+    # the LDS, HBM and MFMA probes run after the headline timing, so that
+    # the MFMA probe's power draw does not precede it
+    pk = peaks(args.no_peaks)
+    if pk:
+        log(f"[bench] peaks: {pk}")
+    lds_peak = max(MI355X_LDS_GBS, pk["lds_b128"] if pk else 0.0)
+
     # ---------------- roofline of the fused kernel ----------------
     # on its own launches of the workload's rollout length, whatever --steps is
     KR = args.rollout
@@ -1009,7 +1011,7 @@ def main():
 
     # ---------------- the same steps in 256-step launches ----------------
     # (the workload's rollouts are 64 steps; longer launches amortise the
-    # per-launch map staging and graph launch over more steps)
+    # per-launch map staging and launch over more steps)
     fused_k256 = None
     K2 = 256
     n2, rem2 = divmod(args.steps, K2)

@@ -238,7 +238,7 @@ int sparrow_qnet_forward(sparrow_env *env, const float *obs, int32_t n, float *q
 int sparrow_act(sparrow_env *env, const float *obs, int32_t *actions);
 
 /* K-step rollout in one persistent kernel (maps stay in LDS for all K steps),
- * launched through a cached HIP graph. Per step: actor (use_qnet = 1: the
+ * launched directly on the stream. Per step: actor (use_qnet = 1: the
  * installed Q-network + VEM on the current observation; 0: uniform random
  * actions), then the step with AutoReset. Outputs, step-major: actions
  * (dev [K][N], nullable), reward (dev [K][N]), done (dev [K][N]), and obs

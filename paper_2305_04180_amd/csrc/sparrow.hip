@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -469,19 +470,11 @@ struct Groups {
   int4* d_slots = nullptr;
 };
 
-struct GraphEntry {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node = nullptr;
-  hipKernelNodeParams kp{};
-};
-
 }  // namespace
 
 struct sparrow_env {
   sparrow_config cfg{};
   hipStream_t stream = nullptr;
-  hipStream_t capture = nullptr;
   int device = 0;
   int lds_max = 65536;
   int n_cu = 256;
@@ -508,7 +501,7 @@ struct sparrow_env {
   int var_epw[2] = {1, 8};
   int var_L[2] = {64, 64};
   std::map<std::tuple<int, int, bool>, Groups> groups;  // (epw, budget words, windowed)
-  std::map<std::tuple<int, int, int, int>, GraphEntry> graphs;
+  std::map<std::tuple<const void*, int, size_t>, int> per_cu;  // (kernel, threads, LDS bytes)
   // task (Sec. 4.3.1); the default is the workloads' task
   sparrow_task task{SPARROW_N_ACTIONS, SPARROW_REWARD_PROGRESS, SPARROW_STATE_TARGET, 10.0f,
                     -10.0f, 1.0f, 0.0f, 0.3f, 0.1f, 0.3f, 0.3f, 0.1f};
@@ -521,6 +514,34 @@ struct sparrow_env {
 };
 
 namespace {
+
+// A kernel's dynamic-LDS limit is a per-device, per-function setting shared by
+// every environment in the process; it is only ever raised, so a launch that
+// fits once keeps fitting, and a launch that is already covered costs no
+// runtime call.
+int allow_lds(const sparrow_env* e, const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> set;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = set[{e->device, fn}];
+  if (bytes <= cur) return SPARROW_OK;
+  HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  cur = bytes;
+  return SPARROW_OK;
+}
+
+// Resident workgroups per CU for a launch shape (cached per environment).
+int blocks_per_cu(sparrow_env* e, const void* fn, int threads, size_t bytes, int* out) {
+  const auto key = std::make_tuple(fn, threads, bytes);
+  auto it = e->per_cu.find(key);
+  if (it == e->per_cu.end()) {
+    int n = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, bytes));
+    it = e->per_cu.emplace(key, n).first;
+  }
+  *out = it->second;
+  return SPARROW_OK;
+}
 
 int obs_dim(const sparrow_env* e) { return e->cfg.n_rays + 4 + e->task.state; }
 
@@ -696,8 +717,8 @@ template <int L, bool TK, int U>
 int launch_step_LTU(sparrow_env* e, const Params& p, const Groups& gr, int mode) {
   const int threads = std::max(64, gr.epw * L);
   const size_t shmem = (size_t)gr.max_words * 4;
-  HIP_TRY(hipFuncSetAttribute((const void*)k_step<L, TK, U>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  int rc = allow_lds(e, (const void*)k_step<L, TK, U>, shmem);
+  if (rc) return rc;
   hipLaunchKernelGGL((k_step<L, TK, U>), dim3(gr.G), dim3(threads), shmem, e->stream, p, mode);
   HIP_TRY(hipGetLastError());
   return SPARROW_OK;
@@ -939,7 +960,6 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
     CREATE_TRY(hipGetLastError());
     CREATE_TRY(hipDeviceSynchronize());
   }
-  CREATE_TRY(hipStreamCreateWithFlags(&e->capture, hipStreamNonBlocking));
 #undef CREATE_TRY
   cleanup(SPARROW_OK);
   *out = e;
@@ -948,17 +968,12 @@ int sparrow_create(const sparrow_config* cfg, const sparrow_maps* maps, void* hi
 
 void sparrow_destroy(sparrow_env* e) {
   if (!e) return;
-  for (auto& kv : e->graphs) {
-    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-  }
   for (auto& kv : e->groups)
     if (kv.second.d_slots) (void)hipFree(kv.second.d_slots);
   void* bufs[] = {e->words, e->meta, e->inv_dn, e->env_map, e->rays, e->cur_obs, e->hit_k,
                   e->err, e->state_block, e->q_block, e->eps};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  if (e->capture) (void)hipStreamDestroy(e->capture);
   delete e;
 }
 
@@ -1153,13 +1168,15 @@ static int launch_qnet(sparrow_env* e, const float* obs, int32_t n, float* q, in
   size_t shmem = 0;
   if (qnet_in_registers(kind)) {
     shmem = qnet_lds_bytes(qp);
-    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    const int rc = allow_lds(e, fn, shmem);
+    if (rc) return rc;
     blocks = std::max(1, std::min((n + kQRows - 1) / kQRows, e->n_cu));
   } else {
     shmem = kind == 3 ? MlpCfg<64, 512>::kLdsBytes : MlpCfg<96, 512>::kLdsBytes;
-    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
     int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kMThreads, shmem));
+    int rc = allow_lds(e, fn, shmem);
+    if (rc == SPARROW_OK) rc = blocks_per_cu(e, fn, kMThreads, shmem, &per_cu);
+    if (rc) return rc;
     if (per_cu < 1) return fail(SPARROW_EUNSUPPORTED, "actor kernel does not fit a CU");
     blocks = std::max(1, std::min((n + kMRows - 1) / kMRows, per_cu * e->n_cu));
   }
@@ -1186,7 +1203,7 @@ int sparrow_act(sparrow_env* e, const float* obs, int32_t* actions) {
 }
 
 static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int32_t* actions,
-                          float* reward, uint8_t* done, float* obs, bool use_graph,
+                          float* reward, uint8_t* done, float* obs,
                           const RingDev* ring = nullptr, int32_t ring_head = 0,
                           bool ring_terminal = true, float* t_obs = nullptr,
                           int16_t* t_hits = nullptr) {
@@ -1200,9 +1217,10 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   const size_t shmem = (size_t)reserve + (size_t)(gr->max_words + 2 * pad) * 4;
   const void* fn = rollout_kernel(L, q ? qnet_kind(e->qp) : 0, ring != nullptr,
                                   task_is_default(e->task));
-  HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   int per_cu = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem));
+  rc = allow_lds(e, fn, shmem);
+  if (rc == SPARROW_OK) rc = blocks_per_cu(e, fn, threads, shmem, &per_cu);
+  if (rc) return rc;
   if (per_cu < 1) return fail(SPARROW_EUNSUPPORTED, "rollout variant does not fit a CU");
   const int grid = std::min(gr->G, per_cu * e->n_cu);
 
@@ -1230,38 +1248,7 @@ static int launch_rollout(sparrow_env* e, int32_t K, bool q, int epw, int L, int
   QParams qp = e->qp;
   qp.lds_base_words = gr->max_words + 2 * pad;
   void* args[] = {&p, &qp};
-  if (!use_graph) {
-    HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(threads), args, shmem, e->stream));
-    e->g += (uint32_t)K;
-    return SPARROW_OK;
-  }
-  // the kernel's arguments are set on every launch; the key names the kernel
-  // and its launch shape
-  const int kind = q ? qnet_kind(e->qp) : 0;
-  auto key = std::make_tuple((int)K, kind | (ring ? 8 : 0) | (task_is_default(e->task) ? 0 : 16),
-                             L, epw);
-  auto it = e->graphs.find(key);
-  if (it == e->graphs.end()) {
-    GraphEntry ge;
-    HIP_TRY(hipStreamBeginCapture(e->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hipLaunchKernel(fn, dim3(grid), dim3(threads), args, shmem, e->capture);
-    hipError_t ce = hipStreamEndCapture(e->capture, &ge.graph);
-    if (le != hipSuccess) return fail(SPARROW_EHIP, std::string("rollout launch: ") + hipGetErrorString(le));
-    if (ce != hipSuccess) return fail(SPARROW_EHIP, std::string("capture: ") + hipGetErrorString(ce));
-    size_t n_nodes = 0;
-    HIP_TRY(hipGraphGetNodes(ge.graph, nullptr, &n_nodes));
-    if (n_nodes != 1) return fail(SPARROW_EHIP, "unexpected graph shape");
-    HIP_TRY(hipGraphGetNodes(ge.graph, &ge.node, &n_nodes));
-    HIP_TRY(hipGraphKernelNodeGetParams(ge.node, &ge.kp));
-    HIP_TRY(hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
-    it = e->graphs.emplace(key, ge).first;
-  }
-  GraphEntry& ge = it->second;
-  hipKernelNodeParams kp = ge.kp;
-  kp.kernelParams = args;
-  kp.extra = nullptr;
-  HIP_TRY(hipGraphExecKernelNodeSetParams(ge.exec, ge.node, &kp));
-  HIP_TRY(hipGraphLaunch(ge.exec, e->stream));
+  HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(threads), args, shmem, e->stream));
   e->g += (uint32_t)K;
   return SPARROW_OK;
 }
@@ -1275,7 +1262,7 @@ int sparrow_rollout(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* action
                 "the fused rollout needs a width-256 actor; use sparrow_act with width 512");
   if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
   return launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done,
-                        obs, true);
+                        obs);
 }
 
 int sparrow_rollout_trace(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* actions,
@@ -1288,7 +1275,7 @@ int sparrow_rollout_trace(sparrow_env* e, int32_t K, int32_t use_qnet, int32_t* 
                 "the fused rollout needs a width-256 actor; use sparrow_act with width 512");
   if (!e->was_reset) return fail(SPARROW_EINVAL, "reset before rollout");
   const int rc = launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward,
-                                done, obs, false, nullptr, 0, true, obs_steps, hits_steps);
+                                done, obs, nullptr, 0, true, obs_steps, hits_steps);
   if (rc) return rc;
   // the last step's rows are the launch's final observation and hit indices
   const size_t N = (size_t)e->cfg.n_envs, D = (size_t)obs_dim(e), nr = (size_t)e->cfg.n_rays;
@@ -1321,7 +1308,7 @@ int sparrow_rollout_collect(sparrow_env* e, sparrow_ring* ring, int32_t K, int32
   if ((int64_t)K * e->cfg.n_envs > (int64_t)rd.cap)
     return fail(SPARROW_EINVAL, "K * n_envs transitions exceed the buffer's capacity");
   rc = launch_rollout(e, K, use_qnet != 0, e->var_epw[1], e->var_L[1], actions, reward, done, obs,
-                      true, &rd, (int32_t)head, terminal_obs != 0);
+                      &rd, (int32_t)head, terminal_obs != 0);
   if (rc) return rc;
   ring_advance(ring, (int64_t)K * e->cfg.n_envs);
   return SPARROW_OK;
@@ -1484,7 +1471,7 @@ int sparrow_autotune(sparrow_env* e, int32_t steps, char* report, int32_t report
             return SPARROW_OK;
           }
           return launch_rollout(e, K, e->has_qnet && qnet_in_registers(qnet_kind(e->qp)), epw, L,
-                                r_act, r_rew, r_done, obs, false);
+                                r_act, r_rew, r_done, obs);
         };
         int r = run();  // warm-up (also builds the slot table)
         restore();

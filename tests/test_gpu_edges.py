@@ -111,7 +111,7 @@ def test_unbordered_empty_and_tiny_maps(torch_gpu):
 
 def test_rollout_lengths_and_interleaving(torch_gpu):
     """K = 1 and K = 7 rollouts interleaved with plain steps, each checked
-    against the oracle; the graph cache keys on K and buffers."""
+    against the oracle; launches of different K reuse one slot table."""
     import oracle
     from paper_2305_04180_amd import sparrow
     torch = torch_gpu

@@ -1,6 +1,5 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
-benchmark times (autotuned default variants, K = 64 rollouts from the graph
-cache): every env where the oracle can afford it, sampled envs otherwise."""
+benchmark times (autotuned default variants, K = 64 rollouts): every env where the oracle can afford it, sampled envs otherwise."""
 from __future__ import annotations
 
 import numpy as np
@@ -30,8 +29,7 @@ def banner(msg):
 
 
 def test_m4096_fused_rollout_every_env(torch_gpu, m_maps):
-    """4096 envs, 366^2 maps, BF16 actor: one K = 32 fused rollout from the
-    graph cache next to the oracle running its own FP64 actor on every env."""
+    """4096 envs, 366^2 maps, BF16 actor: one K = 32 fused rollout next to the oracle running its own FP64 actor on every env."""
     import oracle
     from paper_2305_04180_amd import sparrow
     torch = torch_gpu
@@ -101,7 +99,7 @@ def test_m4096_plain_step_every_env(torch_gpu, m_maps):
 
 def test_c3_uneven_sides_rollout_sampled(torch_gpu):
     """C3: 16384 envs with sides {64,128,256,366,512}, 64 rays, range 128,
-    one persistent 64-step rollout (graph) after autotuning; the oracle steps
+    one persistent 64-step rollout after autotuning; the oracle steps
     every 32nd env."""
     import oracle
     from paper_2305_04180_amd import sparrow

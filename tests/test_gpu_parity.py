@@ -153,7 +153,7 @@ def test_rollout_uniform_parity(torch_gpu):
         of, oi = orc.get_state()
         compare_state(gf, gi, of, oi, f"rollout {variant} final")
         assert env.global_step == orc.global_step
-        # a second rollout replays the cached graph with the new step counter
+        # a second rollout continues from the new step counter
         acts2, rew2, done2, obs2 = env.rollout(K, use_qnet=False)
         torch.cuda.synchronize()
         for t in range(K):
