@@ -3,28 +3,27 @@
 // Table 6: gamma, learning rate, target-network period, mini-batch 256).
 //
 // One update on B transitions (s, a, r, s', done), all in FP32 with every sum
-// in a fixed order (the products are small -- a 256-row mini-batch through a
-// 36-256-256-7 network is ~0.1 GFLOP per pass -- and latency-bound, so the
-// vector units serve them and keep them within FP32 rounding of binary64).
-// Every product runs through one tiled kernel, k_learn_mm: a launch takes up
-// to three independent products C = X^T Y (16 x 16 output tiles, K staged
-// through LDS 128 at a time, each output summed in ascending k after its
-// bias), so the forward pass is one launch per layer for the three passes
-// together and the backward pass two launches:
-//   forward       layer l of the online network on s (activations kept for
-//                 back-propagation), of the online and of the target network
-//                 on s': out = relu(b + W x), the last layer without relu
-//   loss + delta  a* = argmax Q_online(s') (lowest index on ties), y = r +
-//                 gamma (1 - done) Q_target(s')[a*], delta = Q(s)[a] - y,
-//                 dloss/dQ[a] = clip(delta, -k, k) / B, loss = mean Huber;
-//                 then the output error G[b][o] = [a_b == o] dloss/dQ_b and
-//                 da2[b][u] = [a2 > 0] dloss/dQ_b W3[a_b][u]
-//   backward      gW3 = G^T a2, gW2 = da2^T a1 and da1 = [a1 > 0] (da2 W2) in
-//                 one launch, then gW1 = da1^T s; each bias gradient is the
-//                 column sum of X, an extra column of ones in Y; relu'(0) = 0
-//   k_learn_adam  Adam on every weight and bias in one launch; every
-//                 target_every-th update the target network becomes a copy
-//                 of the online one
+// in a fixed order, on the FP32 matrix cores (v_mfma_f32_16x16x4_f32), which
+// keep it within FP32 rounding of binary64. A 256-row mini-batch through a
+// 36-256-256-7 network is ~0.2 GFLOP per update, so the update is bound by
+// launches and memory latency, not by arithmetic: it runs as three launches.
+//   k_learn_fwd   per block of 16 rows and per pass -- the online network on
+//                 s (activations kept for back-propagation), the online and
+//                 the target network on s' -- all three layers with the
+//                 block's activations in LDS: out = relu(b + W x), the last
+//                 layer without relu
+//   k_learn_rows  per block of 16 rows: a* = argmax Q_online(s') (lowest
+//                 index on ties), y = r + gamma (1 - done) Q_target(s')[a*],
+//                 delta = Q(s)[a] - y, g = dloss/dQ[a] = clip(delta, -k, k) /
+//                 B, the block's Huber sum; the output error G[b][o] = [a_b ==
+//                 o] g_b, da2[b][u] = [a2 > 0] g_b W3[a_b][u] and da1 = [a1 >
+//                 0] (da2 W2)
+//   k_learn_mm    the weight gradients gW3 = G^T a2, gW2 = da2^T a1, gW1 =
+//                 da1^T s (each bias gradient the column sum of X, an extra
+//                 column of ones in Y; relu'(0) = 0), each entry followed at
+//                 once by its Adam step, and the mean loss; every
+//                 target_every-th update the same launch writes the updated
+//                 weights into the target network as well
 // Weights are row-major [out][in], concatenated [W1 | W2 | W3]; biases
 // [b1 | b2 | b3].
 #include <hip/hip_runtime.h>
@@ -32,7 +31,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
-#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -51,162 +49,454 @@ struct Dims {
   int32_t d0, h1, h2, A;
 };
 
-// One product C[m][n] = epi(bias[n] + sum_k X(k, m) Y(k, n)) for m < M and
-// n < N, X(k, m) = X[k sxk + m sxm], Y(k, n) = Y[k syk + n syn], each output
-// summed in ascending k after its bias (bias nullable: 0). relu: max(., 0)
-// after the sum; mask: C[m][n] kept only where mask[m ldm + n] > 0 (relu'); Cb:
-// Cb[m] = sum_k X(k, m), computed as column N of a Y with a column of ones
-// (a bias gradient). tile0: the first tile (workgroup) of this product in
-// the launch.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRB = 16;     // rows per block (the matrix-core tile side)
+constexpr int kRWaves = 8;  // waves of k_learn_fwd and k_learn_rows
+constexpr int kMaxCG = 4;   // column groups of the row-block kernels
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One Adam step (bias-corrected; c1, c2 = 1 - beta^t) on parameter p with
+// gradient gi and moments m, v.
+__device__ __forceinline__ float adam_step(float& m, float& v, float p, float gi, float lr,
+                                           float beta1, float beta2, float eps, float c1,
+                                           float c2) {
+  m = beta1 * m + (1.0f - beta1) * gi;
+  v = beta2 * v + (1.0f - beta2) * gi * gi;
+  return p - lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// Tiles on the matrix cores (v_mfma_f32_16x16x4_f32): the sum over k of
+// A[r][k] B(k, n0 + j) for the 16 x 16 tile of rows r = 0..15 of a block and
+// columns n0..n0 + 15. A sits in LDS, row r at As + r sa, zero in columns K ..
+// 16 ceil(K / 16) - 1; B(k, n) = Bp[k sk + n sn] in global memory, vb: sk ==
+// 1 and 16-byte aligned rows (then four k in one load). Lane (i, g) = (lane %
+// 16, lane / 16) holds A[i][k] and B(k, n0 + i) for k = 16 c + 4 g + t in
+// instruction t of chunk c (both operands take the same k, so every k is
+// summed once); the chunks are c0, c0 + dc, ... below c1. Element r of the
+// result is row 4 g + r, column n0 + i. A column of B only reaches the same
+// column of the result, so columns past N read column N - 1 and the caller
+// drops them.
+
+// The lane's column of B.
+__device__ __forceinline__ const float* b_col(const float* Bp, int sn, int n0, int N) {
+  return Bp + (size_t)min(n0 + ((int)threadIdx.x & 15), N - 1) * sn;
+}
+
+// B elements of up to PC chunks from cb.
+template <int PC>
+__device__ __forceinline__ void load_b(float (&bv)[PC][4], const float* bp, int sk, bool vb, int K,
+                                       int cb, int c1, int dc) {
+  const int g = ((int)threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int j = 0; j < PC; ++j) {
+    const int c = cb + j * dc, k = 16 * c + 4 * g;
+    if (c < c1) {
+      if (vb && k + 3 < K) {
+        const float4 v = *(const float4*)(bp + k);
+        bv[j][0] = v.x, bv[j][1] = v.y, bv[j][2] = v.z, bv[j][3] = v.w;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[j][t] = k + t < K ? bp[(size_t)(k + t) * sk] : 0.0f;
+      }
+    }
+  }
+}
+
+// The whole tile, PC chunks per register piece; bv holds the first piece
+// already when pre is set.
+template <int PC>
+__device__ __forceinline__ f32x4 tile_mfma(float (&bv)[PC][4], bool pre, const float* As, int sa,
+                                           const float* bp, int sk, bool vb, int K, int c0, int c1,
+                                           int dc) {
+  const int lane = (int)threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+  const float* ap = As + i * sa + 4 * g;
+  f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+  for (int cb = c0; cb < c1; cb += PC * dc) {
+    if (!(pre && cb == c0)) load_b<PC>(bv, bp, sk, vb, K, cb, c1, dc);
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+      const int c = cb + j * dc;
+      if (c < c1) {
+        const float4 av = *(const float4*)(ap + 16 * c);
+        acc0 = mfma4(av.x, bv[j][0], acc0);
+        acc1 = mfma4(av.y, bv[j][1], acc1);
+        acc0 = mfma4(av.z, bv[j][2], acc0);
+        acc1 = mfma4(av.w, bv[j][3], acc1);
+      }
+    }
+  }
+  return acc0 + acc1;
+}
+
+// LDS row stride for K columns: room for the zero columns up to a multiple of
+// 16, plus 4 to spread the rows over the banks.
+__host__ __device__ __forceinline__ int lds_stride(int K) { return ((K + 15) & ~15) + 4; }
+
+// Tiles [tb, te) of nt in column group cg of n_cg.
+__device__ __forceinline__ void group_tiles(int nt, int cg, int n_cg, int& tb, int& te) {
+  tb = cg * nt / n_cg;
+  te = (cg + 1) * nt / n_cg;
+}
+
+struct FwdArgs {
+  Dims dm;
+  int32_t B;
+  int32_t pass0;       // the block's pass is pass0 + blockIdx.y
+  const float* in[3];  // per pass: input rows [B][d0]
+  const float* w[3];   // per pass: weights [W1 | W2 | W3]
+  const float* b[3];   // per pass: biases [b1 | b2 | b3]
+  int32_t vw;          // the three weight blocks take 16-byte loads
+  float* a1;           // pass 0: [B][h1] activations (for back-propagation)
+  float* a2;           // pass 0: [B][h2]
+  float* q;            // one column group: Q [3][B][A]; several: partial sums
+                       // [group][3][B][A] over each group's units of layer 2
+};
+
+// One block of 16 rows through the three layers of one pass, for one group
+// of the second layer's units (blockIdx.z of gridDim.z): the whole first
+// layer, the group's tiles of the second, and the last layer's sum over the
+// group's units (the column groups' partial sums are added in group order by
+// their reader). Eight waves; each takes every eighth tile of a layer, and
+// the last layer's chunks are spread over the waves and their partial tiles
+// summed in wave order. Every wave issues the weight loads of its first
+// tiles of all three layers before it stages the input, so that the block
+// waits for memory about once.
+__global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
+  extern __shared__ __align__(16) float lds[];
+  const Dims& d = f.dm;
+  const int pass = f.pass0 + (int)blockIdx.y, cg = (int)blockIdx.z, n_cg = (int)gridDim.z;
+  const int r0 = (int)blockIdx.x * kRB, rows = min(kRB, f.B - r0);
+  const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+  const int sx = lds_stride(d.d0), s1 = lds_stride(d.h1), s2 = lds_stride(d.h2);
+  float* xs = lds;
+  float* h1s = xs + kRB * sx;
+  float* h2s = h1s + kRB * s1;
+  float* part = h2s + kRB * s2;  // [waves][16 x 16]
+  const float* W1 = f.w[pass];
+  const float* W2 = W1 + (size_t)d.h1 * d.d0;
+  const float* W3 = W2 + (size_t)d.h2 * d.h1;
+  const float* b1 = f.b[pass];
+  const float* b2 = b1 + d.h1;
+  const float* b3 = b2 + d.h2;
+  const bool vw = f.vw != 0;
+  const int nc0 = (d.d0 + 15) >> 4, nc1 = (d.h1 + 15) >> 4, nc2 = (d.h2 + 15) >> 4;
+  const int nt1 = nc1;
+  int tb, te;
+  group_tiles(nc2, cg, n_cg, tb, te);
+  // the first first-layer tile (d0 <= 128: one piece of 8 chunks), the first
+  // second-layer tile, the first last-layer chunks
+  float p1[8][4], p2[16][4], p3[2][4];
+  if (wave < nt1) load_b<8>(p1, b_col(W1, d.d0, 16 * wave, d.h1), 1, vw, d.d0, 0, nc0, 1);
+  if (tb + wave < te) load_b<16>(p2, b_col(W2, d.h1, 16 * (tb + wave), d.h2), 1, vw, d.h1, 0, nc1, 1);
+  load_b<2>(p3, b_col(W3, d.h2, 0, d.A), 1, vw, d.h2, tb + wave, te, kRWaves);
+  const float* in = f.in[pass] + (size_t)r0 * d.d0;
+  for (int e = tid; e < kRB * sx; e += blockDim.x) {
+    const int r = e / sx, k = e % sx;
+    xs[e] = (r < rows && k < d.d0) ? in[(size_t)r * d.d0 + k] : 0.0f;
+  }
+  __syncthreads();
+  // out[r][n] = relu(b[n] + acc), written to LDS (zero past N) and, when out
+  // is set, to global memory
+  auto store = [&](f32x4 acc, int t, const float* bias, int N, float* Os, int so, float* out) {
+    const int n = 16 * t + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * g + r;
+      const float v = n < N ? fmaxf(bias[n] + acc[r], 0.0f) : 0.0f;
+      Os[row * so + n] = v;
+      if (out && n < N && row < rows) out[(size_t)(r0 + row) * N + n] = v;
+    }
+  };
+  float* a1 = pass == 0 && cg == 0 ? f.a1 : nullptr;
+  for (int t = wave; t < nt1; t += kRWaves) {
+    const float* bp = b_col(W1, d.d0, 16 * t, d.h1);
+    const f32x4 acc = tile_mfma<8>(p1, t == wave, xs, sx, bp, 1, vw, d.d0, 0, nc0, 1);
+    store(acc, t, b1, d.h1, h1s, s1, a1);
+  }
+  __syncthreads();
+  for (int t = tb + wave; t < te; t += kRWaves) {
+    const f32x4 acc = tile_mfma<16>(p2, t == tb + wave, h1s, s1, b_col(W2, d.h1, 16 * t, d.h2), 1,
+                                    vw, d.h1, 0, nc1, 1);
+    store(acc, t, b2, d.h2, h2s, s2, pass == 0 ? f.a2 : nullptr);
+  }
+  __syncthreads();
+  {
+    const f32x4 acc = tile_mfma<2>(p3, true, h2s, s2, b_col(W3, d.h2, 0, d.A), 1, vw, d.h2,
+                                   tb + wave, te, kRWaves);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wave * 256 + (4 * g + r) * 16 + i] = acc[r];
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int row = tid >> 4, o = tid & 15;
+    float sum = 0.0f;
+    for (int w = 0; w < kRWaves; ++w) sum += part[w * 256 + tid];
+    if (row < rows && o < d.A) {
+      if (n_cg == 1)
+        f.q[((size_t)pass * f.B + r0 + row) * d.A + o] = b3[o] + sum;
+      else
+        f.q[(((size_t)cg * 3 + pass) * f.B + r0 + row) * d.A + o] = sum;
+    }
+  }
+}
+
+struct RowsArgs {
+  Dims dm;
+  int32_t B;
+  int32_t n_q;  // column groups of the forward's partial sums
+  float gamma, k_h;
+  const int32_t* a;
+  const float* r;
+  const uint8_t* done;
+  const float* q;    // partial sums [n_q][3][B][A]
+  const float* b3;   // online last-layer bias [A]
+  const float* bt3;  // target last-layer bias [A]
+  const float* W2;   // online [h2][h1]
+  const float* W3;   // online [A][h2]
+  const float* a1;   // [B][h1]
+  const float* a2;   // [B][h2]
+  float* G;          // [B][A]
+  float* da2;        // [B][h2]
+  float* da1;        // [B][h1]
+  float* loss_part;  // [blocks]: the block's Huber sum
+};
+
+// Targets, Huber gradients and back-propagated errors of one block of 16 rows
+// (see the file head), for one group of da1's columns (blockIdx.y of
+// gridDim.y); group 0 also writes G, da2 and the block's Huber sum. Every
+// global read that the block needs is issued first: Q (the forward's partial
+// sums), the transitions' a, r and done, a2 and W3 into LDS, and each wave's
+// W2 columns and relu' mask for its da1 tile.
+__global__ void __launch_bounds__(kRWaves * 64) k_learn_rows(RowsArgs f) {
+  extern __shared__ __align__(16) float lds[];
+  __shared__ float gs[kRB], hub[kRB], qs[kRB][3][16], rs[kRB];
+  __shared__ int32_t as[kRB], ds[kRB];
+  const Dims& d = f.dm;
+  const int cg = (int)blockIdx.y, n_cg = (int)gridDim.y;
+  const int r0 = (int)blockIdx.x * kRB, rows = min(kRB, f.B - r0);
+  const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+  const int s2 = lds_stride(d.h2);
+  float* d2s = lds;             // [16][s2]: a2, then da2
+  float* w3s = d2s + kRB * s2;  // [A][h2]
+  const int nt1 = (d.h1 + 15) >> 4, nc2 = (d.h2 + 15) >> 4;
+  int tb, te;
+  group_tiles(nt1, cg, n_cg, tb, te);
+  const int t0 = tb + wave;
+  float pre[16][4];
+  float mask[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (t0 < te) {
+    load_b<16>(pre, b_col(f.W2, 1, 16 * t0, d.h1), d.h1, false, d.h2, 0, nc2, 1);
+    const int n = 16 * t0 + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (n < d.h1 && 4 * g + r < rows) mask[r] = f.a1[(size_t)(r0 + 4 * g + r) * d.h1 + n];
+  }
+  // Q of the three passes: bias + the column groups' sums in group order
+  for (int e = tid; e < kRB * 3 * d.A; e += blockDim.x) {
+    const int r = e / (3 * d.A), pass = (e / d.A) % 3, o = e % d.A;
+    if (r < rows) {
+      const int b = r0 + r;
+      float sum = 0.0f;
+      for (int c = 0; c < f.n_q; ++c) sum += f.q[(((size_t)c * 3 + pass) * f.B + b) * d.A + o];
+      qs[r][pass][o] = (pass == 2 ? f.bt3 : f.b3)[o] + sum;
+    }
+  }
+  if (tid < rows) {
+    as[tid] = f.a[r0 + tid];
+    rs[tid] = f.r[r0 + tid];
+    ds[tid] = f.done[r0 + tid];
+  }
+  for (int e = tid; e < kRB * s2; e += blockDim.x) {
+    const int r = e / s2, u = e % s2;
+    d2s[e] = (r < rows && u < d.h2) ? f.a2[(size_t)(r0 + r) * d.h2 + u] : 0.0f;
+  }
+  for (int e = tid; e < d.A * d.h2; e += blockDim.x) w3s[e] = f.W3[e];
+  __syncthreads();
+  if (tid < kRB) {
+    float gv = 0.0f, hv = 0.0f;
+    if (tid < rows) {
+      int best = 0;
+      for (int o = 1; o < d.A; ++o)
+        if (qs[tid][1][o] > qs[tid][1][best]) best = o;
+      const float y = rs[tid] + f.gamma * (ds[tid] ? 0.0f : 1.0f) * qs[tid][2][best];
+      const float delta = qs[tid][0][as[tid]] - y;
+      const float ad = fabsf(delta);
+      hv = ad <= f.k_h ? 0.5f * delta * delta : f.k_h * (ad - 0.5f * f.k_h);
+      gv = fminf(fmaxf(delta, -f.k_h), f.k_h) / (float)f.B;
+    } else {
+      as[tid] = 0;
+    }
+    gs[tid] = gv;
+    hub[tid] = hv;
+  }
+  __syncthreads();
+  if (cg == 0 && tid == 0) {
+    float sum = 0.0f;
+    for (int r = 0; r < kRB; ++r) sum += hub[r];
+    f.loss_part[blockIdx.x] = sum;
+  }
+  if (cg == 0)
+    for (int e = tid; e < rows * d.A; e += blockDim.x) {
+      const int r = e / d.A, o = e % d.A;
+      f.G[(size_t)(r0 + r) * d.A + o] = o == as[r] ? gs[r] : 0.0f;
+    }
+  for (int e = tid; e < kRB * s2; e += blockDim.x) {
+    const int r = e / s2, u = e % s2;
+    float v = 0.0f;
+    if (r < rows && u < d.h2) {
+      v = d2s[e] > 0.0f ? gs[r] * w3s[as[r] * d.h2 + u] : 0.0f;
+      if (cg == 0) f.da2[(size_t)(r0 + r) * d.h2 + u] = v;
+    }
+    d2s[e] = v;
+  }
+  __syncthreads();
+  // da1[r][n] = [a1[r][n] > 0] sum_u da2[r][u] W2[u][n]
+  for (int t = t0; t < te; t += kRWaves) {
+    const f32x4 acc = tile_mfma<16>(pre, t == t0, d2s, s2, b_col(f.W2, 1, 16 * t, d.h1), d.h1,
+                                    false, d.h2, 0, nc2, 1);
+    const int n = 16 * t + i;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * g + r;
+      if (n < d.h1 && row < rows) {
+        const size_t bn = (size_t)(r0 + row) * d.h1 + n;
+        const float m = t == t0 ? mask[r] : f.a1[bn];
+        f.da1[bn] = m > 0.0f ? acc[r] : 0.0f;
+      }
+    }
+  }
+}
+
+// One weight-gradient product C[m][n] = sum_k X(k, m) Y(k, n) for m < M and
+// n < N, X(k, m) = X[k sxk + m], Y(k, n) = Y[k syk + n]; Cb: Cb[m] =
+// sum_k X(k, m), computed as column N of a Y with a column of ones (a bias
+// gradient). Each entry, once summed, takes its Adam step at once: weight
+// pw[m ldc + n] (moments pm, pv), bias qb[m] (moments qm, qv); tw, tb
+// (nullable): the target network's copies, written with the new values.
+// tile0: the first tile of this product in the launch.
 struct MMOp {
   const float* X;
   const float* Y;
   float* C;
-  const float* bias;
-  const float* mask;
   float* Cb;
-  int32_t sxk, sxm, syk, syn, ldc, ldm;
-  int32_t M, N, K, relu;
+  float *pw, *pm, *pv, *tw;
+  float *qb, *qm, *qv, *tb;
+  int32_t sxk, syk, ldc;
+  int32_t M, N, K;
   int32_t tiles_n, tile0;
 };
 struct MMBatch {
   MMOp op[3];
   int32_t n_ops;
+  float lr, beta1, beta2, eps, c1, c2;
+  const float* loss_part;  // the row blocks' Huber sums
+  int32_t n_parts;
+  float inv_b;
+  float* loss;  // nullable: the mean loss
 };
 
-constexpr int kMT = 16, kMK = 128;  // output tile side, K chunk
-constexpr int kMR = kMT * kMK / 256;  // elements of each operand chunk per thread
+constexpr int kMT = 16;     // output tile side
+constexpr int kMC = 8;      // 16-deep K chunks per register block
+constexpr int kMK = 16 * kMC;
 
-__device__ __forceinline__ void mm_load(const MMOp& o, int k0, int m0, int n0, float (&xr)[kMR],
-                                        float (&yr)[kMR]) {
-  const bool ones = o.Cb != nullptr;
+// One register block of operands for K from kb: lane (i, g) takes X(k, m)
+// and Y(k, n) of its row m and column n at k = kb + 16 c + 4 g + t for chunk
+// c and t = 0..3, the A and B elements of instruction t of chunk c (both take
+// the same k, so the sum covers every k once). k >= K reads as 0.
+__device__ __forceinline__ void mm_block(const MMOp& o, const float* xp, const float* yp, bool ones,
+                                         int kb, int g, float (&xa)[kMC][4], float (&yb)[kMC][4]) {
+  const bool full = kb + kMK <= o.K;
 #pragma unroll
-  for (int r = 0; r < kMR; ++r) {
-    const int e = (int)threadIdx.x + r * 256;  // the chunk's kMK x kMT elements
-    // consecutive threads walk the operand's unit-stride index
-    const int xk = o.sxm == 1 ? e / kMT : e % kMK, xm = o.sxm == 1 ? e % kMT : e / kMK;
-    const int yk = o.syn == 1 ? e / kMT : e % kMK, yn = o.syn == 1 ? e % kMT : e / kMK;
-    const int kx = k0 + xk, ky = k0 + yk, m = m0 + xm, n = n0 + yn;
-    xr[r] = (kx < o.K && m < o.M) ? o.X[(size_t)kx * o.sxk + (size_t)m * o.sxm] : 0.0f;
-    yr[r] = (ky < o.K && n < o.N) ? o.Y[(size_t)ky * o.syk + (size_t)n * o.syn]
-            : (ky < o.K && ones && n == o.N) ? 1.0f : 0.0f;
-  }
+  for (int c = 0; c < kMC; ++c)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = kb + 16 * c + 4 * g + t;
+      const bool in = full || k < o.K;
+      xa[c][t] = in ? xp[(size_t)k * o.sxk] : 0.0f;
+      yb[c][t] = in ? (ones ? 1.0f : yp[(size_t)k * o.syk]) : 0.0f;
+    }
 }
 
-// One 16 x 16 output tile per workgroup, one output per thread, summed over
-// ascending k after its bias. K goes through LDS 128 at a time (a 256-long
-// sum is two chunks); the next chunk's global loads are issued before this
-// chunk's multiply-adds.
-__global__ void __launch_bounds__(256) k_learn_mm(MMBatch bt) {
-  __shared__ float xs[kMK][kMT + 1];
-  __shared__ float ys[kMK][kMT + 1];
+// One 16 x 16 output tile per wave on the matrix cores (operand layout as in
+// tile_mfma, both operands from global memory). Rows past M and columns past
+// N read a clamped, valid row or column and are not stored. The Adam state
+// of the lane's entries is loaded first; K goes through registers 128 at a
+// time with the next block's loads issued before this block's instructions;
+// two accumulators take alternate instructions.
+__global__ void __launch_bounds__(64) k_learn_mm(MMBatch bt) {
   int which = 0;
   for (int q = 1; q < bt.n_ops; ++q)
     if ((int)blockIdx.x >= bt.op[q].tile0) which = q;
   const MMOp& o = bt.op[which];
   const int t = (int)blockIdx.x - o.tile0;
   const int m0 = (t / o.tiles_n) * kMT, n0 = (t % o.tiles_n) * kMT;
-  const int tn = (int)threadIdx.x % kMT, tm = (int)threadIdx.x / kMT;
-  const int m = m0 + tm, n = n0 + tn;
-  float acc = (o.bias && n < o.N) ? o.bias[n] : 0.0f;
-  float xr[kMR], yr[kMR];
-  mm_load(o, 0, m0, n0, xr, yr);
-  for (int k0 = 0; k0 < o.K; k0 += kMK) {
-    if (k0 > 0) __syncthreads();  // every thread is done with the previous chunk
+  const int lane = (int)threadIdx.x, i = lane & 15, g = lane >> 4;
+  const int n = n0 + i;
+  const bool ones = o.Cb != nullptr && n == o.N;
+  float sm[4], sv[4], sp[4];
 #pragma unroll
-    for (int r = 0; r < kMR; ++r) {
-      const int e = (int)threadIdx.x + r * 256;
-      const int xk = o.sxm == 1 ? e / kMT : e % kMK, xm = o.sxm == 1 ? e % kMT : e / kMK;
-      const int yk = o.syn == 1 ? e / kMT : e % kMK, yn = o.syn == 1 ? e % kMT : e / kMK;
-      xs[xk][xm] = xr[r];
-      ys[yk][yn] = yr[r];
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + 4 * g + r;
+    sm[r] = sv[r] = sp[r] = 0.0f;
+    if (m < o.M && n < o.N) {
+      const size_t e = (size_t)m * o.ldc + n;
+      sm[r] = o.pm[e], sv[r] = o.pv[e], sp[r] = o.pw[e];
+    } else if (m < o.M && ones) {
+      sm[r] = o.qm[m], sv[r] = o.qv[m], sp[r] = o.qb[m];
     }
-    __syncthreads();
-    if (k0 + kMK < o.K) mm_load(o, k0 + kMK, m0, n0, xr, yr);
-    const int kn = min(kMK, o.K - k0);
-    for (int kk = 0; kk < kn; ++kk) acc += xs[kk][tm] * ys[kk][tn];
   }
-  if (m >= o.M) return;
-  if (n < o.N) {
-    float v = acc;
-    if (o.relu) v = fmaxf(v, 0.0f);
-    if (o.mask && !(o.mask[(size_t)m * o.ldm + n] > 0.0f)) v = 0.0f;
-    o.C[(size_t)m * o.ldc + n] = v;
-  } else if (o.Cb && n == o.N) {
-    o.Cb[m] = acc;
+  const float* xp = o.X + min(m0 + i, o.M - 1);
+  const float* yp = o.Y + min(n, o.N - 1);
+  f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+  float xa[kMC][4], yb[kMC][4];
+  mm_block(o, xp, yp, ones, 0, g, xa, yb);
+  if (blockIdx.x == 0 && lane == 0 && bt.loss) {
+    float sum = 0.0f;
+    for (int q = 0; q < bt.n_parts; ++q) sum += bt.loss_part[q];
+    bt.loss[0] = sum * bt.inv_b;
   }
-}
-
-// Per-row targets and Huber gradients of the whole mini-batch (each
-// workgroup computes them all; workgroup 0 also the mean loss by a
-// fixed-order tree), then this workgroup's rows of the output error G[b][o]
-// = [a_b == o] g_b and of da2[b][u] = [a2[b][u] > 0] g_b W3[a_b][u].
-__global__ void __launch_bounds__(1024)
-k_learn_loss_delta(Dims dm, int32_t B, int32_t rows_per_block, float gamma, float k_h,
-                   const int32_t* __restrict__ a, const float* __restrict__ r,
-                   const uint8_t* __restrict__ done, const float* __restrict__ q,
-                   const float* __restrict__ W3, const float* __restrict__ a2,
-                   float* __restrict__ G, float* __restrict__ da2, float* __restrict__ loss) {
-  __shared__ float part[1024];
-  __shared__ float gs[1024];
-  const int tid = threadIdx.x;
-  const int b0 = blockIdx.x * rows_per_block, b1 = min(B, b0 + rows_per_block);
-  float acc = 0.0f;
-  for (int b = tid; b < B; b += blockDim.x) {
-    const float* qon_s = q + (size_t)b * dm.A;
-    const float* qon_n = q + ((size_t)B + b) * dm.A;
-    const float* qtg_n = q + ((size_t)2 * B + b) * dm.A;
-    int best = 0;
-    for (int o = 1; o < dm.A; ++o)
-      if (qon_n[o] > qon_n[best]) best = o;
-    const float y = r[b] + gamma * (done[b] ? 0.0f : 1.0f) * qtg_n[best];
-    const float delta = qon_s[a[b]] - y;
-    const float ad = fabsf(delta);
-    acc += ad <= k_h ? 0.5f * delta * delta : k_h * (ad - 0.5f * k_h);
-    if (b >= b0 && b < b1) gs[b - b0] = fminf(fmaxf(delta, -k_h), k_h) / (float)B;
-  }
-  part[tid] = acc;
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (tid < w) part[tid] += part[tid + w];
-      __syncthreads();
+  for (int kb = 0; kb < o.K; kb += kMK) {
+    float xn[kMC][4], yn[kMC][4];
+    const bool more = kb + kMK < o.K;
+    if (more) mm_block(o, xp, yp, ones, kb + kMK, g, xn, yn);
+#pragma unroll
+    for (int c = 0; c < kMC; ++c) {
+      acc0 = mfma4(xa[c][0], yb[c][0], acc0);
+      acc1 = mfma4(xa[c][1], yb[c][1], acc1);
+      acc0 = mfma4(xa[c][2], yb[c][2], acc0);
+      acc1 = mfma4(xa[c][3], yb[c][3], acc1);
     }
-    if (tid == 0 && loss) loss[0] = part[0] / (float)B;
+    if (more) {
+#pragma unroll
+      for (int c = 0; c < kMC; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xa[c][u] = xn[c][u], yb[c][u] = yn[c][u];
+    }
   }
-  const int nrow = b1 - b0;
-  for (int e = tid; e < nrow * dm.h2; e += blockDim.x) {
-    const int bl = e / dm.h2, u = e % dm.h2, b = b0 + bl;
-    const float a2v = a2[(size_t)b * dm.h2 + u];
-    da2[(size_t)b * dm.h2 + u] = a2v > 0.0f ? gs[bl] * W3[(size_t)a[b] * dm.h2 + u] : 0.0f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + 4 * g + r;
+    if (m >= o.M) continue;
+    const float gi = acc0[r] + acc1[r];
+    if (n < o.N) {
+      const size_t e = (size_t)m * o.ldc + n;
+      o.C[e] = gi;
+      const float p = adam_step(sm[r], sv[r], sp[r], gi, bt.lr, bt.beta1, bt.beta2, bt.eps, bt.c1,
+                                bt.c2);
+      o.pm[e] = sm[r], o.pv[e] = sv[r], o.pw[e] = p;
+      if (o.tw) o.tw[e] = p;
+    } else if (ones) {
+      o.Cb[m] = gi;
+      const float p = adam_step(sm[r], sv[r], sp[r], gi, bt.lr, bt.beta1, bt.beta2, bt.eps, bt.c1,
+                                bt.c2);
+      o.qm[m] = sm[r], o.qv[m] = sv[r], o.qb[m] = p;
+      if (o.tb) o.tb[m] = p;
+    }
   }
-  for (int e = tid; e < nrow * dm.A; e += blockDim.x) {
-    const int bl = e / dm.A, o = e % dm.A, b = b0 + bl;
-    G[(size_t)b * dm.A + o] = o == a[b] ? gs[bl] : 0.0f;
-  }
-}
-
-// Adam on the nw weights (threads [0, nw)) and the nb biases (threads
-// [nw, nw + nb)) in one launch.
-__global__ void k_learn_adam(int64_t nw, int64_t nb, float* __restrict__ w,
-                             float* __restrict__ mw, float* __restrict__ vw,
-                             const float* __restrict__ gw, float* __restrict__ b,
-                             float* __restrict__ mb, float* __restrict__ vb,
-                             const float* __restrict__ gb, float lr, float beta1, float beta2,
-                             float eps, float c1, float c2) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nw + nb) return;
-  const bool is_w = t < nw;
-  const int64_t i = is_w ? t : t - nw;
-  float* p = is_w ? w : b;
-  float* m = is_w ? mw : mb;
-  float* v = is_w ? vw : vb;
-  const float gi = (is_w ? gw : gb)[i];
-  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
-  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 __global__ void k_learn_bf16(int64_t n, const float* __restrict__ w, uint16_t* __restrict__ out) {
@@ -229,10 +519,11 @@ struct sparrow_learner {
   float *w = nullptr, *b = nullptr, *wt = nullptr, *bt = nullptr;
   float *mw = nullptr, *vw = nullptr, *mb = nullptr, *vb = nullptr, *gw = nullptr, *gb = nullptr;
   // per-batch scratch: activations of the online net on s (kept for
-  // back-propagation) and of the two passes on s', Q of the three passes,
-  // output error and back-propagated errors
-  float *a1 = nullptr, *a2 = nullptr, *hs1 = nullptr, *hs2 = nullptr, *q = nullptr;
-  float *da1 = nullptr, *da2 = nullptr, *G = nullptr;
+  // back-propagation), Q of the three passes, output error, back-propagated
+  // errors and the row blocks' Huber sums
+  float *a1 = nullptr, *a2 = nullptr, *q = nullptr;
+  float *da1 = nullptr, *da2 = nullptr, *G = nullptr, *loss_part = nullptr;
+  size_t fwd_lds = 0, rows_lds = 0;  // dynamic LDS bytes of k_learn_fwd, k_learn_rows
 };
 
 namespace {
@@ -244,44 +535,23 @@ int lalloc(sparrow_learner* L, float** p, size_t n) {
   return SPARROW_OK;
 }
 
-// Launch up to three products as one grid (k_learn_mm).
-int launch_mm(sparrow_learner* L, std::initializer_list<MMOp> ops) {
-  MMBatch bt{};
-  int tiles = 0;
-  for (const MMOp& o0 : ops) {
-    MMOp o = o0;
-    const int cols = o.N + (o.Cb ? 1 : 0);
-    o.tiles_n = (cols + kMT - 1) / kMT;
-    o.tile0 = tiles;
-    tiles += o.tiles_n * ((o.M + kMT - 1) / kMT);
-    bt.op[bt.n_ops++] = o;
-  }
-  hipLaunchKernelGGL(k_learn_mm, dim3(tiles), dim3(256), 0, L->stream, bt);
-  HIP_TRY(hipGetLastError());
-  return SPARROW_OK;
-}
-
-// C = epi(bias + X^T Y) with C (ldc), X (sxk, sxm), Y (syk, syn) strides.
-MMOp mm(int M, int N, int K, const float* X, int sxk, int sxm, const float* Y, int syk, int syn,
-        float* C, int ldc, const float* bias = nullptr, bool relu = false,
-        const float* mask = nullptr, int ldm = 0, float* Cb = nullptr) {
+// One weight-gradient product (see MMOp) with its Adam step.
+MMOp grad_op(int M, int N, int K, const float* X, int sxk, const float* Y, int syk, float* C,
+             int ldc, float* Cb, float* pw, float* pm, float* pv, float* tw, float* qb, float* qm,
+             float* qv, float* tb) {
   MMOp o{};
   o.X = X;
   o.Y = Y;
   o.C = C;
-  o.bias = bias;
-  o.mask = mask;
   o.Cb = Cb;
+  o.pw = pw, o.pm = pm, o.pv = pv, o.tw = tw;
+  o.qb = qb, o.qm = qm, o.qv = qv, o.tb = tb;
   o.sxk = sxk;
-  o.sxm = sxm;
   o.syk = syk;
-  o.syn = syn;
   o.ldc = ldc;
-  o.ldm = ldm;
   o.M = M;
   o.N = N;
   o.K = K;
-  o.relu = relu ? 1 : 0;
   return o;
 }
 
@@ -316,12 +586,24 @@ int sparrow_learner_create(const int32_t* dims, const float* w_host, const float
     if (!rc) rc = lalloc(L, p, (size_t)L->nb);
   if (!rc) rc = lalloc(L, &L->a1, B * d.h1);
   if (!rc) rc = lalloc(L, &L->a2, B * d.h2);
-  if (!rc) rc = lalloc(L, &L->hs1, 2 * B * d.h1);
-  if (!rc) rc = lalloc(L, &L->hs2, 2 * B * d.h2);
+  if (!rc) rc = lalloc(L, &L->loss_part, (B + kRB - 1) / kRB);
   if (!rc) rc = lalloc(L, &L->da1, B * d.h1);
   if (!rc) rc = lalloc(L, &L->da2, B * d.h2);
   if (!rc) rc = lalloc(L, &L->G, B * d.A);
-  if (!rc) rc = lalloc(L, &L->q, 3 * B * d.A);
+  if (!rc) rc = lalloc(L, &L->q, (size_t)kMaxCG * 3 * B * d.A);
+  // LDS of the row-block kernels: the block's input, hidden activations and
+  // the last layer's partial tiles; the block's da2
+  L->fwd_lds = sizeof(float) * ((size_t)kRB * (lds_stride(d.d0) + lds_stride(d.h1) +
+                                               lds_stride(d.h2)) + (size_t)kRWaves * 256);
+  L->rows_lds = sizeof(float) * ((size_t)kRB * lds_stride(d.h2) + (size_t)d.A * d.h2);
+  if (!rc && hipFuncSetAttribute((const void*)k_learn_fwd,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)L->fwd_lds) != hipSuccess)
+    rc = fail(SPARROW_EHIP, "k_learn_fwd: LDS size not accepted");
+  if (!rc && hipFuncSetAttribute((const void*)k_learn_rows,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)L->rows_lds) != hipSuccess)
+    rc = fail(SPARROW_EHIP, "k_learn_rows: LDS size not accepted");
   if (rc) {
     sparrow_learner_destroy(L);
     return rc;
@@ -348,28 +630,27 @@ int sparrow_learner_create(const int32_t* dims, const float* w_host, const float
 
 // Q of the online network on s (pass 0, activations kept in a1, a2), of the
 // online network on s' (pass 1) and of the target network on s' (pass 2):
-// one launch per layer for the three passes.
-static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const float* sn) {
+// passes pass0 .. pass0 + n_pass - 1 in one launch.
+static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const float* sn,
+                           int pass0, int n_pass, int n_cg) {
   const Dims& d = L->dm;
-  const size_t o2 = (size_t)d.h1 * d.d0, o3 = o2 + (size_t)d.h2 * d.h1;
-  const float* w[3] = {L->w, L->w, L->wt};
-  const float* b[3] = {L->b, L->b, L->bt};
-  const float* in[3] = {s, sn, sn};
-  float* h1[3] = {L->a1, L->hs1, L->hs1 + (size_t)B * d.h1};
-  float* h2[3] = {L->a2, L->hs2, L->hs2 + (size_t)B * d.h2};
-  int rc = launch_mm(L, {mm(B, d.h1, d.d0, in[0], 1, d.d0, w[0], 1, d.d0, h1[0], d.h1, b[0], true),
-                         mm(B, d.h1, d.d0, in[1], 1, d.d0, w[1], 1, d.d0, h1[1], d.h1, b[1], true),
-                         mm(B, d.h1, d.d0, in[2], 1, d.d0, w[2], 1, d.d0, h1[2], d.h1, b[2], true)});
-  if (rc) return rc;
-  rc = launch_mm(L, {mm(B, d.h2, d.h1, h1[0], 1, d.h1, w[0] + o2, 1, d.h1, h2[0], d.h2, b[0] + d.h1, true),
-                     mm(B, d.h2, d.h1, h1[1], 1, d.h1, w[1] + o2, 1, d.h1, h2[1], d.h2, b[1] + d.h1, true),
-                     mm(B, d.h2, d.h1, h1[2], 1, d.h1, w[2] + o2, 1, d.h1, h2[2], d.h2, b[2] + d.h1, true)});
-  if (rc) return rc;
-  const size_t bq = (size_t)B * d.A, ob = (size_t)d.h1 + d.h2;
-  return launch_mm(L, {mm(B, d.A, d.h2, h2[0], 1, d.h2, w[0] + o3, 1, d.h2, L->q, d.A, b[0] + ob),
-                       mm(B, d.A, d.h2, h2[1], 1, d.h2, w[1] + o3, 1, d.h2, L->q + bq, d.A, b[1] + ob),
-                       mm(B, d.A, d.h2, h2[2], 1, d.h2, w[2] + o3, 1, d.h2, L->q + 2 * bq, d.A,
-                          b[2] + ob)});
+  FwdArgs f{};
+  f.dm = d;
+  f.B = B;
+  f.pass0 = pass0;
+  f.in[0] = s, f.in[1] = sn, f.in[2] = sn;
+  f.w[0] = L->w, f.w[1] = L->w, f.w[2] = L->wt;
+  f.b[0] = L->b, f.b[1] = L->b, f.b[2] = L->bt;
+  // 16-byte loads of weight rows: every row and block start on a multiple of 4
+  const int64_t o2 = (int64_t)d.h1 * d.d0, o3 = o2 + (int64_t)d.h2 * d.h1;
+  f.vw = d.d0 % 4 == 0 && d.h1 % 4 == 0 && d.h2 % 4 == 0 && o2 % 4 == 0 && o3 % 4 == 0;
+  f.a1 = L->a1;
+  f.a2 = L->a2;
+  f.q = L->q;
+  hipLaunchKernelGGL(k_learn_fwd, dim3((B + kRB - 1) / kRB, n_pass, n_cg), dim3(kRWaves * 64),
+                     L->fwd_lds, L->stream, f);
+  HIP_TRY(hipGetLastError());
+  return SPARROW_OK;
 }
 
 int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const int32_t* a,
@@ -378,41 +659,75 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   if (!L || !s || !a || !r || !s_next || !done) return fail(SPARROW_EINVAL, "NULL argument");
   if (B < 1 || B > L->max_batch) return fail(SPARROW_EINVAL, "mini-batch size out of range");
   const Dims& d = L->dm;
-  int rc = learner_forward(L, B, s, s_next);
+  // the products of the second layer and of da1 spread over column groups
+  // (about four tiles per group: more blocks, shorter chains)
+  const int n_cg = std::max(1, std::min(kMaxCG, ((d.h2 + 15) / 16) / 4));
+  const int n_cg1 = std::max(1, std::min(kMaxCG, ((d.h1 + 15) / 16) / 4));
+  int rc = learner_forward(L, B, s, s_next, 0, 3, n_cg);
   if (rc) return rc;
   const int64_t off2 = (int64_t)d.h1 * d.d0, off3 = off2 + (int64_t)d.h2 * d.h1;
-  const float* W2 = L->w + off2;
-  const float* W3 = L->w + off3;
-  const int rows = 16;
-  hipLaunchKernelGGL(k_learn_loss_delta, dim3((B + rows - 1) / rows), dim3(1024), 0, L->stream, d,
-                     B, rows, L->cfg.gamma, L->cfg.huber_k, a, r, done, L->q, W3, L->a2, L->G,
-                     L->da2, loss);
+  const int blocks = (B + kRB - 1) / kRB;
+  RowsArgs ra{};
+  ra.dm = d;
+  ra.B = B;
+  ra.gamma = L->cfg.gamma;
+  ra.k_h = L->cfg.huber_k;
+  ra.a = a;
+  ra.r = r;
+  ra.done = done;
+  ra.n_q = n_cg;
+  ra.q = L->q;
+  ra.b3 = L->b + d.h1 + d.h2;
+  ra.bt3 = L->bt + d.h1 + d.h2;
+  ra.W2 = L->w + off2;
+  ra.W3 = L->w + off3;
+  ra.a1 = L->a1;
+  ra.a2 = L->a2;
+  ra.G = L->G;
+  ra.da2 = L->da2;
+  ra.da1 = L->da1;
+  ra.loss_part = L->loss_part;
+  hipLaunchKernelGGL(k_learn_rows, dim3(blocks, n_cg1), dim3(kRWaves * 64), L->rows_lds, L->stream,
+                     ra);
   HIP_TRY(hipGetLastError());
   // gW3[o][u] = sum_b G[b][o] a2[b][u], gb3[o] = sum_b G[b][o];
   // gW2[u][k] = sum_b da2[b][u] a1[b][k], gb2[u] = sum_b da2[b][u];
-  // da1[b][k] = [a1[b][k] > 0] sum_u da2[b][u] W2[u][k]
-  rc = launch_mm(L, {mm(d.A, d.h2, B, L->G, d.A, 1, L->a2, d.h2, 1, L->gw + off3, d.h2, nullptr,
-                        false, nullptr, 0, L->gb + d.h1 + d.h2),
-                     mm(d.h2, d.h1, B, L->da2, d.h2, 1, L->a1, d.h1, 1, L->gw + off2, d.h1, nullptr,
-                        false, nullptr, 0, L->gb + d.h1),
-                     mm(B, d.h1, d.h2, L->da2, 1, d.h2, W2, d.h1, 1, L->da1, d.h1, nullptr, false,
-                        L->a1, d.h1)});
-  if (rc) return rc;
-  // gW1[k][i] = sum_b da1[b][k] s[b][i], gb1[k] = sum_b da1[b][k]
-  rc = launch_mm(L, {mm(d.h1, d.d0, B, L->da1, d.h1, 1, s, d.d0, 1, L->gw, d.d0, nullptr, false,
-                        nullptr, 0, L->gb)});
-  if (rc) return rc;
+  // gW1[k][i] = sum_b da1[b][k] s[b][i], gb1[k] = sum_b da1[b][k];
+  // each followed by its Adam step, and by the target copy when it is due
   L->steps += 1;
-  const double c1 = 1.0 - std::pow((double)L->cfg.beta1, (double)L->steps);
-  const double c2 = 1.0 - std::pow((double)L->cfg.beta2, (double)L->steps);
-  hipLaunchKernelGGL(k_learn_adam, dim3(blocks_for(L->nw + L->nb, 256)), dim3(256), 0, L->stream,
-                     L->nw, L->nb, L->w, L->mw, L->vw, L->gw, L->b, L->mb, L->vb, L->gb,
-                     L->cfg.lr, L->cfg.beta1, L->cfg.beta2, L->cfg.adam_eps, (float)c1, (float)c2);
-  HIP_TRY(hipGetLastError());
-  if (L->cfg.target_every > 0 && L->steps % L->cfg.target_every == 0) {
-    HIP_TRY(hipMemcpyAsync(L->wt, L->w, sizeof(float) * L->nw, hipMemcpyDeviceToDevice, L->stream));
-    HIP_TRY(hipMemcpyAsync(L->bt, L->b, sizeof(float) * L->nb, hipMemcpyDeviceToDevice, L->stream));
+  const bool copy = L->cfg.target_every > 0 && L->steps % L->cfg.target_every == 0;
+  const int64_t ob2 = d.h1, ob3 = (int64_t)d.h1 + d.h2;
+  auto tw = [&](int64_t off) { return copy ? L->wt + off : nullptr; };
+  auto tb = [&](int64_t off) { return copy ? L->bt + off : nullptr; };
+  const MMOp ops[3] = {
+      grad_op(d.A, d.h2, B, L->G, d.A, L->a2, d.h2, L->gw + off3, d.h2, L->gb + ob3, L->w + off3,
+              L->mw + off3, L->vw + off3, tw(off3), L->b + ob3, L->mb + ob3, L->vb + ob3, tb(ob3)),
+      grad_op(d.h2, d.h1, B, L->da2, d.h2, L->a1, d.h1, L->gw + off2, d.h1, L->gb + ob2,
+              L->w + off2, L->mw + off2, L->vw + off2, tw(off2), L->b + ob2, L->mb + ob2,
+              L->vb + ob2, tb(ob2)),
+      grad_op(d.h1, d.d0, B, L->da1, d.h1, s, d.d0, L->gw, d.d0, L->gb, L->w, L->mw, L->vw, tw(0),
+              L->b, L->mb, L->vb, tb(0))};
+  MMBatch bt{};
+  int tiles = 0;
+  for (const MMOp& o0 : ops) {
+    MMOp o = o0;
+    o.tiles_n = (o.N + 1 + kMT - 1) / kMT;  // + the column of ones
+    o.tile0 = tiles;
+    tiles += o.tiles_n * ((o.M + kMT - 1) / kMT);
+    bt.op[bt.n_ops++] = o;
   }
+  bt.lr = L->cfg.lr;
+  bt.beta1 = L->cfg.beta1;
+  bt.beta2 = L->cfg.beta2;
+  bt.eps = L->cfg.adam_eps;
+  bt.c1 = (float)(1.0 - std::pow((double)L->cfg.beta1, (double)L->steps));
+  bt.c2 = (float)(1.0 - std::pow((double)L->cfg.beta2, (double)L->steps));
+  bt.loss_part = L->loss_part;
+  bt.n_parts = blocks;
+  bt.inv_b = 1.0f / (float)B;
+  bt.loss = loss;
+  hipLaunchKernelGGL(k_learn_mm, dim3(tiles), dim3(64), 0, L->stream, bt);
+  HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
 
@@ -420,10 +735,11 @@ int sparrow_learner_q(sparrow_learner* L, int32_t which, int32_t n, const float*
   if (!L || !x || !q || n < 1 || n > L->max_batch || (which != 0 && which != 1))
     return fail(SPARROW_EINVAL, "bad argument");
   // pass 1 computes the online net on its second input, pass 2 the target
-  int rc = learner_forward(L, n, x, x);
+  const int pass = which ? 2 : 1;
+  int rc = learner_forward(L, n, x, x, pass, 1, 1);
   if (rc) return rc;
   const size_t A = (size_t)L->dm.A;
-  HIP_TRY(hipMemcpyAsync(q, L->q + (size_t)(which ? 2 : 1) * n * A, sizeof(float) * n * A,
+  HIP_TRY(hipMemcpyAsync(q, L->q + (size_t)pass * n * A, sizeof(float) * n * A,
                          hipMemcpyDeviceToDevice, L->stream));
   return SPARROW_OK;
 }
