@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--no-peaks", action="store_true", help="skip the LDS / HBM / MFMA probes")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--learner-only", action="store_true",
+                    help="only run the learner leg and print its result (for kernel traces)")
     return ap.parse_args()
 
 
@@ -446,7 +448,7 @@ def learner_leg(updates=200, batch=256):
     resident 256-row mini-batches of the 36-256-256-7 network, HIP events
     around them. Algorithmic FLOP per update: three forward passes (online
     s, online s', target s') and the backward pass of one (about two
-    forwards), FP32 on the vector units, as tiled products."""
+    forwards), FP32 on the matrix cores in three launches."""
     import torch
     from paper_2305_04180_amd import inputs, sparrow
     dims = (36, 256, 256, 7)
@@ -477,9 +479,10 @@ def learner_leg(updates=200, batch=256):
             "roofline": {"bound": "latency", "achieved": round(tf, 3), "peak": 157.3,
                          "unit": "TFLOP/s", "frac": round(tf / 157.3, 5),
                          "flop_per_update": int(flop),
-                         "note": "FP32 vector peak; a 256-row update is seven small dependent "
-                                 "launches (three forward layers, loss and output error, two "
-                                 "backward product launches, Adam)"}}
+                         "note": "FP32 peak (vector and matrix alike); a 256-row update is three "
+                                 "dependent launches (row-block forward, row-block backward, "
+                                 "weight gradients with their Adam step), each bound by memory "
+                                 "round trips rather than arithmetic"}}
 
 
 def asl_tfm(seconds=3.0, n_envs=256, tps=32, batch=256, learn_start=8192):
@@ -905,6 +908,10 @@ def main():
     if args.copy_mb:
         assert torch.cuda.is_available(), "bench.py needs the GPU"
         copy_calibration(args.copy_mb)
+        return
+    if args.learner_only:
+        assert torch.cuda.is_available(), "bench.py needs the GPU"
+        print(json.dumps({"learner": learner_leg()}), flush=True)
         return
     # maps of the other workloads, generated with a process pool before this
     # process touches the GPU (one process under a profiler, whose preloaded
