@@ -152,8 +152,10 @@ struct FwdArgs {
   int32_t vw;          // the three weight blocks take 16-byte loads
   float* a1;           // pass 0: [B][h1] activations (for back-propagation)
   float* a2;           // pass 0: [B][h2]
-  float* q;            // one column group: Q [3][B][A]; several: partial sums
-                       // [group][3][B][A] over each group's units of layer 2
+  float* q;            // partial == 0: Q [3][B][A] (one column group); else the
+                       // partial sums [group][3][B][A] over each group's units of
+                       // layer 2, without the bias
+  int32_t partial;
 };
 
 // One block of 16 rows through the three layers of one pass, for one group
@@ -236,10 +238,10 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
     float sum = 0.0f;
     for (int w = 0; w < kRWaves; ++w) sum += part[w * 256 + tid];
     if (row < rows && o < d.A) {
-      if (n_cg == 1)
-        f.q[((size_t)pass * f.B + r0 + row) * d.A + o] = b3[o] + sum;
-      else
+      if (f.partial)
         f.q[(((size_t)cg * 3 + pass) * f.B + r0 + row) * d.A + o] = sum;
+      else
+        f.q[((size_t)pass * f.B + r0 + row) * d.A + o] = b3[o] + sum;
     }
   }
 }
@@ -630,9 +632,11 @@ int sparrow_learner_create(const int32_t* dims, const float* w_host, const float
 
 // Q of the online network on s (pass 0, activations kept in a1, a2), of the
 // online network on s' (pass 1) and of the target network on s' (pass 2):
-// passes pass0 .. pass0 + n_pass - 1 in one launch.
+// passes pass0 .. pass0 + n_pass - 1 in one launch, over n_cg column groups;
+// partial: the groups' sums without the bias (k_learn_rows adds them), else
+// Q itself (one group).
 static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const float* sn,
-                           int pass0, int n_pass, int n_cg) {
+                           int pass0, int n_pass, int n_cg, bool partial) {
   const Dims& d = L->dm;
   FwdArgs f{};
   f.dm = d;
@@ -647,6 +651,7 @@ static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const 
   f.a1 = L->a1;
   f.a2 = L->a2;
   f.q = L->q;
+  f.partial = partial ? 1 : 0;
   hipLaunchKernelGGL(k_learn_fwd, dim3((B + kRB - 1) / kRB, n_pass, n_cg), dim3(kRWaves * 64),
                      L->fwd_lds, L->stream, f);
   HIP_TRY(hipGetLastError());
@@ -663,7 +668,7 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   // (about four tiles per group: more blocks, shorter chains)
   const int n_cg = std::max(1, std::min(kMaxCG, ((d.h2 + 15) / 16) / 4));
   const int n_cg1 = std::max(1, std::min(kMaxCG, ((d.h1 + 15) / 16) / 4));
-  int rc = learner_forward(L, B, s, s_next, 0, 3, n_cg);
+  int rc = learner_forward(L, B, s, s_next, 0, 3, n_cg, true);
   if (rc) return rc;
   const int64_t off2 = (int64_t)d.h1 * d.d0, off3 = off2 + (int64_t)d.h2 * d.h1;
   const int blocks = (B + kRB - 1) / kRB;
@@ -736,7 +741,7 @@ int sparrow_learner_q(sparrow_learner* L, int32_t which, int32_t n, const float*
     return fail(SPARROW_EINVAL, "bad argument");
   // pass 1 computes the online net on its second input, pass 2 the target
   const int pass = which ? 2 : 1;
-  int rc = learner_forward(L, n, x, x, pass, 1, 1);
+  int rc = learner_forward(L, n, x, x, pass, 1, 1, false);
   if (rc) return rc;
   const size_t A = (size_t)L->dm.A;
   HIP_TRY(hipMemcpyAsync(q, L->q + (size_t)pass * n * A, sizeof(float) * n * A,

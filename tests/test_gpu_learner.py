@@ -97,6 +97,52 @@ def test_learner_updates_match_oracle(torch_gpu):
     assert np.array_equal(to_np(bb), gl.read()[1])
 
 
+@pytest.mark.parametrize("dims,B,max_batch,target_every", [
+    ((20, 72, 40, 5), 37, 48, 1),     # ragged row block, one column group, copy every update
+    ((36, 300, 136, 7), 300, 300, 0),  # K past 256, three first-layer tiles a wave, two groups
+    ((30, 64, 64, 3), 16, 16, 2),      # rows of 30: no 16-byte weight loads
+])
+def test_learner_odd_shapes_match_oracle(torch_gpu, dims, B, max_batch, target_every):
+    """The update's kernels on shapes that leave partial row blocks, partial
+    tiles, K tails, several tiles per wave and unaligned weight rows: loss,
+    gradients, weights and the forward pass against the binary64 oracle
+    after two updates."""
+    import oracle
+    from paper_2305_04180_amd import sparrow
+    torch = torch_gpu
+    banner(f"learner {dims}, B={B} of {max_batch}, target every {target_every}")
+    _, b, w = inputs.qnet_weights(dims)
+    kw = dict(gamma=0.98, lr=1e-4, target_every=target_every)
+    gl = sparrow.Learner(dims, w, b, max_batch=max_batch, **kw)
+    ol = oracle.Learner(dims, w, b, **kw)
+    rng = np.random.default_rng(sum(dims) + B)
+    for step in range(2):
+        s, a, r, sn, d = transitions(rng, B, dims[0], dims[3])
+        g = [torch.as_tensor(x).cuda() for x in (s, a, r, sn, d)]
+        loss_g = float(gl.update(*g).item())
+        loss_o, gw_o, gb_o = ol.update(s, a, r, sn, d)
+        w_g, b_g, wt_g, bt_g, gw_g, gb_g = gl.read()
+        where = f"{dims} B={B} update {step}"
+        assert abs(loss_g - loss_o) <= 1e-5 * max(1.0, abs(loss_o)), (where, loss_g, loss_o)
+        for name, gg, go in zip(("W1", "W2", "W3"), layers(gw_g, dims), layers(gw_o, dims)):
+            scale = np.abs(go).max()
+            err = np.abs(gg.astype(np.float64) - go)
+            assert err.max() <= 1e-4 * scale + 1e-9, (where, name, err.max(), scale)
+        assert np.abs(gb_g - gb_o).max() <= 1e-4 * np.abs(gb_o).max() + 1e-9, where
+        w_o, b_o, wt_o, bt_o = ol.params()
+        assert np.abs(w_g.astype(np.float64) - w_o).max() <= 2 * kw["lr"] * (step + 1) + 1e-6, where
+        assert np.abs(b_g.astype(np.float64) - b_o).max() <= 2 * kw["lr"] * (step + 1) + 1e-6, where
+        if target_every and (step + 1) % target_every == 0:
+            assert np.array_equal(wt_g, w_g) and np.array_equal(bt_g, b_g), where
+        elif step + 1 < (target_every or 3):
+            assert np.array_equal(wt_g, np.asarray(w, np.float32)), where
+    x = transitions(rng, B, dims[0], dims[3])[0]
+    for target in (False, True):
+        qg = to_np(gl.q(torch.as_tensor(x).cuda(), target=target)).astype(np.float64)
+        qo = ol.q(x, target=target)
+        assert np.abs(qg - qo).max() <= 1e-5 * max(1.0, np.abs(qo).max()), (dims, target)
+
+
 def test_learner_feeds_the_actor_and_rejects_bad_batches(torch_gpu):
     """Alg. 2 step 3 / Alg. 1 step 1: the learner's exported weights install
     as the actor; oversize and empty mini-batches are errors."""
