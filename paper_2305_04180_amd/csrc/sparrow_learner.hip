@@ -401,103 +401,86 @@ struct MMBatch {
   float* loss;  // nullable: the mean loss
 };
 
-constexpr int kMT = 16;     // output tile side
-constexpr int kMC = 8;      // 16-deep K chunks per register block
-constexpr int kMK = 16 * kMC;
+constexpr int kMT = 16;  // output tile side
+constexpr int kGW = 4;   // waves per tile, each summing every fourth 16-deep chunk of K
+constexpr int kGP = 4;   // chunks of a wave per register piece
 
-// One register block of operands for K from kb: lane (i, g) takes X(k, m)
-// and Y(k, n) of its row m and column n at k = kb + 16 c + 4 g + t for chunk
-// c and t = 0..3, the A and B elements of instruction t of chunk c (both take
-// the same k, so the sum covers every k once). k >= K reads as 0.
-__device__ __forceinline__ void mm_block(const MMOp& o, const float* xp, const float* yp, bool ones,
-                                         int kb, int g, float (&xa)[kMC][4], float (&yb)[kMC][4]) {
-  const bool full = kb + kMK <= o.K;
-#pragma unroll
-  for (int c = 0; c < kMC; ++c)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int k = kb + 16 * c + 4 * g + t;
-      const bool in = full || k < o.K;
-      xa[c][t] = in ? xp[(size_t)k * o.sxk] : 0.0f;
-      yb[c][t] = in ? (ones ? 1.0f : yp[(size_t)k * o.syk]) : 0.0f;
-    }
-}
-
-// One 16 x 16 output tile per wave on the matrix cores (operand layout as in
-// tile_mfma, both operands from global memory). Rows past M and columns past
-// N read a clamped, valid row or column and are not stored. The Adam state
-// of the lane's entries is loaded first; K goes through registers 128 at a
-// time with the next block's loads issued before this block's instructions;
-// two accumulators take alternate instructions.
-__global__ void __launch_bounds__(64) k_learn_mm(MMBatch bt) {
+// One 16 x 16 output tile per workgroup on the matrix cores (operand layout as
+// in tile_mfma, both operands from global memory): each of the four waves
+// takes every fourth 16-deep chunk of K, all of a piece's loads in flight
+// together, and the four partial tiles are summed in wave order; then each
+// thread takes one entry, with the Adam state it loaded first. Rows past M and
+// columns past N read a clamped, valid row or column and are not stored.
+__global__ void __launch_bounds__(kGW * 64) k_learn_mm(MMBatch bt) {
+  __shared__ float part[kGW][256];
   int which = 0;
   for (int q = 1; q < bt.n_ops; ++q)
     if ((int)blockIdx.x >= bt.op[q].tile0) which = q;
   const MMOp& o = bt.op[which];
   const int t = (int)blockIdx.x - o.tile0;
   const int m0 = (t / o.tiles_n) * kMT, n0 = (t % o.tiles_n) * kMT;
-  const int lane = (int)threadIdx.x, i = lane & 15, g = lane >> 4;
-  const int n = n0 + i;
-  const bool ones = o.Cb != nullptr && n == o.N;
-  float sm[4], sv[4], sp[4];
+  const int tid = (int)threadIdx.x, wave = tid >> 6, lane = tid & 63, i = lane & 15, g = lane >> 4;
+  // the thread's entry: row m0 + tid / 16, column n0 + tid % 16
+  const int em = m0 + (tid >> 4), en = n0 + (tid & 15);
+  const bool eones = o.Cb != nullptr && en == o.N;
+  float sm = 0.0f, sv = 0.0f, sp = 0.0f;
+  if (em < o.M && en < o.N) {
+    const size_t e = (size_t)em * o.ldc + en;
+    sm = o.pm[e], sv = o.pv[e], sp = o.pw[e];
+  } else if (em < o.M && eones) {
+    sm = o.qm[em], sv = o.qv[em], sp = o.qb[em];
+  }
+  const bool ones = o.Cb != nullptr && n0 + i == o.N;
+  const float* xp = o.X + min(m0 + i, o.M - 1);
+  const float* yp = o.Y + min(n0 + i, o.N - 1);
+  const int nc = (o.K + 15) >> 4;
+  f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+  for (int cb = wave; cb < nc; cb += kGW * kGP) {
+    float xa[kGP][4], yb[kGP][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int m = m0 + 4 * g + r;
-    sm[r] = sv[r] = sp[r] = 0.0f;
-    if (m < o.M && n < o.N) {
-      const size_t e = (size_t)m * o.ldc + n;
-      sm[r] = o.pm[e], sv[r] = o.pv[e], sp[r] = o.pw[e];
-    } else if (m < o.M && ones) {
-      sm[r] = o.qm[m], sv[r] = o.qv[m], sp[r] = o.qb[m];
+    for (int j = 0; j < kGP; ++j) {
+      const int c = cb + j * kGW;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 16 * c + 4 * g + u;
+        const bool in = c < nc && k < o.K;
+        xa[j][u] = in ? xp[(size_t)k * o.sxk] : 0.0f;
+        yb[j][u] = in ? (ones ? 1.0f : yp[(size_t)k * o.syk]) : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kGP; ++j) {
+      if (cb + j * kGW < nc) {
+        acc0 = mfma4(xa[j][0], yb[j][0], acc0);
+        acc1 = mfma4(xa[j][1], yb[j][1], acc1);
+        acc0 = mfma4(xa[j][2], yb[j][2], acc0);
+        acc1 = mfma4(xa[j][3], yb[j][3], acc1);
+      }
     }
   }
-  const float* xp = o.X + min(m0 + i, o.M - 1);
-  const float* yp = o.Y + min(n, o.N - 1);
-  f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
-  float xa[kMC][4], yb[kMC][4];
-  mm_block(o, xp, yp, ones, 0, g, xa, yb);
-  if (blockIdx.x == 0 && lane == 0 && bt.loss) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[wave][(4 * g + r) * 16 + i] = acc0[r] + acc1[r];
+  if (blockIdx.x == 0 && tid == 0 && bt.loss) {
     float sum = 0.0f;
     for (int q = 0; q < bt.n_parts; ++q) sum += bt.loss_part[q];
     bt.loss[0] = sum * bt.inv_b;
   }
-  for (int kb = 0; kb < o.K; kb += kMK) {
-    float xn[kMC][4], yn[kMC][4];
-    const bool more = kb + kMK < o.K;
-    if (more) mm_block(o, xp, yp, ones, kb + kMK, g, xn, yn);
+  __syncthreads();
+  if (em >= o.M) return;
+  float gi = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kMC; ++c) {
-      acc0 = mfma4(xa[c][0], yb[c][0], acc0);
-      acc1 = mfma4(xa[c][1], yb[c][1], acc1);
-      acc0 = mfma4(xa[c][2], yb[c][2], acc0);
-      acc1 = mfma4(xa[c][3], yb[c][3], acc1);
-    }
-    if (more) {
-#pragma unroll
-      for (int c = 0; c < kMC; ++c)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xa[c][u] = xn[c][u], yb[c][u] = yn[c][u];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int m = m0 + 4 * g + r;
-    if (m >= o.M) continue;
-    const float gi = acc0[r] + acc1[r];
-    if (n < o.N) {
-      const size_t e = (size_t)m * o.ldc + n;
-      o.C[e] = gi;
-      const float p = adam_step(sm[r], sv[r], sp[r], gi, bt.lr, bt.beta1, bt.beta2, bt.eps, bt.c1,
-                                bt.c2);
-      o.pm[e] = sm[r], o.pv[e] = sv[r], o.pw[e] = p;
-      if (o.tw) o.tw[e] = p;
-    } else if (ones) {
-      o.Cb[m] = gi;
-      const float p = adam_step(sm[r], sv[r], sp[r], gi, bt.lr, bt.beta1, bt.beta2, bt.eps, bt.c1,
-                                bt.c2);
-      o.qm[m] = sm[r], o.qv[m] = sv[r], o.qb[m] = p;
-      if (o.tb) o.tb[m] = p;
-    }
+  for (int w = 0; w < kGW; ++w) gi += part[w][tid];
+  if (en < o.N) {
+    const size_t e = (size_t)em * o.ldc + en;
+    o.C[e] = gi;
+    const float p = adam_step(sm, sv, sp, gi, bt.lr, bt.beta1, bt.beta2, bt.eps, bt.c1, bt.c2);
+    o.pm[e] = sm, o.pv[e] = sv, o.pw[e] = p;
+    if (o.tw) o.tw[e] = p;
+  } else if (eones) {
+    o.Cb[em] = gi;
+    const float p = adam_step(sm, sv, sp, gi, bt.lr, bt.beta1, bt.beta2, bt.eps, bt.c1, bt.c2);
+    o.qm[em] = sm, o.qv[em] = sv, o.qb[em] = p;
+    if (o.tb) o.tb[em] = p;
   }
 }
 
@@ -731,7 +714,7 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   bt.n_parts = blocks;
   bt.inv_b = 1.0f / (float)B;
   bt.loss = loss;
-  hipLaunchKernelGGL(k_learn_mm, dim3(tiles), dim3(64), 0, L->stream, bt);
+  hipLaunchKernelGGL(k_learn_mm, dim3(tiles), dim3(kGW * 64), 0, L->stream, bt);
   HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
