@@ -53,7 +53,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRB = 16;     // rows per block (the matrix-core tile side)
 constexpr int kRWaves = 8;  // waves of k_learn_fwd and k_learn_rows
-constexpr int kMaxCG = 4;   // column groups of the row-block kernels
+constexpr int kMaxCG = 8;   // column groups of the row-block kernels (four tiles each)
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -152,19 +152,18 @@ struct FwdArgs {
   int32_t vw;          // the three weight blocks take 16-byte loads
   float* a1;           // pass 0: [B][h1] activations (for back-propagation)
   float* a2;           // pass 0: [B][h2]
-  float* q;            // partial == 0: Q [3][B][A] (one column group); else the
-                       // partial sums [group][3][B][A] over each group's units of
-                       // layer 2, without the bias
-  int32_t partial;
+  float* q;            // partial sums [group][3][B][A] of the last layer over each
+                       // group's units of layer 2, without the bias
 };
 
 // One block of 16 rows through the three layers of one pass, for one group
 // of the second layer's units (blockIdx.z of gridDim.z): the whole first
 // layer, the group's tiles of the second, and the last layer's sum over the
 // group's units (the column groups' partial sums are added in group order by
-// their reader). Eight waves; each takes every eighth tile of a layer, and
-// the last layer's chunks are spread over the waves and their partial tiles
-// summed in wave order. Every wave issues the weight loads of its first
+// their reader). Eight waves: each takes every eighth tile of the first
+// layer; a pair of waves takes one of the group's (at most four) tiles of the
+// second; the last layer's chunks are spread over the waves and their partial
+// tiles summed in wave order. Every wave issues the weight loads of its first
 // tiles of all three layers before it stages the input, so that the block
 // waits for memory about once.
 __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
@@ -183,7 +182,6 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
   const float* W3 = W2 + (size_t)d.h2 * d.h1;
   const float* b1 = f.b[pass];
   const float* b2 = b1 + d.h1;
-  const float* b3 = b2 + d.h2;
   const bool vw = f.vw != 0;
   const int nc0 = (d.d0 + 15) >> 4, nc1 = (d.h1 + 15) >> 4, nc2 = (d.h2 + 15) >> 4;
   const int nt1 = nc1;
@@ -191,9 +189,13 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
   group_tiles(nc2, cg, n_cg, tb, te);
   // the first first-layer tile (d0 <= 128: one piece of 8 chunks), the first
   // second-layer tile, the first last-layer chunks
-  float p1[8][4], p2[16][4], p3[2][4];
+  // at most four second-layer tiles in the group (the host makes enough
+  // groups): two waves per tile, each summing every other 16-deep chunk, the
+  // partial tiles added in LDS
+  const int kp = wave & 1, t2 = tb + (wave >> 1);
+  float p1[8][4], p2[8][4], p3[2][4];
   if (wave < nt1) load_b<8>(p1, b_col(W1, d.d0, 16 * wave, d.h1), 1, vw, d.d0, 0, nc0, 1);
-  if (tb + wave < te) load_b<16>(p2, b_col(W2, d.h1, 16 * (tb + wave), d.h2), 1, vw, d.h1, 0, nc1, 1);
+  if (t2 < te) load_b<8>(p2, b_col(W2, d.h1, 16 * t2, d.h2), 1, vw, d.h1, kp, nc1, 2);
   load_b<2>(p3, b_col(W3, d.h2, 0, d.A), 1, vw, d.h2, tb + wave, te, kRWaves);
   const float* in = f.in[pass] + (size_t)r0 * d.d0;
   for (int e = tid; e < kRB * sx; e += blockDim.x) {
@@ -220,12 +222,21 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
     store(acc, t, b1, d.h1, h1s, s1, a1);
   }
   __syncthreads();
-  for (int t = tb + wave; t < te; t += kRWaves) {
-    const f32x4 acc = tile_mfma<16>(p2, t == tb + wave, h1s, s1, b_col(W2, d.h1, 16 * t, d.h2), 1,
-                                    vw, d.h1, 0, nc1, 1);
-    store(acc, t, b2, d.h2, h2s, s2, pass == 0 ? f.a2 : nullptr);
+  {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (t2 < te)
+      acc = tile_mfma<8>(p2, true, h1s, s1, b_col(W2, d.h1, 16 * t2, d.h2), 1, vw, d.h1, kp, nc1, 2);
+    if (kp == 1)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[wave * 256 + (4 * g + r) * 16 + i] = acc[r];
+    __syncthreads();
+    if (kp == 0 && t2 < te) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] += part[(wave + 1) * 256 + (4 * g + r) * 16 + i];
+      store(acc, t2, b2, d.h2, h2s, s2, pass == 0 ? f.a2 : nullptr);
+    }
   }
-  __syncthreads();
+  __syncthreads();  // h2s is complete; the partial tiles are written again
   {
     const f32x4 acc = tile_mfma<2>(p3, true, h2s, s2, b_col(W3, d.h2, 0, d.A), 1, vw, d.h2,
                                    tb + wave, te, kRWaves);
@@ -237,12 +248,7 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
     const int row = tid >> 4, o = tid & 15;
     float sum = 0.0f;
     for (int w = 0; w < kRWaves; ++w) sum += part[w * 256 + tid];
-    if (row < rows && o < d.A) {
-      if (f.partial)
-        f.q[(((size_t)cg * 3 + pass) * f.B + r0 + row) * d.A + o] = sum;
-      else
-        f.q[((size_t)pass * f.B + r0 + row) * d.A + o] = b3[o] + sum;
-    }
+    if (row < rows && o < d.A) f.q[(((size_t)cg * 3 + pass) * f.B + r0 + row) * d.A + o] = sum;
   }
 }
 
@@ -275,7 +281,7 @@ struct RowsArgs {
 // W2 columns and relu' mask for its da1 tile.
 __global__ void __launch_bounds__(kRWaves * 64) k_learn_rows(RowsArgs f) {
   extern __shared__ __align__(16) float lds[];
-  __shared__ float gs[kRB], hub[kRB], qs[kRB][3][16], rs[kRB];
+  __shared__ float gs[kRB], hub[kRB], qs[kRB][3][16], rs[kRB], part[kRWaves][256];
   __shared__ int32_t as[kRB], ds[kRB];
   const Dims& d = f.dm;
   const int cg = (int)blockIdx.y, n_cg = (int)gridDim.y;
@@ -287,11 +293,14 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_rows(RowsArgs f) {
   const int nt1 = (d.h1 + 15) >> 4, nc2 = (d.h2 + 15) >> 4;
   int tb, te;
   group_tiles(nt1, cg, n_cg, tb, te);
-  const int t0 = tb + wave;
-  float pre[16][4];
+  // at most four tiles in the group (the host makes enough groups): two waves
+  // per da1 tile, each summing every other 16-deep chunk of h2, their partial
+  // tiles added in LDS
+  const int kp = wave & 1, t0 = tb + (wave >> 1);
+  float pre[8][4];
   float mask[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   if (t0 < te) {
-    load_b<16>(pre, b_col(f.W2, 1, 16 * t0, d.h1), d.h1, false, d.h2, 0, nc2, 1);
+    load_b<8>(pre, b_col(f.W2, 1, 16 * t0, d.h1), d.h1, false, d.h2, kp, nc2, 2);
     const int n = 16 * t0 + i;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -302,8 +311,14 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_rows(RowsArgs f) {
     const int r = e / (3 * d.A), pass = (e / d.A) % 3, o = e % d.A;
     if (r < rows) {
       const int b = r0 + r;
+      // every group's load in flight together, then the sum in group order
+      float v[kMaxCG];
+#pragma unroll
+      for (int c = 0; c < kMaxCG; ++c)
+        v[c] = c < f.n_q ? f.q[(((size_t)c * 3 + pass) * f.B + b) * d.A + o] : 0.0f;
       float sum = 0.0f;
-      for (int c = 0; c < f.n_q; ++c) sum += f.q[(((size_t)c * 3 + pass) * f.B + b) * d.A + o];
+#pragma unroll
+      for (int c = 0; c < kMaxCG; ++c) sum += v[c];
       qs[r][pass][o] = (pass == 2 ? f.bt3 : f.b3)[o] + sum;
     }
   }
@@ -357,17 +372,22 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_rows(RowsArgs f) {
   }
   __syncthreads();
   // da1[r][n] = [a1[r][n] > 0] sum_u da2[r][u] W2[u][n]
-  for (int t = t0; t < te; t += kRWaves) {
-    const f32x4 acc = tile_mfma<16>(pre, t == t0, d2s, s2, b_col(f.W2, 1, 16 * t, d.h1), d.h1,
-                                    false, d.h2, 0, nc2, 1);
-    const int n = 16 * t + i;
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (t0 < te)
+    acc = tile_mfma<8>(pre, true, d2s, s2, b_col(f.W2, 1, 16 * t0, d.h1), d.h1, false, d.h2, kp,
+                       nc2, 2);
+  if (kp == 1)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wave][(4 * g + r) * 16 + i] = acc[r];
+  __syncthreads();
+  if (kp == 0 && t0 < te) {
+    const int n = 16 * t0 + i;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 4 * g + r;
       if (n < d.h1 && row < rows) {
         const size_t bn = (size_t)(r0 + row) * d.h1 + n;
-        const float m = t == t0 ? mask[r] : f.a1[bn];
-        f.da1[bn] = m > 0.0f ? acc[r] : 0.0f;
+        f.da1[bn] = mask[r] > 0.0f ? acc[r] + part[wave + 1][row * 16 + i] : 0.0f;
       }
     }
   }
@@ -461,8 +481,15 @@ __global__ void __launch_bounds__(kGW * 64) k_learn_mm(MMBatch bt) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) part[wave][(4 * g + r) * 16 + i] = acc0[r] + acc1[r];
   if (blockIdx.x == 0 && tid == 0 && bt.loss) {
+    // the row blocks' sums in block order, 16 loads in flight at a time
     float sum = 0.0f;
-    for (int q = 0; q < bt.n_parts; ++q) sum += bt.loss_part[q];
+    for (int q0 = 0; q0 < bt.n_parts; q0 += 16) {
+      float v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = q0 + j < bt.n_parts ? bt.loss_part[q0 + j] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sum += v[j];
+    }
     bt.loss[0] = sum * bt.inv_b;
   }
   __syncthreads();
@@ -482,6 +509,18 @@ __global__ void __launch_bounds__(kGW * 64) k_learn_mm(MMBatch bt) {
     o.qm[em] = sm, o.qv[em] = sv, o.qb[em] = p;
     if (o.tb) o.tb[em] = p;
   }
+}
+
+// Q from the forward's partial sums: q[e] = b3[e % A] + sum over the groups
+// in group order of part[c * stride + e].
+__global__ void k_learn_qsum(int64_t n, int32_t A, int32_t n_groups, int64_t stride,
+                             const float* __restrict__ part, const float* __restrict__ b3,
+                             float* __restrict__ q) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float sum = 0.0f;
+  for (int c = 0; c < n_groups; ++c) sum += part[c * stride + e];
+  q[e] = b3[e % A] + sum;
 }
 
 __global__ void k_learn_bf16(int64_t n, const float* __restrict__ w, uint16_t* __restrict__ out) {
@@ -613,13 +652,15 @@ int sparrow_learner_create(const int32_t* dims, const float* w_host, const float
   return SPARROW_OK;
 }
 
-// Q of the online network on s (pass 0, activations kept in a1, a2), of the
-// online network on s' (pass 1) and of the target network on s' (pass 2):
-// passes pass0 .. pass0 + n_pass - 1 in one launch, over n_cg column groups;
-// partial: the groups' sums without the bias (k_learn_rows adds them), else
-// Q itself (one group).
+// Column groups of the second layer (and of da1): four 16-unit tiles each.
+int col_groups(int units) { return std::max(1, ((units + 15) / 16 + 3) / 4); }
+
+// The last layer's partial sums of the online network on s (pass 0,
+// activations kept in a1, a2), of the online network on s' (pass 1) and of
+// the target network on s' (pass 2): passes pass0 .. pass0 + n_pass - 1 in
+// one launch, over the column groups of the second layer.
 static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const float* sn,
-                           int pass0, int n_pass, int n_cg, bool partial) {
+                           int pass0, int n_pass) {
   const Dims& d = L->dm;
   FwdArgs f{};
   f.dm = d;
@@ -634,9 +675,8 @@ static int learner_forward(sparrow_learner* L, int32_t B, const float* s, const 
   f.a1 = L->a1;
   f.a2 = L->a2;
   f.q = L->q;
-  f.partial = partial ? 1 : 0;
-  hipLaunchKernelGGL(k_learn_fwd, dim3((B + kRB - 1) / kRB, n_pass, n_cg), dim3(kRWaves * 64),
-                     L->fwd_lds, L->stream, f);
+  hipLaunchKernelGGL(k_learn_fwd, dim3((B + kRB - 1) / kRB, n_pass, col_groups(d.h2)),
+                     dim3(kRWaves * 64), L->fwd_lds, L->stream, f);
   HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
@@ -647,11 +687,7 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   if (!L || !s || !a || !r || !s_next || !done) return fail(SPARROW_EINVAL, "NULL argument");
   if (B < 1 || B > L->max_batch) return fail(SPARROW_EINVAL, "mini-batch size out of range");
   const Dims& d = L->dm;
-  // the products of the second layer and of da1 spread over column groups
-  // (about four tiles per group: more blocks, shorter chains)
-  const int n_cg = std::max(1, std::min(kMaxCG, ((d.h2 + 15) / 16) / 4));
-  const int n_cg1 = std::max(1, std::min(kMaxCG, ((d.h1 + 15) / 16) / 4));
-  int rc = learner_forward(L, B, s, s_next, 0, 3, n_cg, true);
+  int rc = learner_forward(L, B, s, s_next, 0, 3);
   if (rc) return rc;
   const int64_t off2 = (int64_t)d.h1 * d.d0, off3 = off2 + (int64_t)d.h2 * d.h1;
   const int blocks = (B + kRB - 1) / kRB;
@@ -663,7 +699,7 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   ra.a = a;
   ra.r = r;
   ra.done = done;
-  ra.n_q = n_cg;
+  ra.n_q = col_groups(d.h2);
   ra.q = L->q;
   ra.b3 = L->b + d.h1 + d.h2;
   ra.bt3 = L->bt + d.h1 + d.h2;
@@ -675,8 +711,8 @@ int sparrow_learner_update(sparrow_learner* L, int32_t B, const float* s, const 
   ra.da2 = L->da2;
   ra.da1 = L->da1;
   ra.loss_part = L->loss_part;
-  hipLaunchKernelGGL(k_learn_rows, dim3(blocks, n_cg1), dim3(kRWaves * 64), L->rows_lds, L->stream,
-                     ra);
+  hipLaunchKernelGGL(k_learn_rows, dim3(blocks, col_groups(d.h1)), dim3(kRWaves * 64), L->rows_lds,
+                     L->stream, ra);
   HIP_TRY(hipGetLastError());
   // gW3[o][u] = sum_b G[b][o] a2[b][u], gb3[o] = sum_b G[b][o];
   // gW2[u][k] = sum_b da2[b][u] a1[b][k], gb2[u] = sum_b da2[b][u];
@@ -724,11 +760,14 @@ int sparrow_learner_q(sparrow_learner* L, int32_t which, int32_t n, const float*
     return fail(SPARROW_EINVAL, "bad argument");
   // pass 1 computes the online net on its second input, pass 2 the target
   const int pass = which ? 2 : 1;
-  int rc = learner_forward(L, n, x, x, pass, 1, 1, false);
+  int rc = learner_forward(L, n, x, x, pass, 1);
   if (rc) return rc;
-  const size_t A = (size_t)L->dm.A;
-  HIP_TRY(hipMemcpyAsync(q, L->q + (size_t)pass * n * A, sizeof(float) * n * A,
-                         hipMemcpyDeviceToDevice, L->stream));
+  const Dims& d = L->dm;
+  const float* b3 = (which ? L->bt : L->b) + d.h1 + d.h2;
+  hipLaunchKernelGGL(k_learn_qsum, dim3(blocks_for((int64_t)n * d.A, 256)), dim3(256), 0,
+                     L->stream, (int64_t)n * d.A, d.A, col_groups(d.h2), (int64_t)3 * n * d.A,
+                     L->q + (size_t)pass * n * d.A, b3, q);
+  HIP_TRY(hipGetLastError());
   return SPARROW_OK;
 }
 
