@@ -187,14 +187,16 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
   const int nt1 = nc1;
   int tb, te;
   group_tiles(nc2, cg, n_cg, tb, te);
-  // the first first-layer tile (d0 <= 128: one piece of 8 chunks), the first
-  // second-layer tile, the first last-layer chunks
+  // the wave's first tiles of the three layers
   // at most four second-layer tiles in the group (the host makes enough
   // groups): two waves per tile, each summing every other 16-deep chunk, the
   // partial tiles added in LDS
   const int kp = wave & 1, t2 = tb + (wave >> 1);
-  float p1[8][4], p2[8][4], p3[2][4];
-  if (wave < nt1) load_b<8>(p1, b_col(W1, d.d0, 16 * wave, d.h1), 1, vw, d.d0, 0, nc0, 1);
+  // (the first two first-layer tiles, 64 inputs at a time)
+  float p1a[4][4], p1b[4][4], p2[8][4], p3[2][4];
+  if (wave < nt1) load_b<4>(p1a, b_col(W1, d.d0, 16 * wave, d.h1), 1, vw, d.d0, 0, nc0, 1);
+  if (wave + kRWaves < nt1)
+    load_b<4>(p1b, b_col(W1, d.d0, 16 * (wave + kRWaves), d.h1), 1, vw, d.d0, 0, nc0, 1);
   if (t2 < te) load_b<8>(p2, b_col(W2, d.h1, 16 * t2, d.h2), 1, vw, d.h1, kp, nc1, 2);
   load_b<2>(p3, b_col(W3, d.h2, 0, d.A), 1, vw, d.h2, tb + wave, te, kRWaves);
   const float* in = f.in[pass] + (size_t)r0 * d.d0;
@@ -218,7 +220,9 @@ __global__ void __launch_bounds__(kRWaves * 64) k_learn_fwd(FwdArgs f) {
   float* a1 = pass == 0 && cg == 0 ? f.a1 : nullptr;
   for (int t = wave; t < nt1; t += kRWaves) {
     const float* bp = b_col(W1, d.d0, 16 * t, d.h1);
-    const f32x4 acc = tile_mfma<8>(p1, t == wave, xs, sx, bp, 1, vw, d.d0, 0, nc0, 1);
+    const f32x4 acc = t == wave ? tile_mfma<4>(p1a, true, xs, sx, bp, 1, vw, d.d0, 0, nc0, 1)
+                                : tile_mfma<4>(p1b, t == wave + kRWaves, xs, sx, bp, 1, vw, d.d0,
+                                               0, nc0, 1);
     store(acc, t, b1, d.h1, h1s, s1, a1);
   }
   __syncthreads();
